@@ -1,0 +1,177 @@
+"""FP64 CPU reference of the pseudo-spectral Navier-Stokes RK4 step.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code with
+the GPU library (``paper_1807_01769_amd``): the C source ``fs_oracle.c`` is
+compiled on its own with gcc and loaded here with ctypes.
+
+Every function is the plain definition of an operation the paper names
+(section "Implementation and architecture": FFT/IFFT, dealiasing, curl,
+divergence operators and RK4 time stepping; section "CFD pseudo-spectral code
+comparisons": the 3D step's tasks FFT, RK4, curl, vector product and
+projection, with part of the linear terms treated exactly).
+
+Pins (tests/test_oracle_*.py, all CPU):
+  fft / rfftn / irfftn   brute-force DFT, round trip, Parseval, single modes,
+                         numpy.fft cross-check
+  tendency3d             exact Galerkin triad sum (dealiasing), closed-form
+                         Taylor-Green vorticity/product, energy and helicity
+                         conservation at nu = 0, solenoidality, ABC flow N = 0
+  tendency2d             Taylor-Green N = 0, triad sum, energy and enstrophy
+                         conservation (enstrophy only when alias free)
+  step2d / step3d        exact decaying Taylor-Green / ABC solutions, a scalar
+                         ODE with closed form (order-4 convergence of the
+                         Lawson scheme), energy budget dE/dt = -2 nu Z
+  forcing_alpha3d        injected power equals the prescribed power
+  diag2d / diag3d        closed-form Taylor-Green energy, enstrophy and shell,
+                         sum of the spectrum equals the energy
+Beyond those pins, long nonlinear runs are "parity unpinned": the reference
+and the GPU path are compared with each other only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(path)
+        vp, i, d = C.c_void_p, C.c_int, C.c_double
+        L.or_fft1d.argtypes = [vp, i, i]
+        L.or_fftn.argtypes = [vp, i, vp, i]
+        L.or_rfftn.argtypes = [i, i, vp, vp]
+        L.or_irfftn.argtypes = [i, i, vp, vp]
+        L.or_tendency3d.argtypes = [i, d, vp, d, d, d, vp]
+        L.or_tendency2d.argtypes = [i, d, vp, vp]
+        L.or_forcing_alpha3d.argtypes = [i, d, vp, d, d, d]
+        L.or_forcing_alpha3d.restype = d
+        L.or_step3d.argtypes = [i, d, d, d, d, d, d, vp, i]
+        L.or_step2d.argtypes = [i, d, d, d, vp, i]
+        L.or_diag3d.argtypes = [i, d, vp, i, vp, vp, vp]
+        L.or_diag2d.argtypes = [i, d, vp, i, vp, vp, vp]
+        L.or_set_threads.argtypes = [i]
+        L.or_get_threads.restype = i
+        L.or_kept.argtypes = [i, i]
+        L.or_kept.restype = i
+        L.or_lawson_scalar.argtypes = [d, d, d, i]
+        L.or_lawson_scalar.restype = d
+        _LIB = L
+    return _LIB
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(n: int) -> None:
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
+
+
+def fft1d(x, sign=-1):
+    """Unnormalised radix-2 DFT (sign -1 forward, +1 inverse)."""
+    a = _c128(x).copy()
+    lib().or_fft1d(_p(a), a.size, int(sign))
+    return a
+
+
+def fftn(x, sign=-1):
+    a = _c128(x).copy()
+    shape = np.array(a.shape, dtype=np.int32)
+    lib().or_fftn(_p(a), a.ndim, shape.ctypes.data_as(C.c_void_p), int(sign))
+    return a
+
+
+def rfftn(phys):
+    """Forward R2C over all axes of a real cube, scaled by 1/N^d."""
+    p = np.ascontiguousarray(phys, dtype=np.float64)
+    n, d = p.shape[0], p.ndim
+    out = np.empty(p.shape[:-1] + (n // 2 + 1,), np.complex128)
+    lib().or_rfftn(d, n, _p(p), _p(out))
+    return out
+
+
+def irfftn(spec):
+    """Unscaled C2R over all axes (half spectrum -> real cube)."""
+    s = _c128(spec)
+    n, d = s.shape[0], s.ndim
+    out = np.empty((n,) * d, np.float64)
+    lib().or_irfftn(d, n, _p(s), _p(out))
+    return out
+
+
+def tendency3d(uh, L=2 * np.pi, alpha=0.0, kf_min=2.0, kf_max=3.0):
+    u = _c128(uh)
+    out = np.empty_like(u)
+    lib().or_tendency3d(u.shape[1], float(L), _p(u), float(alpha), float(kf_min),
+                        float(kf_max), _p(out))
+    return out
+
+
+def tendency2d(wh, L=2 * np.pi):
+    w = _c128(wh)
+    out = np.empty_like(w)
+    lib().or_tendency2d(w.shape[0], float(L), _p(w), _p(out))
+    return out
+
+
+def forcing_alpha3d(uh, power, L=2 * np.pi, kf_min=2.0, kf_max=3.0):
+    u = _c128(uh)
+    return float(lib().or_forcing_alpha3d(u.shape[1], float(L), _p(u), float(power),
+                                          float(kf_min), float(kf_max)))
+
+
+def step3d(uh, nu, dt, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0):
+    u = _c128(uh).copy()
+    lib().or_step3d(u.shape[1], float(L), float(nu), float(dt), float(power),
+                    float(kf_min), float(kf_max), _p(u), int(nsteps))
+    return u
+
+
+def step2d(wh, nu, dt, nsteps, L=2 * np.pi):
+    w = _c128(wh).copy()
+    lib().or_step2d(w.shape[0], float(L), float(nu), float(dt), _p(w), int(nsteps))
+    return w
+
+
+def diag3d(uh, nbins, L=2 * np.pi):
+    u = _c128(uh)
+    spec = np.zeros(nbins, np.float64)
+    e, z = C.c_double(), C.c_double()
+    lib().or_diag3d(u.shape[1], float(L), _p(u), int(nbins), _p(spec), C.byref(e), C.byref(z))
+    return spec, e.value, z.value
+
+
+def diag2d(wh, nbins, L=2 * np.pi):
+    w = _c128(wh)
+    spec = np.zeros(nbins, np.float64)
+    e, z = C.c_double(), C.c_double()
+    lib().or_diag2d(w.shape[0], float(L), _p(w), int(nbins), _p(spec), C.byref(e), C.byref(z))
+    return spec, e.value, z.value
+
+
+def kept(m: int, n: int) -> bool:
+    return bool(lib().or_kept(int(m), int(n)))
+
+
+def lawson_scalar(lam, y0, dt, nsteps):
+    """Lawson RK4 on y' = -lam y + y^2 (the scheme used by step2d/step3d)."""
+    return float(lib().or_lawson_scalar(float(lam), float(y0), float(dt), int(nsteps)))

@@ -1,0 +1,504 @@
+/*
+ * fs_oracle.c -- plain, slow FP64 CPU reference of the pseudo-spectral
+ * Navier-Stokes RK4 step.  TEST INFRASTRUCTURE ONLY: it is loaded by the test
+ * suite, by the smoke check and by the benchmark's CPU-baseline leg, never by
+ * the product path.  It shares no code with the GPU library.
+ *
+ * What the paper fixes (FluidSim, section "Implementation and architecture",
+ * description of sim.oper / sim.time_stepping; section "CFD pseudo-spectral
+ * code comparisons", the 3D task list "FFT, Runge-Kutta 4, curl, vector
+ * product and projection"): a Fourier pseudo-spectral solver in a periodic box
+ * with FFT/IFFT, dealiasing, curl and divergence operators, advanced by RK4 at
+ * constant time step, with part of the linear terms treated exactly.  The
+ * paper prints no formulas; everything below is the textbook definition of
+ * each of those operations, written out plainly:
+ *
+ *   transforms   forward  u_hat(k) = N^-d sum_x u(x) exp(-i k.x)  (R2C keeps
+ *                kx in [0, N/2]); inverse unscaled; iterative radix-2
+ *                Cooley-Tukey with every twiddle taken from libm cos/sin.
+ *   dealiasing   keep a mode iff 3|m_a| < N on every axis (2/3 rule, cube);
+ *                every entry point treats modes outside that set as zero.
+ *   3D tendency  N(u) = P[(u x w)^] with w_hat = i k x u_hat and
+ *                P v = v - k (k.v)/|k|^2, N(0) = 0, plus band forcing.
+ *   2D tendency  u_hat = i ky w_hat/|k|^2, v_hat = -i kx w_hat/|k|^2,
+ *                N(w) = -i kx (u w)^ - i ky (v w)^, N(0) = 0.
+ *   time step    Lawson integrating-factor RK4 with E = exp(-nu |k|^2 dt).
+ *   diagnostics  E = 1/2 sum w |u_hat|^2, Z = 1/2 sum w |w_hat|^2 with
+ *                w = 1 on kx = 0 and 2 elsewhere; shell s = floor(|m| + 1/2).
+ *
+ * Parity status of every function is listed in the header comment of
+ * oracle/__init__.py.
+ */
+#define _GNU_SOURCE
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+/* ------------------------------------------------------------------------ */
+/* threads                                                                  */
+/* ------------------------------------------------------------------------ */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int or_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1D FFT: iterative radix-2 decimation in time, in place, unnormalised.     */
+/* sign = -1 forward, +1 inverse.  n must be a power of two.                 */
+/* ------------------------------------------------------------------------ */
+static void fft_line(cplx *x, int n, int sign, const cplx *tw /* n/2 */) {
+  /* bit-reversal permutation */
+  for (int i = 1, j = 0; i < n; i++) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) {
+      cplx t = x[i];
+      x[i] = x[j];
+      x[j] = t;
+    }
+  }
+  for (int len = 2; len <= n; len <<= 1) {
+    int half = len >> 1, step = n / len;
+    for (int i = 0; i < n; i += len)
+      for (int j = 0; j < half; j++) {
+        cplx w = tw[j * step];
+        if (sign > 0) w = conj(w);
+        cplx a = x[i + j], b = x[i + j + half] * w;
+        x[i + j] = a + b;
+        x[i + j + half] = a - b;
+      }
+  }
+}
+
+/* twiddles exp(-2 pi i j / n), j < n/2, each from libm */
+static cplx *make_twiddles(int n) {
+  cplx *tw = malloc(sizeof(cplx) * (size_t)(n / 2 > 0 ? n / 2 : 1));
+  for (int j = 0; j < n / 2; j++) {
+    double a = -2.0 * M_PI * (double)j / (double)n;
+    tw[j] = cos(a) + I * sin(a);
+  }
+  return tw;
+}
+
+static int is_pow2(int n) { return n >= 1 && (n & (n - 1)) == 0; }
+
+void or_fft1d(cplx *x, int n, int sign) {
+  if (!is_pow2(n)) return;
+  cplx *tw = make_twiddles(n);
+  fft_line(x, n, sign, tw);
+  free(tw);
+}
+
+/* Transform a C-order complex array of shape (n0, n1, ..., n_{d-1}) along
+ * one axis: gather each line, transform, scatter back. */
+static void fft_axis(cplx *a, int ndim, const int *shape, int axis, int sign) {
+  int64_t inner = 1, outer = 1;
+  for (int d = axis + 1; d < ndim; d++) inner *= shape[d];
+  for (int d = 0; d < axis; d++) outer *= shape[d];
+  int n = shape[axis];
+  cplx *tw = make_twiddles(n);
+  int64_t lines = outer * inner;
+#pragma omp parallel
+  {
+    cplx *buf = malloc(sizeof(cplx) * (size_t)n);
+#pragma omp for schedule(static)
+    for (int64_t l = 0; l < lines; l++) {
+      int64_t o = l / inner, in = l % inner;
+      cplx *base = a + o * (int64_t)n * inner + in;
+      for (int i = 0; i < n; i++) buf[i] = base[(int64_t)i * inner];
+      fft_line(buf, n, sign, tw);
+      for (int i = 0; i < n; i++) base[(int64_t)i * inner] = buf[i];
+    }
+    free(buf);
+  }
+  free(tw);
+}
+
+void or_fftn(cplx *a, int ndim, const int *shape, int sign) {
+  for (int ax = 0; ax < ndim; ax++) fft_axis(a, ndim, shape, ax, sign);
+}
+
+static int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+/* R2C: complex FFT of the real field over all axes, scaled by 1/N^d, then
+ * keep kx in [0, N/2].  phys: N^d reals (C order, x last);
+ * spec: N^{d-1} x (N/2+1). */
+void or_rfftn(int ndim, int n, const double *phys, cplx *spec) {
+  int shape[3] = {n, n, n};
+  int64_t tot = ipow(n, ndim), h = n / 2 + 1, rows = tot / n;
+  cplx *a = malloc(sizeof(cplx) * (size_t)tot);
+  for (int64_t i = 0; i < tot; i++) a[i] = phys[i];
+  or_fftn(a, ndim, shape, -1);
+  double s = 1.0 / (double)tot;
+  for (int64_t r = 0; r < rows; r++)
+    for (int64_t kx = 0; kx < h; kx++) spec[r * h + kx] = a[r * n + kx] * s;
+  free(a);
+}
+
+/* C2R: rebuild the full Hermitian spectrum from the half one
+ * (F(-k) = conj F(k) for kx > N/2), inverse complex FFT (unscaled), real
+ * part. */
+void or_irfftn(int ndim, int n, const cplx *spec, double *phys) {
+  int shape[3] = {n, n, n};
+  int64_t tot = ipow(n, ndim), h = n / 2 + 1, rows = tot / n;
+  cplx *a = malloc(sizeof(cplx) * (size_t)tot);
+  for (int64_t r = 0; r < rows; r++) {
+    /* row r indexes (kz, ky) or (ky); its mirror indexes (-kz, -ky) */
+    int64_t mr;
+    if (ndim == 1) {
+      mr = 0;
+    } else if (ndim == 2) {
+      mr = (n - r) % n;
+    } else {
+      int64_t kz = r / n, ky = r % n;
+      mr = ((n - kz) % n) * n + (n - ky) % n;
+    }
+    for (int64_t kx = 0; kx < n; kx++) {
+      if (kx < h)
+        a[r * n + kx] = spec[r * h + kx];
+      else
+        a[r * n + kx] = conj(spec[mr * h + (n - kx)]);
+    }
+  }
+  or_fftn(a, ndim, shape, +1);
+  for (int64_t i = 0; i < tot; i++) phys[i] = creal(a[i]);
+  free(a);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wavenumbers and the dealiasing set                                        */
+/* ------------------------------------------------------------------------ */
+/* integer mode number of FFT index i on a full axis of length n */
+static int mode_full(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+/* 2/3 rule on one axis: keep iff 3|m| < n */
+static int keep1(int m, int n) { return 3 * abs(m) < n; }
+
+int or_kept(int m, int n) { return keep1(m, n); }
+
+/* ------------------------------------------------------------------------ */
+/* 3D tendency: N(u) = P[(u x curl u)^] on the kept set, plus band forcing.  */
+/* uh: [3][n][n][n/2+1]; nh same shape (all modes written).                  */
+/* alpha multiplies u_hat on modes with kf_min <= |k| <= kf_max.              */
+/* ------------------------------------------------------------------------ */
+void or_tendency3d(int n, double L, const cplx *uh, double alpha, double kf_min,
+                   double kf_max, cplx *nh) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h, np = (int64_t)n * n * n;
+  const double kb = 2.0 * M_PI / L;
+  cplx *um = malloc(sizeof(cplx) * 3 * ns); /* masked input */
+  cplx *wh = malloc(sizeof(cplx) * 3 * ns); /* vorticity i k x u */
+  double *ur = malloc(sizeof(double) * 3 * np), *wr = malloc(sizeof(double) * 3 * np);
+  double *pr = malloc(sizeof(double) * 3 * np);
+  cplx *ph = malloc(sizeof(cplx) * 3 * ns);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int mz = mode_full(iz, n), my = mode_full(iy, n), mx = ix;
+    int keep = keep1(mx, n) && keep1(my, n) && keep1(mz, n);
+    double kx = kb * mx, ky = kb * my, kz = kb * mz;
+    cplx u0 = keep ? uh[i] : 0, u1 = keep ? uh[ns + i] : 0, u2 = keep ? uh[2 * ns + i] : 0;
+    um[i] = u0;
+    um[ns + i] = u1;
+    um[2 * ns + i] = u2;
+    wh[i] = I * (ky * u2 - kz * u1);
+    wh[ns + i] = I * (kz * u0 - kx * u2);
+    wh[2 * ns + i] = I * (kx * u1 - ky * u0);
+  }
+  for (int c = 0; c < 3; c++) {
+    or_irfftn(3, n, um + c * ns, ur + c * np);
+    or_irfftn(3, n, wh + c * ns, wr + c * np);
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < np; i++) {
+    double u0 = ur[i], u1 = ur[np + i], u2 = ur[2 * np + i];
+    double w0 = wr[i], w1 = wr[np + i], w2 = wr[2 * np + i];
+    pr[i] = u1 * w2 - u2 * w1;
+    pr[np + i] = u2 * w0 - u0 * w2;
+    pr[2 * np + i] = u0 * w1 - u1 * w0;
+  }
+  for (int c = 0; c < 3; c++) or_rfftn(3, n, pr + c * np, ph + c * ns);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int mz = mode_full(iz, n), my = mode_full(iy, n), mx = ix;
+    int keep = keep1(mx, n) && keep1(my, n) && keep1(mz, n);
+    double kx = kb * mx, ky = kb * my, kz = kb * mz;
+    double k2 = kx * kx + ky * ky + kz * kz;
+    cplx r0 = 0, r1 = 0, r2 = 0;
+    if (keep && k2 > 0) {
+      cplx p0 = ph[i], p1 = ph[ns + i], p2 = ph[2 * ns + i];
+      cplx kp = (kx * p0 + ky * p1 + kz * p2) / k2;
+      r0 = p0 - kx * kp;
+      r1 = p1 - ky * kp;
+      r2 = p2 - kz * kp;
+      double km = sqrt(k2);
+      if (alpha != 0.0 && km >= kf_min && km <= kf_max) {
+        r0 += alpha * um[i];
+        r1 += alpha * um[ns + i];
+        r2 += alpha * um[2 * ns + i];
+      }
+    }
+    nh[i] = r0;
+    nh[ns + i] = r1;
+    nh[2 * ns + i] = r2;
+  }
+  free(um);
+  free(wh);
+  free(ur);
+  free(wr);
+  free(pr);
+  free(ph);
+}
+
+/* Constant-power forcing coefficient: alpha = P / sum_band w |u_hat|^2, so
+ * that the injected power sum w Re(u_hat* . alpha u_hat) equals P; 0 when
+ * the band holds no energy or P == 0. */
+double or_forcing_alpha3d(int n, double L, const cplx *uh, double power, double kf_min,
+                          double kf_max) {
+  if (power == 0.0) return 0.0;
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
+  const double kb = 2.0 * M_PI / L;
+  double s = 0.0;
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int mz = mode_full(iz, n), my = mode_full(iy, n), mx = ix;
+    if (!(keep1(mx, n) && keep1(my, n) && keep1(mz, n))) continue;
+    double km = kb * sqrt((double)mx * mx + (double)my * my + (double)mz * mz);
+    if (km < kf_min || km > kf_max || km == 0.0) continue;
+    double w = mx == 0 ? 1.0 : 2.0;
+    for (int c = 0; c < 3; c++) {
+      cplx u = uh[c * ns + i];
+      s += w * (creal(u) * creal(u) + cimag(u) * cimag(u));
+    }
+  }
+  return s > 0.0 ? power / s : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2D tendency in vorticity form.  wh, nh: [n][n/2+1].                       */
+/* ------------------------------------------------------------------------ */
+void or_tendency2d(int n, double L, const cplx *wh, cplx *nh) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * h, np = (int64_t)n * n;
+  const double kb = 2.0 * M_PI / L;
+  cplx *uh = malloc(sizeof(cplx) * 3 * ns);
+  double *r = malloc(sizeof(double) * 3 * np), *q = malloc(sizeof(double) * 2 * np);
+  cplx *fh = malloc(sizeof(cplx) * 2 * ns);
+  for (int64_t i = 0; i < ns; i++) {
+    int my = mode_full((int)(i / h), n), mx = (int)(i % h);
+    int keep = keep1(mx, n) && keep1(my, n);
+    double kx = kb * mx, ky = kb * my, k2 = kx * kx + ky * ky;
+    cplx w = keep ? wh[i] : 0;
+    uh[i] = k2 > 0 ? I * ky * w / k2 : 0;        /* u =  d psi / dy */
+    uh[ns + i] = k2 > 0 ? -I * kx * w / k2 : 0;  /* v = -d psi / dx */
+    uh[2 * ns + i] = w;
+  }
+  for (int c = 0; c < 3; c++) or_irfftn(2, n, uh + c * ns, r + c * np);
+  for (int64_t i = 0; i < np; i++) {
+    q[i] = r[i] * r[2 * np + i];
+    q[np + i] = r[np + i] * r[2 * np + i];
+  }
+  or_rfftn(2, n, q, fh);
+  or_rfftn(2, n, q + np, fh + ns);
+  for (int64_t i = 0; i < ns; i++) {
+    int my = mode_full((int)(i / h), n), mx = (int)(i % h);
+    int keep = keep1(mx, n) && keep1(my, n);
+    double kx = kb * mx, ky = kb * my;
+    nh[i] = (keep && (mx != 0 || my != 0)) ? -I * kx * fh[i] - I * ky * fh[ns + i] : 0;
+  }
+  free(uh);
+  free(r);
+  free(q);
+  free(fh);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lawson integrating-factor RK4 (exact viscous factor E = exp(-nu k^2 dt)): */
+/*   k1 = N(u)            k2 = N(E_h (u + dt/2 k1))                          */
+/*   k3 = N(E_h u + dt/2 k2)            k4 = N(E u + dt E_h k3)              */
+/*   u' = E u + dt/6 (E k1 + 2 E_h k2 + 2 E_h k3 + k4),   E_h = E^(1/2)       */
+/* Modes outside the kept set are returned as zero.                          */
+/* ------------------------------------------------------------------------ */
+typedef void (*tend_fn)(const cplx *u, cplx *out, void *ctx);
+typedef void (*hook_fn)(const cplx *u, void *ctx);
+
+/* The Lawson combination itself, for nf modes x ncomp components with
+ * per-mode factors E = exp(L dt), Eh = exp(L dt / 2).  `pre` (optional) runs
+ * on u_n before the first stage of every step. */
+static void lawson_rk4(int64_t nf, int ncomp, const double *E, const double *Eh, double dt,
+                       cplx *u, int nsteps, tend_fn f, hook_fn pre, void *ctx) {
+  const int64_t tot = nf * ncomp;
+  cplx *k1 = malloc(sizeof(cplx) * tot), *k2 = malloc(sizeof(cplx) * tot);
+  cplx *k3 = malloc(sizeof(cplx) * tot), *k4 = malloc(sizeof(cplx) * tot);
+  cplx *v = malloc(sizeof(cplx) * tot);
+  for (int s = 0; s < nsteps; s++) {
+    if (pre) pre(u, ctx);
+    f(u, k1, ctx);
+    for (int64_t i = 0; i < tot; i++) v[i] = Eh[i % nf] * (u[i] + 0.5 * dt * k1[i]);
+    f(v, k2, ctx);
+    for (int64_t i = 0; i < tot; i++) v[i] = Eh[i % nf] * u[i] + 0.5 * dt * k2[i];
+    f(v, k3, ctx);
+    for (int64_t i = 0; i < tot; i++) v[i] = E[i % nf] * u[i] + dt * Eh[i % nf] * k3[i];
+    f(v, k4, ctx);
+    for (int64_t i = 0; i < tot; i++) {
+      double e = E[i % nf], eh = Eh[i % nf];
+      u[i] = e * u[i] + dt / 6.0 * (e * k1[i] + 2.0 * eh * k2[i] + 2.0 * eh * k3[i] + k4[i]);
+    }
+  }
+  free(k1);
+  free(k2);
+  free(k3);
+  free(k4);
+  free(v);
+}
+
+/* factor exp(-nu |k|^2 t) of element i of one field; 0 outside kept set */
+static double decay(int ndim, int n, double L, double nu, double t, int64_t i) {
+  const int64_t h = n / 2 + 1;
+  const double kb = 2.0 * M_PI / L;
+  int mx = (int)(i % h), my, mz = 0;
+  if (ndim == 2) {
+    my = mode_full((int)(i / h), n);
+  } else {
+    my = mode_full((int)((i / h) % n), n);
+    mz = mode_full((int)(i / (n * h)), n);
+  }
+  if (!(keep1(mx, n) && keep1(my, n) && keep1(mz, n))) return 0.0;
+  double k2 = kb * kb * ((double)mx * mx + (double)my * my + (double)mz * mz);
+  return exp(-nu * k2 * t);
+}
+
+struct grid_ctx {
+  int n;
+  double L, alpha, power, kf_min, kf_max;
+};
+
+static void tend3(const cplx *u, cplx *out, void *ctx) {
+  struct grid_ctx *c = ctx;
+  or_tendency3d(c->n, c->L, u, c->alpha, c->kf_min, c->kf_max, out);
+}
+
+/* constant-power forcing: alpha from u_n, frozen for the whole step */
+static void alpha3(const cplx *u, void *ctx) {
+  struct grid_ctx *c = ctx;
+  c->alpha = or_forcing_alpha3d(c->n, c->L, u, c->power, c->kf_min, c->kf_max);
+}
+
+static void tend2(const cplx *u, cplx *out, void *ctx) {
+  struct grid_ctx *c = ctx;
+  or_tendency2d(c->n, c->L, u, out);
+}
+
+static void grid_steps(int ndim, int n, double L, double nu, double dt, cplx *u, int nsteps,
+                       struct grid_ctx *c) {
+  const int64_t h = n / 2 + 1, nf = (ndim == 2 ? (int64_t)n * h : (int64_t)n * n * h);
+  double *E = malloc(sizeof(double) * nf), *Eh = malloc(sizeof(double) * nf);
+  for (int64_t i = 0; i < nf; i++) {
+    E[i] = decay(ndim, n, L, nu, dt, i);
+    Eh[i] = decay(ndim, n, L, nu, 0.5 * dt, i);
+  }
+  if (ndim == 3)
+    lawson_rk4(nf, 3, E, Eh, dt, u, nsteps, tend3, alpha3, c);
+  else
+    lawson_rk4(nf, 1, E, Eh, dt, u, nsteps, tend2, NULL, c);
+  free(E);
+  free(Eh);
+}
+
+void or_step3d(int n, double L, double nu, double dt, double power, double kf_min,
+               double kf_max, cplx *uh, int nsteps) {
+  struct grid_ctx c = {n, L, 0.0, power, kf_min, kf_max};
+  grid_steps(3, n, L, nu, dt, uh, nsteps, &c);
+}
+
+void or_step2d(int n, double L, double nu, double dt, cplx *wh, int nsteps) {
+  struct grid_ctx c = {n, L, 0.0, 0.0, 0.0, 0.0};
+  grid_steps(2, n, L, nu, dt, wh, nsteps, &c);
+}
+
+/* The same Lawson combination on the scalar ODE y' = -lam y + y^2 (linear
+ * part exact, quadratic part by RK4); used only to pin the scheme. */
+static void tend_sq(const cplx *u, cplx *out, void *ctx) {
+  (void)ctx;
+  out[0] = u[0] * u[0];
+}
+
+double or_lawson_scalar(double lam, double y0, double dt, int nsteps) {
+  double E = exp(-lam * dt), Eh = exp(-0.5 * lam * dt);
+  cplx y = y0;
+  lawson_rk4(1, 1, &E, &Eh, dt, &y, nsteps, tend_sq, NULL, NULL);
+  return creal(y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics over the kept set: E = 1/2 sum w |u_hat|^2,                   */
+/* Z = 1/2 sum w |w_hat|^2, shell spectrum E(s), s = floor(|m| + 1/2),       */
+/* bins s >= nbins dropped from the spectrum only.                            */
+/* ------------------------------------------------------------------------ */
+void or_diag3d(int n, double L, const cplx *uh, int nbins, double *spec, double *E,
+               double *Z) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
+  const double kb = 2.0 * M_PI / L;
+  double e = 0, z = 0;
+  for (int b = 0; b < nbins; b++) spec[b] = 0.0;
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int mz = mode_full(iz, n), my = mode_full(iy, n), mx = ix;
+    if (!(keep1(mx, n) && keep1(my, n) && keep1(mz, n))) continue;
+    double w = mx == 0 ? 1.0 : 2.0;
+    double kx = kb * mx, ky = kb * my, kz = kb * mz;
+    cplx u0 = uh[i], u1 = uh[ns + i], u2 = uh[2 * ns + i];
+    double eu = 0.5 * w * (creal(u0 * conj(u0)) + creal(u1 * conj(u1)) + creal(u2 * conj(u2)));
+    cplx w0 = I * (ky * u2 - kz * u1), w1 = I * (kz * u0 - kx * u2), w2 = I * (kx * u1 - ky * u0);
+    double ew = 0.5 * w * (creal(w0 * conj(w0)) + creal(w1 * conj(w1)) + creal(w2 * conj(w2)));
+    e += eu;
+    z += ew;
+    int s = (int)floor(sqrt((double)mx * mx + (double)my * my + (double)mz * mz) + 0.5);
+    if (s < nbins) spec[s] += eu;
+  }
+  *E = e;
+  *Z = z;
+}
+
+void or_diag2d(int n, double L, const cplx *wh, int nbins, double *spec, double *E, double *Z) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * h;
+  const double kb = 2.0 * M_PI / L;
+  double e = 0, z = 0;
+  for (int b = 0; b < nbins; b++) spec[b] = 0.0;
+  for (int64_t i = 0; i < ns; i++) {
+    int my = mode_full((int)(i / h), n), mx = (int)(i % h);
+    if (!(keep1(mx, n) && keep1(my, n))) continue;
+    if (mx == 0 && my == 0) continue;
+    double w = mx == 0 ? 1.0 : 2.0;
+    double k2 = kb * kb * ((double)mx * mx + (double)my * my);
+    double a2 = creal(wh[i] * conj(wh[i]));
+    double eu = 0.5 * w * a2 / k2;
+    e += eu;
+    z += 0.5 * w * a2;
+    int s = (int)floor(sqrt((double)mx * mx + (double)my * my) + 0.5);
+    if (s < nbins) spec[s] += eu;
+  }
+  *E = e;
+  *Z = z;
+}
