@@ -1,0 +1,186 @@
+/*
+ * fs.h -- C ABI of the MI355X pseudo-spectral Navier-Stokes library (libfs.so).
+ *
+ * The library advances the incompressible Navier-Stokes equations in a
+ * periodic box [0, L)^d (d = 2 in vorticity form, d = 3 in velocity form)
+ * with a Fourier pseudo-spectral method and the fourth-order Runge-Kutta
+ * scheme at constant time step, the viscous term integrated exactly.  This is
+ * the numerical method of the FluidSim paper (section "Implementation and
+ * architecture": the operators object provides FFT/IFFT, dealiasing, curl and
+ * divergence, the time-stepping object advances the state with RK4; section
+ * "CFD pseudo-spectral code comparisons": one 3D step is made of FFTs, the
+ * RK4 update, curl, vector product and projection, with part of the linear
+ * terms treated exactly).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Wavenumbers k = (2 pi / L) m, m integer.  Forward transforms carry the
+ * factor 1/N^d; inverse transforms are unscaled.  Dealiasing is the 2/3 rule
+ * on a cube: a mode is kept iff 3|m_a| < N on every axis.  Entry points that
+ * take a spectral state treat modes outside the kept set as zero and never
+ * write them (except fs_tendency, which writes zeros there).
+ *
+ * Layouts (C order, interleaved complex, contiguous):
+ *   3D state / tendency : complex[3][N][N][N/2+1]   (component, kz, ky, kx)
+ *   2D state / tendency : complex[N][N/2+1]         (ky, kx), vorticity
+ *   3D physical field   : real[N][N][N]             (z, y, x)
+ *   2D physical field   : real[N][N]                (y, x)
+ * ky and kz are in FFT order (0..N/2-1, -N/2..-1).  "complex" is two floats
+ * (FS_F32) or two doubles (FS_F64).
+ *
+ * Memory and streams: every array argument is device memory owned by the
+ * caller (e.g. a torch tensor), 16-byte aligned.  The plan owns its
+ * workspace and tables, allocated once by fs_plan_create; no other call
+ * allocates device memory.  Every call enqueues work on the plan's stream and
+ * returns without synchronising; results are visible to later work on that
+ * stream.  Plans are not thread safe; distinct plans are independent.
+ *
+ * Errors: arguments are validated on the host before anything is enqueued;
+ * on error nothing is enqueued, outputs are untouched and the status is
+ * negative.  fs_last_error() returns a description of the last failure of
+ * the calling thread.  A HIP runtime failure marks the plan failed
+ * (FS_E_DEVICE for every later call); destroy it.
+ */
+#ifndef FS_H_
+#define FS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FS_OK = 0,
+  FS_E_INVALID = -1,     /* bad argument (null pointer, n, L, nu, dt, ...) */
+  FS_E_UNSUPPORTED = -2, /* valid but not implemented (e.g. n not 2^k in 16..1024) */
+  FS_E_NOMEM = -3,       /* device allocation failed at plan creation */
+  FS_E_DEVICE = -4,      /* HIP runtime error; the plan is unusable */
+  FS_E_NONFINITE = -5    /* reserved: non-finite values detected */
+} fs_status;
+
+enum { FS_F32 = 0, FS_F64 = 1 };
+
+/* flags */
+#define FS_NO_GRAPH 0x1u /* launch kernels one by one instead of a captured graph */
+#define FS_PROFILE 0x2u  /* time every kernel with events (see fs_profile_read) */
+
+typedef struct fs_plan fs_plan;
+
+typedef struct {
+  int ndim;             /* 2 or 3 (default 3) */
+  int precision;        /* FS_F32 (default) or FS_F64 */
+  void *stream;         /* hipStream_t the plan enqueues on; NULL = null stream */
+  double forcing_power; /* 3D only: constant injected power P; 0 = no forcing */
+  double forcing_kmin;  /* forcing band kmin <= |k| <= kmax (default 2, 3) */
+  double forcing_kmax;
+  unsigned flags;       /* FS_NO_GRAPH | FS_PROFILE */
+} fs_plan_opts;
+
+/* Fill *opts with the defaults listed above. */
+void fs_plan_opts_default(fs_plan_opts *opts);
+
+/*
+ * Create a plan for grid size n (power of two, 16..1024), box length L > 0,
+ * kinematic viscosity nu >= 0 and time step dt > 0 (the four physical
+ * parameters of one constant-step RK4 run).  Builds the twiddle and
+ * integrating-factor tables in FP64 on the host (rounded once to the plan's
+ * precision) and allocates the workspace.  opts may be NULL (defaults).
+ * The forcing band must lie inside the kept cube.
+ * Errors: FS_E_INVALID, FS_E_UNSUPPORTED, FS_E_NOMEM, FS_E_DEVICE.
+ */
+fs_status fs_plan_create(fs_plan **out, int n, double L, double nu, double dt,
+                         const fs_plan_opts *opts);
+
+/* Release a plan and its workspace (waits for its stream).  NULL is a no-op. */
+fs_status fs_plan_destroy(fs_plan *plan);
+
+/* Replace the stream the plan enqueues on (NULL = null stream). */
+fs_status fs_plan_set_stream(fs_plan *plan, void *stream);
+
+/* Number of complex elements of a state: 3*N*N*(N/2+1) (3D) or N*(N/2+1) (2D). */
+fs_status fs_state_elems(const fs_plan *plan, size_t *n_complex);
+
+/* Device bytes owned by the plan (workspace and tables). */
+fs_status fs_workspace_bytes(const fs_plan *plan, size_t *bytes);
+
+/* Number of spectrum bins that covers every kept mode:
+ * floor(sqrt(d) * K + 1/2) + 1 with K = floor((N-1)/3). */
+fs_status fs_spectrum_bins(const fs_plan *plan, int *nbins);
+
+/*
+ * Forward real-to-complex transform of one scalar field (the paper's
+ * fft_as_arg, section "Performance", profiling): spec = N^-d sum_x phys(x)
+ * exp(-i k.x) for kx in [0, N/2].  Undealiased; out of place; phys is not
+ * modified.  phys: real[N]^d; spec: complex[N]^(d-1)[N/2+1].
+ */
+fs_status fs_fft_forward(fs_plan *plan, const void *phys, void *spec);
+
+/*
+ * Inverse complex-to-real transform (ifft_as_arg): phys(x) = Re sum_k
+ * spec_full(k) exp(i k.x), spec_full the Hermitian completion of spec (the
+ * imaginary parts of self-conjugate modes do not contribute).  Unscaled;
+ * spec is not modified.
+ */
+fs_status fs_fft_inverse(fs_plan *plan, const void *spec, void *phys);
+
+/*
+ * Nonlinear tendency of a spectral state, dealiased (3D: the curl, vector
+ * product and projection tasks; 2D: velocity from vorticity and the
+ * divergence of the vorticity flux), without the viscous term:
+ *   3D: tend = P[(u x w)^] + alpha u_hat on the forcing band, w = curl u,
+ *       P v = v - k (k.v)/|k|^2, tend(0) = 0, alpha = power / sum_band
+ *       w |u_hat|^2 computed from `state` (0 when forcing is off);
+ *   2D: tend = -i kx (u w)^ - i ky (v w)^, u_hat = i ky w_hat/|k|^2,
+ *       v_hat = -i kx w_hat/|k|^2, tend(0) = 0.
+ * Every element of tend is written (zero outside the kept set).  state and
+ * tend must not overlap.
+ */
+fs_status fs_tendency(fs_plan *plan, const void *state, void *tend);
+
+/*
+ * Advance state in place by nsteps >= 0 steps of the Lawson integrating-factor
+ * RK4 scheme (RK4 at constant step, section "Performance", 2D and 3D
+ * benchmarks; exact viscous factor E = exp(-nu |k|^2 dt)):
+ *   k1 = N(u)  k2 = N(Eh (u + dt/2 k1))  k3 = N(Eh u + dt/2 k2)
+ *   k4 = N(E u + dt Eh k3)   u' = E u + dt/6 (E k1 + 2 Eh k2 + 2 Eh k3 + k4)
+ * with Eh = exp(-nu |k|^2 dt/2) and N the tendency of fs_tendency.  With
+ * forcing, alpha is recomputed from u at the start of every step and held
+ * for its four stages.  Modes outside the kept set are not written.
+ */
+fs_status fs_step_rk4(fs_plan *plan, void *state, int nsteps);
+
+/*
+ * FP64 diagnostics of a state (sim.output.spatial_means and spectra of the
+ * paper, section "Implementation and architecture"), reduced
+ * deterministically on the GPU over the kept set with half-spectrum weights
+ * w = 1 (kx = 0), 2 (kx > 0):
+ *   energy    E = 1/2 sum w |u_hat|^2      (2D: |u_hat|^2 = |w_hat|^2/|k|^2)
+ *   enstrophy Z = 1/2 sum w |w_hat|^2      (3D: w_hat = i k x u_hat)
+ *   spectrum[s] = 1/2 sum over modes with floor(|m| + 1/2) = s of w |u_hat|^2
+ * for s < nbins (1 <= nbins <= 1024); modes in higher shells count in E only.
+ * spectrum (nbins doubles), energy and enstrophy (one double each, may be
+ * NULL) are device pointers.
+ */
+fs_status fs_energy_spectrum(fs_plan *plan, const void *state, double *spectrum, int nbins,
+                             double *energy, double *enstrophy);
+
+/*
+ * With FS_PROFILE: accumulate the elapsed time of every kernel launched since
+ * the previous call (waits for them) into ms[kid] and launch counts into
+ * counts[kid] for kid < nk; names[kid] receives a static kernel name.  Kernel
+ * ids: 0 p1 (first inverse pass from the state), 1 y-inverse, 2 x (C2R,
+ * product, R2C), 3 y-forward, 4 z/y fused stage pass, 5 forcing coefficient,
+ * 6 fill, 7 transform-only passes, 8 diagnostics.  Any pointer may be NULL.
+ */
+fs_status fs_profile_read(fs_plan *plan, double *ms, long *counts, const char **names, int nk);
+
+/* Status name and last error message of the calling thread. */
+const char *fs_status_str(fs_status s);
+const char *fs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FS_H_ */

@@ -1,0 +1,228 @@
+// diag.hip -- FP64 diagnostics (energy, enstrophy, shell spectrum), the
+// constant-power forcing coefficient and a fill kernel.
+//
+// All reductions are deterministic: every partial sum is formed in a fixed
+// order (per-lane accumulators, fixed shuffle trees, wave-private LDS bins,
+// then a second kernel summing block partials in block order), so a rerun on
+// the same input gives the same bits.
+#include <cmath>
+
+#include "fft_core.h"
+#include "fs_internal.h"
+
+namespace fs {
+namespace {
+
+constexpr int kWaves = kDiagThreads / 64;
+
+__device__ __forceinline__ int dmode(int i, int n) { return i <= n / 2 ? i : i - n; }
+__device__ __forceinline__ int j2i_rt(int j, int K, int n) { return j <= K ? j : j + n - (2 * K + 1); }
+
+// Pass 1: one wave per row of kept modes ((kz, ky) in 3D, ky in 2D); lanes
+// run along kx, where the shell index is non-decreasing, so the spectrum
+// contributions of a 64-mode chunk form contiguous segments that a segmented
+// scan sums before one lane per segment adds into the wave's own bins.
+template <typename T>
+__global__ void __launch_bounds__(kDiagThreads)
+    k_diag1(const cx<T>* __restrict__ state, int ndim, int n, int K, double kb, int nbins,
+            double* __restrict__ partial) {
+  __shared__ double bins[kWaves][kDiagMaxBins];
+  __shared__ double red[2][kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int s = threadIdx.x; s < kWaves * kDiagMaxBins; s += kDiagThreads)
+    (&bins[0][0])[s] = 0.0;
+  __syncthreads();
+  const int M = 2 * K + 1, H = K + 1, NH = n / 2 + 1;
+  const int rows = ndim == 3 ? M * M : M;
+  const int W = gridDim.x * kWaves;
+  const size_t cstride = (size_t)n * n * NH;
+  double eacc = 0.0, zacc = 0.0;
+  for (int r = blockIdx.x * kWaves + wave; r < rows; r += W) {
+    int iz = 0, mz = 0, iy, my;
+    if (ndim == 3) {
+      iz = j2i_rt(r / M, K, n);
+      iy = j2i_rt(r % M, K, n);
+      mz = dmode(iz, n);
+    } else {
+      iy = j2i_rt(r, K, n);
+    }
+    my = dmode(iy, n);
+    const size_t rowoff = ((size_t)iz * n + iy) * NH;
+    for (int c0 = 0; c0 < H; c0 += 64) {
+      const int mx = c0 + lane;
+      double eu = 0.0, ez = 0.0;
+      int s = 0x7fffffff;
+      if (mx < H) {
+        const double w = mx == 0 ? 1.0 : 2.0;
+        const double kx = kb * mx, ky = kb * my, kz = kb * mz;
+        const int m2 = mx * mx + my * my + mz * mz;
+        if (ndim == 3) {
+          const cx<T> a = state[rowoff + mx], b = state[cstride + rowoff + mx],
+                      c = state[2 * cstride + rowoff + mx];
+          const double ar = a.re, ai = a.im, br = b.re, bi = b.im, cr = c.re, ci = c.im;
+          eu = 0.5 * w * (ar * ar + ai * ai + br * br + bi * bi + cr * cr + ci * ci);
+          // |k x u|^2, real and imaginary parts separately
+          const double x0r = ky * cr - kz * br, x0i = ky * ci - kz * bi;
+          const double x1r = kz * ar - kx * cr, x1i = kz * ai - kx * ci;
+          const double x2r = kx * br - ky * ar, x2i = kx * bi - ky * ai;
+          ez = 0.5 * w * (x0r * x0r + x0i * x0i + x1r * x1r + x1i * x1i + x2r * x2r + x2i * x2i);
+          s = (int)floor(sqrt((double)m2) + 0.5);
+        } else if (m2 > 0) {
+          const cx<T> a = state[rowoff + mx];
+          const double a2 = (double)a.re * a.re + (double)a.im * a.im;
+          const double k2 = kx * kx + ky * ky;
+          eu = 0.5 * w * a2 / k2;
+          ez = 0.5 * w * a2;
+          s = (int)floor(sqrt((double)m2) + 0.5);
+        } else {
+          s = 0;
+        }
+      }
+      eacc += eu;
+      zacc += ez;
+      double val = eu;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const double o = __shfl_up(val, d, 64);
+        const int so = __shfl_up(s, d, 64);
+        if (lane >= d && so == s) val += o;
+      }
+      const int sn = __shfl_down(s, 1, 64);
+      const bool last = lane == 63 || sn != s;
+      if (last && s < nbins) bins[wave][s] += val;
+    }
+  }
+  // fixed-order wave reduction of the totals
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    eacc += __shfl_down(eacc, d, 64);
+    zacc += __shfl_down(zacc, d, 64);
+  }
+  if (lane == 0) {
+    red[0][wave] = eacc;
+    red[1][wave] = zacc;
+  }
+  __syncthreads();
+  double* out = partial + (size_t)blockIdx.x * (nbins + 2);
+  for (int s = threadIdx.x; s < nbins; s += kDiagThreads) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) v += bins[w][s];
+    out[s] = v;
+  }
+  if (threadIdx.x == 0) {
+    double e = 0.0, z = 0.0;
+    for (int w = 0; w < kWaves; w++) {
+      e += red[0][w];
+      z += red[1][w];
+    }
+    out[nbins] = e;
+    out[nbins + 1] = z;
+  }
+}
+
+// Pass 2: sum block partials in block order.
+__global__ void __launch_bounds__(kDiagThreads)
+    k_diag2(const double* __restrict__ partial, int nblocks, int nbins, double* spectrum,
+            double* energy, double* enstrophy) {
+  for (int s = threadIdx.x; s < nbins + 2; s += kDiagThreads) {
+    double v = 0.0;
+    for (int b = 0; b < nblocks; b++) v += partial[(size_t)b * (nbins + 2) + s];
+    if (s < nbins)
+      spectrum[s] = v;
+    else if (s == nbins && energy)
+      *energy = v;
+    else if (s == nbins + 1 && enstrophy)
+      *enstrophy = v;
+  }
+}
+
+// Forcing coefficient alpha = power / sum_band w |u_hat|^2 (0 if the band is
+// empty), one block, fixed-order tree.
+template <typename T>
+__global__ void __launch_bounds__(kDiagThreads)
+    k_alpha(const cx<T>* __restrict__ state, int n, int bw, int m2min, int m2max, double power,
+            T* __restrict__ alpha) {
+  __shared__ double red[kDiagThreads];
+  const int NH = n / 2 + 1;
+  const size_t cstride = (size_t)n * n * NH;
+  const int side = 2 * bw + 1, cnt = side * side * (bw + 1);
+  double acc = 0.0;
+  for (int idx = threadIdx.x; idx < cnt; idx += kDiagThreads) {
+    const int mx = idx % (bw + 1);
+    const int my = (idx / (bw + 1)) % side - bw;
+    const int mz = idx / ((bw + 1) * side) - bw;
+    const int m2 = mx * mx + my * my + mz * mz;
+    if (m2 < m2min || m2 > m2max) continue;
+    const double w = mx == 0 ? 1.0 : 2.0;
+    const int iz = mz < 0 ? mz + n : mz, iy = my < 0 ? my + n : my;
+    const size_t o = ((size_t)iz * n + iy) * NH + mx;
+    for (int c = 0; c < 3; c++) {
+      const cx<T> u = state[c * cstride + o];
+      acc += w * ((double)u.re * u.re + (double)u.im * u.im);
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int d = kDiagThreads / 2; d >= 1; d >>= 1) {
+    if (threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) alpha[0] = (T)(red[0] > 0.0 ? power / red[0] : 0.0);
+}
+
+template <typename T>
+__global__ void k_fill_zero(cx<T>* __restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = cx<T>{0, 0};
+}
+
+}  // namespace
+
+template <typename T>
+void launch_diag(Plan* p, const void* state, double* spectrum, int nbins, double* energy,
+                 double* enstrophy) {
+  const int K = (p->n - 1) / 3, M = 2 * K + 1;
+  const int rows = p->ndim == 3 ? M * M : M;
+  int blocks = (rows + kWaves - 1) / kWaves;
+  if (blocks > p->dpart_blocks) blocks = p->dpart_blocks;
+  p->begin(KID_DIAG);
+  hipLaunchKernelGGL((k_diag1<T>), dim3(blocks), dim3(kDiagThreads), 0, p->launch,
+                     (const cx<T>*)state, p->ndim, p->n, K, 2.0 * M_PI / p->L, nbins, p->dpart);
+  launched(p, "k_diag1");
+  hipLaunchKernelGGL(k_diag2, dim3(1), dim3(kDiagThreads), 0, p->launch, (const double*)p->dpart,
+                     blocks, nbins, spectrum, energy, enstrophy);
+  launched(p, "k_diag2");
+  p->end(KID_DIAG);
+}
+
+template <typename T>
+void launch_alpha(Plan* p, const void* state) {
+  p->begin(KID_ALPHA);
+  hipLaunchKernelGGL((k_alpha<T>), dim3(1), dim3(kDiagThreads), 0, p->launch, (const cx<T>*)state,
+                     p->n, p->bw, p->m2min, p->m2max, p->fpow, (T*)p->alpha);
+  launched(p, "k_alpha");
+  p->end(KID_ALPHA);
+}
+
+template <typename T>
+void launch_fill(Plan* p, void* ptr, size_t n_complex) {
+  p->begin(KID_FILL);
+  size_t blocks = (n_complex + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL((k_fill_zero<T>), dim3((unsigned)blocks), dim3(256), 0, p->launch,
+                     (cx<T>*)ptr, n_complex);
+  launched(p, "k_fill_zero");
+  p->end(KID_FILL);
+}
+
+template void launch_diag<float>(Plan*, const void*, double*, int, double*, double*);
+template void launch_diag<double>(Plan*, const void*, double*, int, double*, double*);
+template void launch_alpha<float>(Plan*, const void*);
+template void launch_alpha<double>(Plan*, const void*);
+template void launch_fill<float>(Plan*, void*, size_t);
+template void launch_fill<double>(Plan*, void*, size_t);
+
+}  // namespace fs

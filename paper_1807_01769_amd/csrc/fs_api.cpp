@@ -1,0 +1,433 @@
+// fs_api.cpp -- the C ABI of libfs: argument validation, plan construction
+// (FP64 tables rounded once to the working precision, one workspace
+// allocation), step graphs and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fs.h"
+#include "fft_core.h"
+#include "fs_internal.h"
+
+struct fs_plan {
+  fs::Plan p;
+};
+
+namespace fs {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+bool Plan::ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  set_error("%s: %s", what, hipGetErrorString(e));
+  failed = true;
+  return false;
+}
+
+bool launched(Plan* p, const char* what) { return p->ok(hipGetLastError(), what); }
+
+void Plan::begin(int kid) {
+  (void)kid;
+  if (!(flags & FS_PROFILE)) return;
+  if (pool_used + 2 > pool.size()) {
+    for (int i = 0; i < 64; i++) {
+      hipEvent_t e;
+      if (!ok(hipEventCreate(&e), "hipEventCreate")) return;
+      pool.push_back(e);
+    }
+  }
+  Mark m{kid, pool[pool_used], pool[pool_used + 1]};
+  pool_used += 2;
+  ok(hipEventRecord(m.a, launch), "hipEventRecord");
+  marks.push_back(m);
+}
+
+void Plan::end(int kid) {
+  (void)kid;
+  if (!(flags & FS_PROFILE) || marks.empty()) return;
+  ok(hipEventRecord(marks.back().b, launch), "hipEventRecord");
+}
+
+}  // namespace fs
+
+using fs::Plan;
+
+namespace {
+
+const char* kKernelNames[fs::KID_COUNT] = {"p1",    "y_inverse", "x_c2r_product_r2c",
+                                           "y_forward", "z_stage", "forcing_alpha",
+                                           "fill",  "fft_only",  "diagnostics"};
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+bool isfin(double x) { return std::isfinite(x); }
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+fs_status fail(fs_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  fs::g_err = buf;
+  return s;
+}
+
+fs_status usable(const fs_plan* plan) {
+  if (!plan) return fail(FS_E_INVALID, "plan is NULL");
+  if (plan->p.failed) return fail(FS_E_DEVICE, "plan failed earlier: %s", fs::g_err.c_str());
+  return FS_OK;
+}
+
+fs_status device_status(Plan* p) { return p->failed ? FS_E_DEVICE : FS_OK; }
+
+void release(Plan* p) {
+  if (p->gmid) hipGraphExecDestroy(p->gmid);
+  if (p->glast) hipGraphExecDestroy(p->glast);
+  p->gmid = p->glast = nullptr;
+  for (auto e : p->pool) hipEventDestroy(e);
+  p->pool.clear();
+  if (p->cap) hipStreamDestroy(p->cap);
+  p->cap = nullptr;
+  if (p->base) hipFree(p->base);
+  p->base = nullptr;
+}
+
+// One RK4 step (forcing coefficient, four stages) on p->launch.
+void enqueue_step(Plan* p, void* state, int do_p1) {
+  if (p->ops.alpha && p->m2max >= 0) p->ops.alpha(p, state);
+  for (int mode = 1; mode <= 4; mode++) p->ops.stage(p, state, mode, mode == 4 ? do_p1 : 1);
+}
+
+bool capture(Plan* p, void* state, int do_p1, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  p->launch = p->cap;
+  if (!p->ok(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal), "begin capture")) {
+    p->launch = p->stream;
+    return false;
+  }
+  enqueue_step(p, state, do_p1);
+  hipError_t e = hipStreamEndCapture(p->cap, &g);
+  p->launch = p->stream;
+  if (!p->ok(e, "end capture") || p->failed) {
+    if (g) hipGraphDestroy(g);
+    return false;
+  }
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  return p->ok(e, "hipGraphInstantiate");
+}
+
+int K_of(int n) { return (n - 1) / 3; }
+
+}  // namespace
+
+extern "C" {
+
+void fs_plan_opts_default(fs_plan_opts* o) {
+  if (!o) return;
+  o->ndim = 3;
+  o->precision = FS_F32;
+  o->stream = nullptr;
+  o->forcing_power = 0.0;
+  o->forcing_kmin = 2.0;
+  o->forcing_kmax = 3.0;
+  o->flags = 0;
+}
+
+fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
+                         const fs_plan_opts* opts) {
+  if (!out) return fail(FS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fs_plan_opts o;
+  fs_plan_opts_default(&o);
+  if (opts) o = *opts;
+  if (n <= 0) return fail(FS_E_INVALID, "n = %d must be positive", n);
+  if (!is_pow2(n) || n < 16 || n > 1024)
+    return fail(FS_E_UNSUPPORTED, "n = %d: supported sizes are powers of two 16..1024", n);
+  if (!(isfin(L) && L > 0)) return fail(FS_E_INVALID, "L must be finite and > 0");
+  if (!(isfin(nu) && nu >= 0)) return fail(FS_E_INVALID, "nu must be finite and >= 0");
+  if (!(isfin(dt) && dt > 0)) return fail(FS_E_INVALID, "dt must be finite and > 0");
+  if (o.ndim != 2 && o.ndim != 3) return fail(FS_E_INVALID, "ndim = %d must be 2 or 3", o.ndim);
+  if (o.precision != FS_F32 && o.precision != FS_F64)
+    return fail(FS_E_INVALID, "precision = %d must be FS_F32 or FS_F64", o.precision);
+  if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE)) return fail(FS_E_INVALID, "unknown flags");
+  if (!(isfin(o.forcing_power) && o.forcing_power >= 0))
+    return fail(FS_E_INVALID, "forcing_power must be finite and >= 0");
+  const double kb = 2.0 * M_PI / L;
+  const int K = K_of(n);
+  int bw = 0, m2min = 0, m2max = -1;
+  if (o.forcing_power > 0) {
+    if (o.ndim != 3) return fail(FS_E_UNSUPPORTED, "forcing is implemented for ndim = 3 only");
+    if (!(isfin(o.forcing_kmin) && isfin(o.forcing_kmax) && o.forcing_kmin >= 0 &&
+          o.forcing_kmax >= o.forcing_kmin && o.forcing_kmax > 0))
+      return fail(FS_E_INVALID, "forcing band must satisfy 0 <= kmin <= kmax, kmax > 0");
+    bw = (int)std::floor(o.forcing_kmax / kb);
+    if (bw > K) return fail(FS_E_INVALID, "forcing band reaches beyond the dealiased modes");
+    // integer |m|^2 range, evaluated as |k| = kb sqrt(m2) in FP64
+    m2min = 1 << 30;
+    for (int m2 = 1; m2 <= 3 * bw * bw; m2++) {
+      const double km = kb * std::sqrt((double)m2);
+      if (km >= o.forcing_kmin && km <= o.forcing_kmax) {
+        if (m2 < m2min) m2min = m2;
+        m2max = m2;
+      }
+    }
+    if (m2max < 0) return fail(FS_E_INVALID, "forcing band contains no mode");
+    if (bw < 1) bw = 1;
+  }
+
+  fs_plan* h = new (std::nothrow) fs_plan();
+  if (!h) return fail(FS_E_NOMEM, "host allocation failed");
+  Plan* p = &h->p;
+  p->n = n;
+  p->ndim = o.ndim;
+  p->prec = o.precision;
+  p->L = L;
+  p->nu = nu;
+  p->dt = dt;
+  p->fpow = o.forcing_power;
+  p->fkmin = o.forcing_kmin;
+  p->fkmax = o.forcing_kmax;
+  p->bw = bw;
+  p->m2min = m2min;
+  p->m2max = m2max;
+  p->flags = o.flags;
+  p->stream = (hipStream_t)o.stream;
+  p->launch = p->stream;
+  if (o.ndim == 3)
+    p->ops = o.precision == FS_F32 ? fs::make_ops3<float>(n) : fs::make_ops3<double>(n);
+  else
+    p->ops = o.precision == FS_F32 ? fs::make_ops2<float>(n) : fs::make_ops2<double>(n);
+  if (!p->ops.stage) {
+    delete h;
+    return fail(FS_E_UNSUPPORTED, "no kernels for n = %d", n);
+  }
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete h;
+    return fail(FS_E_DEVICE, "no HIP device");
+  }
+  const size_t rs = o.precision == FS_F32 ? 4 : 8, cs = 2 * rs;
+  const int band_elems = 3 * (2 * bw + 1) * (2 * bw + 1) * (bw + 1);
+  const size_t dpart = (size_t)fs::kDiagMaxBlocks * (fs::kDiagMaxBins + 2) * sizeof(double);
+  size_t off[9];
+  size_t sz[9] = {cs * n,
+                  rs * n,
+                  rs * n,
+                  cs * p->ops.elems_a,
+                  cs * p->ops.elems_b,
+                  cs * p->ops.elems_acc,
+                  cs * (size_t)(band_elems > 0 ? band_elems : 1),
+                  rs * 2,
+                  dpart};
+  size_t total = 0;
+  for (int i = 0; i < 9; i++) {
+    off[i] = total;
+    total += align256(sz[i]);
+  }
+  if (hipMalloc(&p->base, total) != hipSuccess) {
+    hipGetLastError();
+    delete h;
+    return fail(FS_E_NOMEM, "hipMalloc of %zu bytes failed", total);
+  }
+  p->bytes_total = total;
+  char* b = (char*)p->base;
+  p->tw = b + off[0];
+  p->e1 = b + off[1];
+  p->eh1 = b + off[2];
+  p->bufA = b + off[3];
+  p->bufB = b + off[4];
+  p->acc = b + off[5];
+  p->vband = b + off[6];
+  p->alpha = b + off[7];
+  p->dpart = (double*)(b + off[8]);
+  p->dpart_blocks = fs::kDiagMaxBlocks;
+
+  // FP64 tables, rounded once
+  std::vector<char> host(sz[0] + sz[1] + sz[2]);
+  for (int m = 0; m < n; m++) {
+    const double a = -2.0 * M_PI * (double)m / (double)n;
+    const double c = std::cos(a), s = std::sin(a);
+    const int mm = m <= n / 2 ? m : m - n;
+    const double k2 = kb * kb * (double)mm * (double)mm;
+    const double e = std::exp(-nu * dt * k2), eh = std::exp(-0.5 * nu * dt * k2);
+    if (rs == 4) {
+      float* t = (float*)host.data();
+      t[2 * m] = (float)c;
+      t[2 * m + 1] = (float)s;
+      ((float*)(host.data() + sz[0]))[m] = (float)e;
+      ((float*)(host.data() + sz[0] + sz[1]))[m] = (float)eh;
+    } else {
+      double* t = (double*)host.data();
+      t[2 * m] = c;
+      t[2 * m + 1] = s;
+      ((double*)(host.data() + sz[0]))[m] = e;
+      ((double*)(host.data() + sz[0] + sz[1]))[m] = eh;
+    }
+  }
+  bool ok = p->ok(hipMemcpy(p->tw, host.data(), sz[0], hipMemcpyHostToDevice), "copy tables") &&
+            p->ok(hipMemcpy(p->e1, host.data() + sz[0], sz[1], hipMemcpyHostToDevice),
+                  "copy tables") &&
+            p->ok(hipMemcpy(p->eh1, host.data() + sz[0] + sz[1], sz[2], hipMemcpyHostToDevice),
+                  "copy tables") &&
+            p->ok(hipMemset(p->vband, 0, sz[6]), "clear band") &&
+            p->ok(hipMemset(p->alpha, 0, sz[7]), "clear alpha") &&
+            p->ok(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking), "capture stream");
+  if (!ok) {
+    std::string msg = fs::g_err;
+    release(p);
+    delete h;
+    return fail(FS_E_DEVICE, "%s", msg.c_str());
+  }
+  *out = h;
+  return FS_OK;
+}
+
+fs_status fs_plan_destroy(fs_plan* plan) {
+  if (!plan) return FS_OK;
+  Plan* p = &plan->p;
+  if (p->stream) hipStreamSynchronize(p->stream);
+  else hipDeviceSynchronize();
+  release(p);
+  delete plan;
+  return FS_OK;
+}
+
+fs_status fs_plan_set_stream(fs_plan* plan, void* stream) {
+  if (fs_status s = usable(plan)) return s;
+  plan->p.stream = (hipStream_t)stream;
+  plan->p.launch = plan->p.stream;
+  return FS_OK;
+}
+
+fs_status fs_state_elems(const fs_plan* plan, size_t* n_complex) {
+  if (!plan || !n_complex) return fail(FS_E_INVALID, "NULL argument");
+  const size_t n = plan->p.n;
+  *n_complex = plan->p.ndim == 3 ? 3 * n * n * (n / 2 + 1) : n * (n / 2 + 1);
+  return FS_OK;
+}
+
+fs_status fs_workspace_bytes(const fs_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(FS_E_INVALID, "NULL argument");
+  *bytes = plan->p.bytes_total;
+  return FS_OK;
+}
+
+fs_status fs_spectrum_bins(const fs_plan* plan, int* nbins) {
+  if (!plan || !nbins) return fail(FS_E_INVALID, "NULL argument");
+  const int K = K_of(plan->p.n);
+  *nbins = (int)std::floor(std::sqrt((double)plan->p.ndim) * K + 0.5) + 1;
+  return FS_OK;
+}
+
+fs_status fs_fft_forward(fs_plan* plan, const void* phys, void* spec) {
+  if (fs_status s = usable(plan)) return s;
+  if (!phys || !spec) return fail(FS_E_INVALID, "NULL array");
+  plan->p.ops.fft_fwd(&plan->p, phys, spec);
+  return device_status(&plan->p);
+}
+
+fs_status fs_fft_inverse(fs_plan* plan, const void* spec, void* phys) {
+  if (fs_status s = usable(plan)) return s;
+  if (!phys || !spec) return fail(FS_E_INVALID, "NULL array");
+  plan->p.ops.fft_inv(&plan->p, spec, phys);
+  return device_status(&plan->p);
+}
+
+fs_status fs_tendency(fs_plan* plan, const void* state, void* tend) {
+  if (fs_status s = usable(plan)) return s;
+  if (!state || !tend) return fail(FS_E_INVALID, "NULL array");
+  if (state == tend) return fail(FS_E_INVALID, "state and tend must not overlap");
+  plan->p.ops.tendency(&plan->p, state, tend);
+  return device_status(&plan->p);
+}
+
+fs_status fs_step_rk4(fs_plan* plan, void* state, int nsteps) {
+  if (fs_status s = usable(plan)) return s;
+  if (!state) return fail(FS_E_INVALID, "NULL state");
+  if (nsteps < 0) return fail(FS_E_INVALID, "nsteps = %d must be >= 0", nsteps);
+  if (nsteps == 0) return FS_OK;
+  Plan* p = &plan->p;
+  p->ops.p1(p, state);
+  const bool graphs = !(p->flags & (FS_NO_GRAPH | FS_PROFILE));
+  if (graphs) {
+    if (p->gstate != state || !p->gmid || !p->glast) {
+      if (p->gmid) hipGraphExecDestroy(p->gmid);
+      if (p->glast) hipGraphExecDestroy(p->glast);
+      p->gmid = p->glast = nullptr;
+      p->gstate = nullptr;
+      if (!capture(p, state, 1, &p->gmid) || !capture(p, state, 0, &p->glast))
+        return FS_E_DEVICE;
+      p->gstate = state;
+    }
+    for (int s = 0; s < nsteps; s++)
+      if (!p->ok(hipGraphLaunch(s + 1 < nsteps ? p->gmid : p->glast, p->stream), "graph launch"))
+        return FS_E_DEVICE;
+  } else {
+    for (int s = 0; s < nsteps; s++) enqueue_step(p, state, s + 1 < nsteps);
+  }
+  return device_status(p);
+}
+
+fs_status fs_energy_spectrum(fs_plan* plan, const void* state, double* spectrum, int nbins,
+                             double* energy, double* enstrophy) {
+  if (fs_status s = usable(plan)) return s;
+  if (!state || !spectrum) return fail(FS_E_INVALID, "NULL array");
+  if (nbins < 1 || nbins > fs::kDiagMaxBins)
+    return fail(FS_E_INVALID, "nbins = %d must be in 1..%d", nbins, fs::kDiagMaxBins);
+  plan->p.ops.diag(&plan->p, state, spectrum, nbins, energy, enstrophy);
+  return device_status(&plan->p);
+}
+
+fs_status fs_profile_read(fs_plan* plan, double* ms, long* counts, const char** names, int nk) {
+  if (fs_status s = usable(plan)) return s;
+  Plan* p = &plan->p;
+  for (auto& m : p->marks) {
+    float t = 0.f;
+    if (!p->ok(hipEventSynchronize(m.b), "hipEventSynchronize")) return FS_E_DEVICE;
+    if (!p->ok(hipEventElapsedTime(&t, m.a, m.b), "hipEventElapsedTime")) return FS_E_DEVICE;
+    p->kms[m.kid] += t;
+    p->kcount[m.kid] += 1;
+  }
+  p->marks.clear();
+  p->pool_used = 0;
+  for (int k = 0; k < nk && k < fs::KID_COUNT; k++) {
+    if (ms) ms[k] = p->kms[k];
+    if (counts) counts[k] = p->kcount[k];
+    if (names) names[k] = kKernelNames[k];
+  }
+  for (int k = 0; k < fs::KID_COUNT; k++) {
+    p->kms[k] = 0;
+    p->kcount[k] = 0;
+  }
+  return FS_OK;
+}
+
+const char* fs_status_str(fs_status s) {
+  switch (s) {
+    case FS_OK: return "FS_OK";
+    case FS_E_INVALID: return "FS_E_INVALID";
+    case FS_E_UNSUPPORTED: return "FS_E_UNSUPPORTED";
+    case FS_E_NOMEM: return "FS_E_NOMEM";
+    case FS_E_DEVICE: return "FS_E_DEVICE";
+    case FS_E_NONFINITE: return "FS_E_NONFINITE";
+  }
+  return "FS_E_UNKNOWN";
+}
+
+const char* fs_last_error(void) { return fs::g_err.c_str(); }
+
+}  // extern "C"

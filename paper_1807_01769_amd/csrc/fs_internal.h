@@ -1,0 +1,110 @@
+// fs_internal.h -- plan object and kernel-family dispatch shared by the host
+// sources of libfs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/fs.h"
+
+namespace fs {
+
+enum KernelId {
+  KID_P1 = 0,
+  KID_YINV,
+  KID_X,
+  KID_YFWD,
+  KID_Z,
+  KID_ALPHA,
+  KID_FILL,
+  KID_FFT,
+  KID_DIAG,
+  KID_COUNT
+};
+
+struct Plan;
+
+// Kernel sequences of one (ndim, precision, n) combination.
+struct Ops {
+  // first inverse pass of a stage from the caller's state (also records the
+  // forcing-band stage input)
+  void (*p1)(Plan*, const void* state);
+  // one RK4 stage (mode 1..4) after its first pass; do_p1 = 0 skips the next
+  // stage's inverse transforms at the end of the last step
+  void (*stage)(Plan*, void* state, int mode, int do_p1);
+  // tendency of `state` into `out` (all elements written)
+  void (*tendency)(Plan*, const void* state, void* out);
+  void (*fft_fwd)(Plan*, const void* phys, void* spec);
+  void (*fft_inv)(Plan*, const void* spec, void* phys);
+  // forcing coefficient from the state (3D only; may be null)
+  void (*alpha)(Plan*, const void* state);
+  // diagnostics
+  void (*diag)(Plan*, const void* state, double* spectrum, int nbins, double* energy,
+               double* enstrophy);
+  // workspace element counts (complex elements of the plan's precision)
+  size_t elems_a, elems_b, elems_acc;
+};
+
+struct Plan {
+  int n = 0, ndim = 3, prec = FS_F32;
+  double L = 0, nu = 0, dt = 0;
+  double fpow = 0, fkmin = 2, fkmax = 3;
+  int bw = 0, m2min = 0, m2max = -1;  // forcing band in integer |m|^2
+  unsigned flags = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;  // caller's stream
+  hipStream_t launch = nullptr;  // stream kernels go to right now
+  hipStream_t cap = nullptr;     // private stream used for graph capture
+  Ops ops{};
+  // device memory (one allocation, carved)
+  void* base = nullptr;
+  size_t bytes_total = 0;
+  void *tw = nullptr, *e1 = nullptr, *eh1 = nullptr;
+  void *bufA = nullptr, *bufB = nullptr, *acc = nullptr, *vband = nullptr, *alpha = nullptr;
+  double* dpart = nullptr;  // diagnostics partial sums
+  int dpart_blocks = 0;
+  // captured step graphs for one state pointer
+  hipGraphExec_t gmid = nullptr, glast = nullptr;
+  void* gstate = nullptr;
+  // profiling
+  struct Mark {
+    int kid;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  double kms[KID_COUNT] = {};
+  long kcount[KID_COUNT] = {};
+  bool failed = false;
+
+  // bracket a kernel launch (records events when profiling)
+  void begin(int kid);
+  void end(int kid);
+  bool ok(hipError_t e, const char* what);
+};
+
+void set_error(const char* fmt, ...);
+// check the launch just made; marks the plan failed on error
+bool launched(Plan* p, const char* what);
+
+template <typename T>
+Ops make_ops3(int n);
+template <typename T>
+Ops make_ops2(int n);
+
+// diagnostics launchers (diag.hip)
+template <typename T>
+void launch_diag(Plan* p, const void* state, double* spectrum, int nbins, double* energy,
+                 double* enstrophy);
+template <typename T>
+void launch_alpha(Plan* p, const void* state);
+template <typename T>
+void launch_fill(Plan* p, void* ptr, size_t n_complex);
+
+constexpr int kDiagThreads = 256;
+constexpr int kDiagMaxBins = 1024;
+constexpr int kDiagMaxBlocks = 1024;
+
+}  // namespace fs

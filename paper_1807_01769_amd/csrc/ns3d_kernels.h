@@ -1,0 +1,440 @@
+// ns3d_kernels.h -- kernels of the 3D velocity-form step.
+//
+// One tendency evaluation N(u) = P[(u x w)^] (w = curl u, P the projection
+// onto divergence-free fields, 2/3-rule cube truncation) is four passes over
+// HBM, each a batch of 1D transforms with the pointwise work fused in:
+//
+//   Z  (z, fwd + inv)  previous stage's products -> forward z transform ->
+//                      projection, forcing, Lawson RK4 combine -> next stage
+//                      input -> curl -> six inverse z transforms   [k3_z]
+//   Yi (y, inverse)    six fields                                 [k_y_inv]
+//   X  (x, c2r / r2c)  six C2R, u x w, three R2C                  [k3_x]
+//   Yf (y, forward)    three fields                               [k_y_fwd]
+//
+// Only kept modes are ever moved: the z passes touch the M x H kept
+// (ky, kx) columns, the y passes the H kept kx planes, and the x pass reads
+// and writes the H kept kx values of every row.
+#pragma once
+#include "ns_common.h"
+
+namespace fs {
+
+// ---------------------------------------------------------------------------
+// X pass: for each row pair (y0, y0+1) at height z, inverse-transform
+// (ux,uy) (uz,wx) (wy,wz) of both rows, form p = (u x w) * scale, forward
+// transform (px + i py) of each row and (pz(y0) + i pz(y1)), store kept kx.
+// in : Wn[6][N][XT][N][16]   out: Wn[3][N][XT][N][16]
+// Grid: (N/2/RP, N).
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__((RowPairs<N>::THREADS))
+    k3_x(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
+         T scale) {
+  using G = Geo<N, false>;
+  using R = RowPairs<N>;
+  constexpr int P = G::P;
+  __shared__ cx<T> lds[R::RP * 3 * R::NPAD];
+  const int rp = threadIdx.x / P, t = threadIdx.x % P;
+  const int z = blockIdx.y;
+  const int y0 = 2 * (blockIdx.x * R::RP + rp);
+  cx<T>* my_lds = lds + rp * 3 * R::NPAD;
+  auto lidx = [=](int f, int pos) { return f * R::NPAD + R::pad(pos); };
+
+  const size_t fstride = (size_t)N * G::XT * N * kTile;  // one field
+  const cx<T>* inz = in + (size_t)z * G::XT * N * kTile;
+  auto at = [=](int f, int y, int m) -> cx<T> {
+    return inz[f * fstride + ((size_t)(m >> 4) * N + y) * kTile + (m & 15)];
+  };
+
+  // u (3) and w (3) of both rows, two real fields per complex line
+  cx<T> uw[6][8];
+#pragma unroll
+  for (int g = 0; g < 3; g++) {
+    cx<T> v[2][8];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int y = y0 + r;
+#pragma unroll
+      for (int e = 0; e < 8; e++)
+        v[r][e] = c2r_pair_at<T, N, false>(
+            t + e * P, [&](int m) { return at(2 * g, y, m); },
+            [&](int m) { return at(2 * g + 1, y, m); });
+    }
+    fft_lines<T, N, +1, 2>(v, t, my_lds, lidx, tw);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      uw[g][e] = v[0][e];
+      uw[3 + g][e] = v[1][e];
+    }
+  }
+  // uw[0] = (ux, uy)(y0)  uw[1] = (uz, wx)(y0)  uw[2] = (wy, wz)(y0); +3 for y1
+  cx<T> pp[3][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    T pz[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const cx<T> a = uw[3 * r][e], b = uw[3 * r + 1][e], c = uw[3 * r + 2][e];
+      const T ux = a.re, uy = a.im, uz = b.re, wx = b.im, wy = c.re, wz = c.im;
+      const T px = (uy * wz - uz * wy) * scale;
+      const T py = (uz * wx - ux * wz) * scale;
+      pz[r] = (ux * wy - uy * wx) * scale;
+      pp[r][e] = {px, py};
+    }
+    pp[2][e] = {pz[0], pz[1]};
+  }
+  fft_lines<T, N, -1, 3>(pp, t, my_lds, lidx, tw);
+#pragma unroll
+  for (int f = 0; f < 3; f++)
+#pragma unroll
+    for (int e = 0; e < 8; e++) my_lds[lidx(f, t + e * P)] = pp[f][e];
+  __syncthreads();
+  cx<T>* outz = out + (size_t)z * G::XT * N * kTile;
+  for (int m = t; m < G::XT * kTile; m += P) {
+    cx<T> a[3], bq[3];
+#pragma unroll
+    for (int f = 0; f < 3; f++) {
+      if (m < G::H) {
+        r2c_untangle(my_lds[lidx(f, m)], my_lds[lidx(f, (N - m) & (N - 1))], a[f], bq[f]);
+      } else {
+        a[f] = {0, 0};
+        bq[f] = {0, 0};
+      }
+    }
+    const size_t o = ((size_t)(m >> 4) * N) * kTile + (m & 15);
+    // px, py, pz of row y0 and y1
+    outz[0 * fstride + o + (size_t)y0 * kTile] = a[0];
+    outz[1 * fstride + o + (size_t)y0 * kTile] = bq[0];
+    outz[0 * fstride + o + (size_t)(y0 + 1) * kTile] = a[1];
+    outz[1 * fstride + o + (size_t)(y0 + 1) * kTile] = bq[1];
+    outz[2 * fstride + o + (size_t)y0 * kTile] = a[2];
+    outz[2 * fstride + o + (size_t)(y0 + 1) * kTile] = bq[2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse z transforms of the six fields (u, w = i k x v) of a stage input v
+// held in registers as v[c][e] at z-position t + e*P of line b; writes
+// Wm[6][N][XT][M][16] (fields ordered ux uy uz wx wy wz).
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__device__ __forceinline__ void z_inverse_six(cx<T> (&v)[3][8], int t, int b, int jy, int xt,
+                                              int sub, int mx, int my, T kb,
+                                              cx<T>* __restrict__ w1, cx<T>* lds,
+                                              const cx<T>* __restrict__ tw) {
+  using G = Geo<N, false>;
+  using C = Strided<T, N>;
+  constexpr int P = G::P;
+  const size_t fstride = (size_t)N * G::XT * G::M * kTile;
+  cx<T>* dst0 = w1 + (size_t)xt * G::M * kTile + (size_t)jy * kTile + sub * C::LB + b;
+  const size_t zstride = (size_t)G::XT * G::M * kTile;
+  auto lidx = [=](int, int pos) { return pos * C::LB + b; };
+  const T kx = kb * (T)mx, ky = kb * (T)my;
+  // vorticity first (needs v), then velocity in place
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    cx<T> w[1][8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int iz = t + e * P;
+      const T kz = kb * (T)(iz <= N / 2 ? iz : iz - N);
+      cx<T> r;
+      if (c == 0) r = mul_i(cscale(v[2][e], ky) - cscale(v[1][e], kz));
+      else if (c == 1) r = mul_i(cscale(v[0][e], kz) - cscale(v[2][e], kx));
+      else r = mul_i(cscale(v[1][e], kx) - cscale(v[0][e], ky));
+      w[0][e] = r;
+    }
+    fft_lines<T, N, +1, 1>(w, t, lds, lidx, tw);
+    cx<T>* dst = dst0 + (3 + c) * fstride;
+#pragma unroll
+    for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = w[0][e];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    cx<T> w[1][8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) w[0][e] = v[c][e];
+    fft_lines<T, N, +1, 1>(w, t, lds, lidx, tw);
+    cx<T>* dst = dst0 + c * fstride;
+#pragma unroll
+    for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = w[0][e];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ int band_index(int mx, int my, int mz, int bw) {
+  return ((mz + bw) * (2 * bw + 1) + (my + bw)) * (bw + 1) + mx;
+}
+
+template <typename T>
+__device__ __forceinline__ bool in_band(const StageArgs<T>& a, int mx, int my, int mz) {
+  if (a.m2max < 0) return false;
+  if (mx > a.bw || my > a.bw || my < -a.bw || mz > a.bw || mz < -a.bw) return false;
+  const int m2 = mx * mx + my * my + mz * mz;
+  return m2 >= a.m2min && m2 <= a.m2max;
+}
+
+// ---------------------------------------------------------------------------
+// First inverse pass of a stage, from the caller's state (ABI layout
+// [3][N][N][N/2+1]): masks to the kept set, records the band values, and
+// writes the six inverse-z-transformed fields.  Grid: M * XT * SUB.
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+    k3_p1(const cx<T>* __restrict__ state, cx<T>* __restrict__ w1, StageArgs<T> a) {
+  using G = Geo<N, false>;
+  using C = Strided<T, N>;
+  constexpr int P = G::P;
+  constexpr int NH = N / 2 + 1;
+  __shared__ cx<T> lds[C::LB * N];
+  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  int blk = blockIdx.x;
+  const int sub = blk % C::SUB;
+  blk /= C::SUB;
+  const int xt = blk % G::XT, jy = blk / G::XT;
+  const int mx = xt * kTile + sub * C::LB + b;
+  const int iy = G::j2i(jy), my = G::jmode(jy);
+  const bool col = mx < G::H;
+  const size_t cstride = (size_t)N * N * NH;
+  cx<T> v[3][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int iz = t + e * P;
+    const bool kept = col && G::i2j(iz) >= 0;
+    const size_t o = ((size_t)iz * N + iy) * NH + mx;
+#pragma unroll
+    for (int c = 0; c < 3; c++) v[c][e] = kept ? state[c * cstride + o] : cx<T>{0, 0};
+    if (kept) {
+      const int mz = iz <= N / 2 ? iz : iz - N;
+      if (in_band(a, mx, my, mz)) {
+        const int bi = band_index<T>(mx, my, mz, a.bw);
+        const int bn = (2 * a.bw + 1) * (2 * a.bw + 1) * (a.bw + 1);
+#pragma unroll
+        for (int c = 0; c < 3; c++) a.vband[c * bn + bi] = v[c][e];
+      }
+    }
+  }
+  z_inverse_six<T, N>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, a.tw);
+}
+
+// ---------------------------------------------------------------------------
+// Z pass: forward z transforms of the stage's products (Wm[3][N][XT][M][16]),
+// projection + forcing -> tendency of this stage, Lawson RK4 combine, and
+// (do_p1) the next stage's six inverse z transforms into w1.
+// MODE kModeTend writes the tendency to a.tend instead.  Grid: M * XT * SUB.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+    k3_z(const cx<T>* __restrict__ w4, cx<T>* __restrict__ w1, StageArgs<T> a, int do_p1) {
+  using G = Geo<N, false>;
+  using C = Strided<T, N>;
+  constexpr int P = G::P;
+  constexpr int NH = N / 2 + 1;
+  __shared__ cx<T> lds[C::LB * N];
+  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  int blk = blockIdx.x;
+  const int sub = blk % C::SUB;
+  blk /= C::SUB;
+  const int xt = blk % G::XT, jy = blk / G::XT;
+  const int mx = xt * kTile + sub * C::LB + b;
+  const int iy = G::j2i(jy), my = G::jmode(jy);
+  const bool col = mx < G::H;
+  auto lidx = [=](int, int pos) { return pos * C::LB + b; };
+
+  // forward z transforms of the three product components
+  const size_t fstride = (size_t)N * G::XT * G::M * kTile;
+  const size_t zstride = (size_t)G::XT * G::M * kTile;
+  const cx<T>* src0 = w4 + (size_t)xt * G::M * kTile + (size_t)jy * kTile + sub * C::LB + b;
+  cx<T> v[3][8];
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    cx<T> w[1][8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) w[0][e] = src0[c * fstride + (size_t)(t + e * P) * zstride];
+    fft_lines<T, N, -1, 1>(w, t, lds, lidx, a.tw);
+#pragma unroll
+    for (int e = 0; e < 8; e++) v[c][e] = w[0][e];
+  }
+
+  const size_t cstride = (size_t)N * N * NH;
+  const size_t acstride = (size_t)G::XT * G::M * G::M * kTile;
+  const int bn = (2 * a.bw + 1) * (2 * a.bw + 1) * (a.bw + 1);
+  const T alpha = a.m2max >= 0 ? a.alpha[0] : (T)0;
+  const T kx = a.kb * (T)mx, ky = a.kb * (T)my;
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int iz = t + e * P;
+    const int jz = G::i2j(iz);
+    const bool kept = col && jz >= 0;
+    if (!kept) {
+#pragma unroll
+      for (int c = 0; c < 3; c++) v[c][e] = {0, 0};
+      continue;
+    }
+    const int mz = iz <= N / 2 ? iz : iz - N;
+    const T kz = a.kb * (T)mz;
+    const T k2 = kx * kx + ky * ky + kz * kz;
+    cx<T> nl[3];
+    if (k2 > (T)0) {
+      const T ik2 = (T)1 / k2;
+      const cx<T> kp = cscale(cscale(v[0][e], kx) + cscale(v[1][e], ky) + cscale(v[2][e], kz), ik2);
+      nl[0] = v[0][e] - cscale(kp, kx);
+      nl[1] = v[1][e] - cscale(kp, ky);
+      nl[2] = v[2][e] - cscale(kp, kz);
+    } else {
+      nl[0] = nl[1] = nl[2] = {0, 0};
+    }
+    const bool band = in_band(a, mx, my, mz);
+    const int bi = band ? band_index<T>(mx, my, mz, a.bw) : 0;
+    if (band) {
+#pragma unroll
+      for (int c = 0; c < 3; c++) nl[c] = nl[c] + cscale(a.vband[c * bn + bi], alpha);
+    }
+    const size_t so = ((size_t)iz * N + iy) * NH + mx;
+    if constexpr (MODE == kModeTend) {
+#pragma unroll
+      for (int c = 0; c < 3; c++) a.tend[c * cstride + so] = nl[c];
+    } else {
+      const T E = a.e1[mx] * a.e1[iy] * a.e1[iz];
+      const T Eh = a.eh1[mx] * a.eh1[iy] * a.eh1[iz];
+      const size_t ao = (((size_t)xt * G::M + jy) * G::M + jz) * kTile + sub * C::LB + b;
+#pragma unroll
+      for (int c = 0; c < 3; c++) {
+        cx<T> acc = {0, 0};
+        cx<T> u = {0, 0};
+        if constexpr (MODE != kStage4) u = a.state[c * cstride + so];
+        if constexpr (MODE != kStage1) acc = a.acc[c * acstride + ao];
+        const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, a.dt);
+        if constexpr (MODE == kStage4) {
+          a.state[c * cstride + so] = nxt;
+        } else {
+          a.acc[c * acstride + ao] = acc;
+        }
+        v[c][e] = nxt;
+      }
+      if (band && do_p1) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) a.vband[c * bn + bi] = v[c][e];
+      }
+    }
+  }
+  if constexpr (MODE != kModeTend) {
+    if (do_p1) z_inverse_six<T, N>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, a.tw);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plain (undealiased) 3D transforms, used by the FFT entry points.
+// spec: [N][N][N/2+1] complex; phys: [N][N][N] real.
+// ---------------------------------------------------------------------------
+// inverse z: spec -> Wm(FULL)[N][XT][N][16]; grid N * XT * SUB
+template <typename T, int N>
+__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+    k3f_z_inv(const cx<T>* __restrict__ spec, cx<T>* __restrict__ w, const cx<T>* __restrict__ tw) {
+  using G = Geo<N, true>;
+  using C = Strided<T, N>;
+  constexpr int P = G::P, NH = N / 2 + 1;
+  __shared__ cx<T> lds[C::LB * N];
+  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  int blk = blockIdx.x;
+  const int sub = blk % C::SUB;
+  blk /= C::SUB;
+  const int xt = blk % G::XT, iy = blk / G::XT;
+  const int mx = xt * kTile + sub * C::LB + b;
+  cx<T> v[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++)
+    v[0][e] = mx < G::H ? spec[((size_t)(t + e * P) * N + iy) * NH + mx] : cx<T>{0, 0};
+  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  const size_t zstride = (size_t)G::XT * N * kTile;
+  cx<T>* dst = w + ((size_t)xt * N + iy) * kTile + sub * C::LB + b;
+#pragma unroll
+  for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = v[0][e];
+}
+
+// forward z: Wm(FULL) -> spec; grid N * XT * SUB
+template <typename T, int N>
+__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+    k3f_z_fwd(const cx<T>* __restrict__ w, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw) {
+  using G = Geo<N, true>;
+  using C = Strided<T, N>;
+  constexpr int P = G::P, NH = N / 2 + 1;
+  __shared__ cx<T> lds[C::LB * N];
+  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  int blk = blockIdx.x;
+  const int sub = blk % C::SUB;
+  blk /= C::SUB;
+  const int xt = blk % G::XT, iy = blk / G::XT;
+  const int mx = xt * kTile + sub * C::LB + b;
+  const size_t zstride = (size_t)G::XT * N * kTile;
+  const cx<T>* src = w + ((size_t)xt * N + iy) * kTile + sub * C::LB + b;
+  cx<T> v[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) v[0][e] = src[(size_t)(t + e * P) * zstride];
+  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  if (mx < G::H) {
+#pragma unroll
+    for (int e = 0; e < 8; e++) spec[((size_t)(t + e * P) * N + iy) * NH + mx] = v[0][e];
+  }
+}
+
+// x c2r of rows (y0, y0+1) of nz planes: Wn(FULL)[nz][XT][N][16] -> phys
+// [nz][N][N]; grid (N/2/RP, nz)
+template <typename T, int N>
+__global__ void __launch_bounds__((RowPairs<N>::THREADS))
+    kf_x_c2r(const cx<T>* __restrict__ w, T* __restrict__ phys, const cx<T>* __restrict__ tw) {
+  using G = Geo<N, true>;
+  using R = RowPairs<N>;
+  constexpr int P = G::P;
+  __shared__ cx<T> lds[R::RP * R::NPAD];
+  const int rp = threadIdx.x / P, t = threadIdx.x % P;
+  const int z = blockIdx.y, y0 = 2 * (blockIdx.x * R::RP + rp);
+  const cx<T>* wz = w + (size_t)z * G::XT * N * kTile;
+  auto at = [=](int y, int m) { return wz[((size_t)(m >> 4) * N + y) * kTile + (m & 15)]; };
+  cx<T> v[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++)
+    v[0][e] = c2r_pair_at<T, N, true>(
+        t + e * P, [&](int m) { return at(y0, m); }, [&](int m) { return at(y0 + 1, m); });
+  fft_lines<T, N, +1, 1>(v, t, lds + rp * R::NPAD,
+                         [=](int, int pos) { return R::pad(pos); }, tw);
+  T* row = phys + ((size_t)z * N + y0) * N;
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    row[t + e * P] = v[0][e].re;
+    row[N + t + e * P] = v[0][e].im;
+  }
+}
+
+// x r2c of rows (y0, y0+1): phys -> Wn(FULL), scaled; grid (N/2/RP, nz)
+template <typename T, int N>
+__global__ void __launch_bounds__((RowPairs<N>::THREADS))
+    kf_x_r2c(const T* __restrict__ phys, cx<T>* __restrict__ w, const cx<T>* __restrict__ tw,
+             T scale) {
+  using G = Geo<N, true>;
+  using R = RowPairs<N>;
+  constexpr int P = G::P;
+  __shared__ cx<T> lds[R::RP * R::NPAD];
+  const int rp = threadIdx.x / P, t = threadIdx.x % P;
+  const int z = blockIdx.y, y0 = 2 * (blockIdx.x * R::RP + rp);
+  const T* row = phys + ((size_t)z * N + y0) * N;
+  cx<T> v[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) v[0][e] = {row[t + e * P] * scale, row[N + t + e * P] * scale};
+  cx<T>* my = lds + rp * R::NPAD;
+  auto lidx = [=](int, int pos) { return R::pad(pos); };
+  fft_lines<T, N, -1, 1>(v, t, my, lidx, tw);
+#pragma unroll
+  for (int e = 0; e < 8; e++) my[lidx(0, t + e * P)] = v[0][e];
+  __syncthreads();
+  cx<T>* wz = w + (size_t)z * G::XT * N * kTile;
+  for (int m = t; m < G::XT * kTile; m += P) {
+    cx<T> A = {0, 0}, B = {0, 0};
+    if (m < G::H) r2c_untangle(my[lidx(0, m)], my[lidx(0, (N - m) & (N - 1))], A, B);
+    const size_t o = ((size_t)(m >> 4) * N) * kTile + (m & 15);
+    wz[o + (size_t)y0 * kTile] = A;
+    wz[o + (size_t)(y0 + 1) * kTile] = B;
+  }
+}
+
+}  // namespace fs

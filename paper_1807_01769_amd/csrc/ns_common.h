@@ -1,0 +1,197 @@
+// ns_common.h -- geometry of the dealiased spectral layout and the passes
+// shared by the 2D and 3D solvers.
+//
+// Spectral index conventions (domain [0, L)^d, k = (2 pi / L) m):
+//   full axes (ky, kz): FFT index i in [0, N), mode m = i (i <= N/2) or i - N;
+//   half axis (kx):     index = mode m in [0, N/2].
+// Dealiasing (2/3 rule, cube): a mode is kept iff 3|m_a| < N on every axis,
+// i.e. |m_a| <= K = floor((N-1)/3).  Kept full-axis modes are stored
+// compactly as j in [0, M), M = 2K+1 (j <= K: m = j; j > K: m = j - M).
+// Kept half-axis modes are m in [0, H), H = K+1, grouped in XT tiles of 16.
+//
+// The "FULL" geometry (K = N/2, M = N) describes undealiased transforms.
+//
+// Intermediate workspace arrays are tile-blocked so that every strided pass
+// reads and writes whole 16-element (128 B for complex64) rows:
+//   Wm[f][z][xt][j][16]  (compact index along y)
+//   Wn[f][z][xt][y][16]  (full index along y)
+// In 2D the z extent is 1.
+#pragma once
+#include "fft_core.h"
+
+namespace fs {
+
+constexpr int kTile = 16;
+
+template <int N, bool FULL>
+struct Geo {
+  static constexpr int K = FULL ? N / 2 : (N - 1) / 3;
+  static constexpr int M = FULL ? N : 2 * K + 1;
+  static constexpr int H = K + 1;
+  static constexpr int XT = (H + kTile - 1) / kTile;
+  static constexpr int P = N / 8;
+  // compact index -> FFT index, and back (-1 when the mode is not kept)
+  __host__ __device__ static constexpr int j2i(int j) { return j <= K ? j : j + (N - M); }
+  __host__ __device__ static constexpr int i2j(int i) {
+    return i <= K ? i : (i >= N - K ? i - (N - M) : -1);
+  }
+  // signed mode number of a kept compact index
+  __host__ __device__ static constexpr int jmode(int j) { return j <= K ? j : j - M; }
+};
+
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+// Lines per block of a strided (y or z) pass: at most 16 (one tile), at most
+// 1024 threads and at most 64 KiB of LDS.
+template <typename T, int N>
+struct Strided {
+  static constexpr int P = N / 8;
+  static constexpr int LB =
+      cmin(kTile, cmin(65536 / (N * (int)sizeof(cx<T>)), 1024 / P));
+  static constexpr int SUB = kTile / LB;
+  static constexpr int THREADS = LB * P;
+};
+
+// Row pairs per block of an x pass (a row pair is owned by P lanes).
+template <int N>
+struct RowPairs {
+  static constexpr int P = N / 8;
+  static constexpr int RP = cmax(1, cmin(64 / P, N / 2));
+  static constexpr int THREADS = RP * P;
+  static constexpr int NPAD = N + N / 8;  // LDS line stride, +1 slot per 8
+  __host__ __device__ static constexpr int pad(int pos) { return pos + (pos >> 3); }
+};
+
+// Parameters of a fused RK4 stage epilogue.
+template <typename T>
+struct StageArgs {
+  cx<T>* state;        // caller's spectral state (ABI layout)
+  cx<T>* acc;          // RK4 accumulator, compact blocked layout
+  cx<T>* tend;         // tendency output (ABI layout), tendency mode only
+  cx<T>* vband;        // stage input on the forcing-band cube
+  const T* alpha;      // forcing coefficient (device scalar)
+  const T* e1;         // exp(-nu dt k^2) per FFT index (one axis)
+  const T* eh1;        // exp(-nu dt k^2 / 2) per FFT index
+  const cx<T>* tw;     // twiddle table of the transform size
+  T kb;                // 2 pi / L
+  T dt;
+  int bw;              // half width of the forcing-band cube (modes)
+  int m2min, m2max;    // band: m2min <= |m|^2 <= m2max; m2max < 0 => off
+};
+
+enum StageMode : int { kModeTend = 0, kStage1 = 1, kStage2 = 2, kStage3 = 3, kStage4 = 4 };
+
+// Lawson IF-RK4 stage combination at one mode.  `u` is u_n, `a` the
+// accumulator, `nl` the tendency of this stage; returns the next stage input
+// (stage 4: u_{n+1}).  E = exp(-nu k^2 dt), Eh = exp(-nu k^2 dt/2).
+//   stage1: a = E u + dt/6 E k1          next = Eh (u + dt/2 k1)
+//   stage2: a += dt/3 Eh k2              next = Eh u + dt/2 k2
+//   stage3: a += dt/3 Eh k3              next = E u + dt Eh k3
+//   stage4: u_{n+1} = a + dt/6 k4
+template <int MODE, typename T>
+__device__ __forceinline__ cx<T> rk4_combine(cx<T> u, cx<T>& a, cx<T> nl, T E, T Eh, T dt) {
+  const T d2 = dt * (T)0.5, d3 = dt / (T)3, d6 = dt / (T)6;
+  if constexpr (MODE == kStage1) {
+    a = cscale(u, E) + cscale(nl, d6 * E);
+    return cscale(u + cscale(nl, d2), Eh);
+  } else if constexpr (MODE == kStage2) {
+    a = a + cscale(nl, d3 * Eh);
+    return cscale(u, Eh) + cscale(nl, d2);
+  } else if constexpr (MODE == kStage3) {
+    a = a + cscale(nl, d3 * Eh);
+    return cscale(u, E) + cscale(nl, dt * Eh);
+  } else {
+    return a + cscale(nl, d6);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Strided passes along y: blocks of [XT][M][16] <-> [XT][N][16].
+// Grid: nblk * XT * SUB blocks, nblk = fields * z extent.
+// ---------------------------------------------------------------------------
+template <typename T, int N, bool FULL>
+__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+    k_y_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+            const cx<T>* __restrict__ tw) {
+  using G = Geo<N, FULL>;
+  using C = Strided<T, N>;
+  __shared__ cx<T> lds[C::LB * N];
+  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  int blk = blockIdx.x;
+  const int sub = blk % C::SUB;
+  blk /= C::SUB;
+  const size_t tile = (size_t)blk;  // = (field*nz + z)*XT + xt
+  const cx<T>* src = in + tile * G::M * kTile + sub * C::LB + b;
+  cx<T> v[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int j = G::i2j(t + e * G::P);
+    v[0][e] = j >= 0 ? src[j * kTile] : cx<T>{0, 0};
+  }
+  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  cx<T>* dst = out + tile * N * kTile + sub * C::LB + b;
+#pragma unroll
+  for (int e = 0; e < 8; e++) dst[(t + e * G::P) * kTile] = v[0][e];
+}
+
+template <typename T, int N, bool FULL>
+__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+    k_y_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+            const cx<T>* __restrict__ tw) {
+  using G = Geo<N, FULL>;
+  using C = Strided<T, N>;
+  __shared__ cx<T> lds[C::LB * N];
+  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  int blk = blockIdx.x;
+  const int sub = blk % C::SUB;
+  blk /= C::SUB;
+  const size_t tile = (size_t)blk;
+  const cx<T>* src = in + tile * N * kTile + sub * C::LB + b;
+  cx<T> v[1][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) v[0][e] = src[(t + e * G::P) * kTile];
+  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  cx<T>* dst = out + tile * G::M * kTile + sub * C::LB + b;
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int j = G::i2j(t + e * G::P);
+    if (j >= 0) dst[j * kTile] = v[0][e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Real-transform helpers for the x passes.
+// Two real lines a(x), b(x) travel as one complex line a + i b:
+//   inverse: Z[k] = A[k] + i B[k], with A[N-k] = conj A[k] (k > N/2);
+//            the imaginary parts of the self-conjugate A[0], A[N/2] are
+//            dropped (the real part of the inverse of the Hermitian
+//            completion, as C2R defines);
+//   forward: A[k] = (Z[k] + conj Z[N-k]) / 2,  B[k] = (Z[k] - conj Z[N-k]) / 2i.
+// ---------------------------------------------------------------------------
+template <typename T, int N, bool FULL, class FA, class FB>
+__device__ __forceinline__ cx<T> c2r_pair_at(int k, FA fa, FB fb) {
+  using G = Geo<N, FULL>;
+  if (k <= G::K) {
+    cx<T> A = fa(k), B = fb(k);
+    if (k == 0 || (FULL && k == N / 2)) {
+      A.im = 0;
+      B.im = 0;
+    }
+    return {A.re - B.im, A.im + B.re};
+  } else if (k >= N - G::K) {
+    const int m = N - k;
+    cx<T> A = fa(m), B = fb(m);
+    return {A.re + B.im, B.re - A.im};
+  }
+  return {0, 0};
+}
+
+template <typename T>
+__device__ __forceinline__ void r2c_untangle(cx<T> zk, cx<T> zn, cx<T>& A, cx<T>& B) {
+  const T h = (T)0.5;
+  A = {(zk.re + zn.re) * h, (zk.im - zn.im) * h};
+  B = {(zk.im + zn.im) * h, (zn.re - zk.re) * h};
+}
+
+}  // namespace fs

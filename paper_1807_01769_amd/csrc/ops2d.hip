@@ -1,0 +1,139 @@
+// ops2d.hip -- launch sequences of the 2D solver for every supported size.
+#include <cmath>
+
+#include "fs_internal.h"
+#include "ns2d_kernels.h"
+#include "ns3d_kernels.h"
+
+namespace fs {
+namespace {
+
+template <typename T>
+StageArgs<T> stage_args2(Plan* p, void* state, void* tend) {
+  StageArgs<T> a;
+  a.state = (cx<T>*)state;
+  a.acc = (cx<T>*)p->acc;
+  a.tend = (cx<T>*)tend;
+  a.vband = nullptr;
+  a.alpha = nullptr;
+  a.e1 = (const T*)p->e1;
+  a.eh1 = (const T*)p->eh1;
+  a.tw = (const cx<T>*)p->tw;
+  a.kb = (T)(2.0 * M_PI / p->L);
+  a.dt = (T)p->dt;
+  a.bw = 0;
+  a.m2min = 0;
+  a.m2max = -1;
+  return a;
+}
+
+template <typename T, int N>
+struct L2 {
+  using G = Geo<N, false>;
+  using GF = Geo<N, true>;
+  using C = Strided<T, N>;
+  using R = RowPairs<N>;
+  static cx<T>* A(Plan* p) { return (cx<T>*)p->bufA; }
+  static cx<T>* B(Plan* p) { return (cx<T>*)p->bufB; }
+  static const cx<T>* TW(Plan* p) { return (const cx<T>*)p->tw; }
+
+  static void p1(Plan* p, const void* state) {
+    p->begin(KID_P1);
+    hipLaunchKernelGGL((k2_p1<T, N>), dim3(G::XT * C::SUB), dim3(C::THREADS), 0, p->launch,
+                       (const cx<T>*)state, A(p), stage_args2<T>(p, (void*)state, nullptr));
+    launched(p, "k2_p1");
+    p->end(KID_P1);
+  }
+  static void x(Plan* p) {
+    p->begin(KID_X);
+    hipLaunchKernelGGL((k2_x<T, N>), dim3(N / 2 / R::RP), dim3(R::THREADS), 0, p->launch,
+                       (const cx<T>*)A(p), B(p), TW(p), (T)(1.0 / ((double)N * N)));
+    launched(p, "k2_x");
+    p->end(KID_X);
+  }
+  template <int MODE>
+  static void yk(Plan* p, void* state, void* tend, int do_p1) {
+    p->begin(KID_Z);
+    hipLaunchKernelGGL((k2_y<T, N, MODE>), dim3(G::XT * C::SUB), dim3(C::THREADS), 0, p->launch,
+                       (const cx<T>*)B(p), A(p), stage_args2<T>(p, state, tend), do_p1);
+    launched(p, "k2_y");
+    p->end(KID_Z);
+  }
+  static void stage(Plan* p, void* state, int mode, int do_p1) {
+    x(p);
+    switch (mode) {
+      case 1: yk<kStage1>(p, state, nullptr, 1); break;
+      case 2: yk<kStage2>(p, state, nullptr, 1); break;
+      case 3: yk<kStage3>(p, state, nullptr, 1); break;
+      default: yk<kStage4>(p, state, nullptr, do_p1); break;
+    }
+  }
+  static void tendency(Plan* p, const void* state, void* out) {
+    launch_fill<T>(p, out, (size_t)N * (N / 2 + 1));
+    p1(p, state);
+    x(p);
+    yk<kModeTend>(p, (void*)state, out, 0);
+  }
+  static void fft_inv(Plan* p, const void* spec, void* phys) {
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((k2f_y_inv<T, N>), dim3(GF::XT * C::SUB), dim3(C::THREADS), 0, p->launch,
+                       (const cx<T>*)spec, B(p), TW(p));
+    launched(p, "k2f_y_inv");
+    p->end(KID_FFT);
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((kf_x_c2r<T, N>), dim3(N / 2 / R::RP, 1), dim3(R::THREADS), 0, p->launch,
+                       (const cx<T>*)B(p), (T*)phys, TW(p));
+    launched(p, "kf_x_c2r");
+    p->end(KID_FFT);
+  }
+  static void fft_fwd(Plan* p, const void* phys, void* spec) {
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((kf_x_r2c<T, N>), dim3(N / 2 / R::RP, 1), dim3(R::THREADS), 0, p->launch,
+                       (const T*)phys, B(p), TW(p), (T)(1.0 / ((double)N * N)));
+    launched(p, "kf_x_r2c");
+    p->end(KID_FFT);
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((k2f_y_fwd<T, N>), dim3(GF::XT * C::SUB), dim3(C::THREADS), 0, p->launch,
+                       (const cx<T>*)B(p), (cx<T>*)spec, TW(p));
+    launched(p, "k2f_y_fwd");
+    p->end(KID_FFT);
+  }
+  static Ops ops() {
+    Ops o{};
+    o.p1 = p1;
+    o.stage = stage;
+    o.tendency = tendency;
+    o.fft_fwd = fft_fwd;
+    o.fft_inv = fft_inv;
+    o.alpha = nullptr;
+    o.diag = launch_diag<T>;
+    const size_t wn3 = (size_t)3 * G::XT * N * kTile;
+    const size_t wn2 = (size_t)2 * G::XT * N * kTile;
+    const size_t wfull = (size_t)GF::XT * N * kTile;
+    o.elems_a = wn3 > wfull ? wn3 : wfull;
+    o.elems_b = wn2 > wfull ? wn2 : wfull;
+    o.elems_acc = (size_t)G::XT * G::M * kTile;
+    return o;
+  }
+};
+
+}  // namespace
+
+template <typename T>
+Ops make_ops2(int n) {
+  switch (n) {
+    case 16: return L2<T, 16>::ops();
+    case 32: return L2<T, 32>::ops();
+    case 64: return L2<T, 64>::ops();
+    case 128: return L2<T, 128>::ops();
+    case 256: return L2<T, 256>::ops();
+    case 512: return L2<T, 512>::ops();
+    case 1024: return L2<T, 1024>::ops();
+    default: return Ops{};
+  }
+}
+
+template Ops make_ops2<float>(int);
+template Ops make_ops2<double>(int);
+
+}  // namespace fs

@@ -1,0 +1,169 @@
+// ops3d.hip -- launch sequences of the 3D solver for every supported size.
+#include <cmath>
+
+#include "fs_internal.h"
+#include "ns3d_kernels.h"
+
+namespace fs {
+namespace {
+
+template <typename T>
+StageArgs<T> stage_args(Plan* p, void* state, void* tend) {
+  StageArgs<T> a;
+  a.state = (cx<T>*)state;
+  a.acc = (cx<T>*)p->acc;
+  a.tend = (cx<T>*)tend;
+  a.vband = (cx<T>*)p->vband;
+  a.alpha = (const T*)p->alpha;
+  a.e1 = (const T*)p->e1;
+  a.eh1 = (const T*)p->eh1;
+  a.tw = (const cx<T>*)p->tw;
+  a.kb = (T)(2.0 * M_PI / p->L);
+  a.dt = (T)p->dt;
+  a.bw = p->bw;
+  a.m2min = p->m2min;
+  a.m2max = p->m2max;
+  return a;
+}
+
+template <typename T, int N>
+struct L3 {
+  using G = Geo<N, false>;
+  using GF = Geo<N, true>;
+  using C = Strided<T, N>;
+  using R = RowPairs<N>;
+  static cx<T>* A(Plan* p) { return (cx<T>*)p->bufA; }
+  static cx<T>* B(Plan* p) { return (cx<T>*)p->bufB; }
+  static const cx<T>* TW(Plan* p) { return (const cx<T>*)p->tw; }
+
+  static void p1(Plan* p, const void* state) {
+    p->begin(KID_P1);
+    hipLaunchKernelGGL((k3_p1<T, N>), dim3(G::M * G::XT * C::SUB), dim3(C::THREADS), 0,
+                       p->launch, (const cx<T>*)state, A(p),
+                       stage_args<T>(p, (void*)state, nullptr));
+    launched(p, "k3_p1");
+    p->end(KID_P1);
+  }
+  static void yinv(Plan* p) {
+    p->begin(KID_YINV);
+    hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(6 * N * G::XT * C::SUB), dim3(C::THREADS),
+                       0, p->launch, (const cx<T>*)A(p), B(p), TW(p));
+    launched(p, "k_y_inv");
+    p->end(KID_YINV);
+  }
+  static void x(Plan* p) {
+    p->begin(KID_X);
+    hipLaunchKernelGGL((k3_x<T, N>), dim3(N / 2 / R::RP, N), dim3(R::THREADS), 0, p->launch,
+                       (const cx<T>*)B(p), A(p), TW(p), (T)(1.0 / ((double)N * N * N)));
+    launched(p, "k3_x");
+    p->end(KID_X);
+  }
+  static void yfwd(Plan* p) {
+    p->begin(KID_YFWD);
+    hipLaunchKernelGGL((k_y_fwd<T, N, false>), dim3(3 * N * G::XT * C::SUB), dim3(C::THREADS),
+                       0, p->launch, (const cx<T>*)A(p), B(p), TW(p));
+    launched(p, "k_y_fwd");
+    p->end(KID_YFWD);
+  }
+  template <int MODE>
+  static void zk(Plan* p, void* state, void* tend, int do_p1) {
+    p->begin(KID_Z);
+    hipLaunchKernelGGL((k3_z<T, N, MODE>), dim3(G::M * G::XT * C::SUB), dim3(C::THREADS), 0,
+                       p->launch, (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend),
+                       do_p1);
+    launched(p, "k3_z");
+    p->end(KID_Z);
+  }
+  static void stage(Plan* p, void* state, int mode, int do_p1) {
+    yinv(p);
+    x(p);
+    yfwd(p);
+    switch (mode) {
+      case 1: zk<kStage1>(p, state, nullptr, 1); break;
+      case 2: zk<kStage2>(p, state, nullptr, 1); break;
+      case 3: zk<kStage3>(p, state, nullptr, 1); break;
+      default: zk<kStage4>(p, state, nullptr, do_p1); break;
+    }
+  }
+  static void tendency(Plan* p, const void* state, void* out) {
+    launch_fill<T>(p, out, (size_t)3 * N * N * (N / 2 + 1));
+    if (p->m2max >= 0) launch_alpha<T>(p, state);
+    p1(p, state);
+    yinv(p);
+    x(p);
+    yfwd(p);
+    zk<kModeTend>(p, (void*)state, out, 0);
+  }
+  static void fft_inv(Plan* p, const void* spec, void* phys) {
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((k3f_z_inv<T, N>), dim3(N * GF::XT * C::SUB), dim3(C::THREADS), 0,
+                       p->launch, (const cx<T>*)spec, A(p), TW(p));
+    launched(p, "k3f_z_inv");
+    p->end(KID_FFT);
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(N * GF::XT * C::SUB), dim3(C::THREADS), 0,
+                       p->launch, (const cx<T>*)A(p), B(p), TW(p));
+    launched(p, "k_y_inv full");
+    p->end(KID_FFT);
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((kf_x_c2r<T, N>), dim3(N / 2 / R::RP, N), dim3(R::THREADS), 0, p->launch,
+                       (const cx<T>*)B(p), (T*)phys, TW(p));
+    launched(p, "kf_x_c2r");
+    p->end(KID_FFT);
+  }
+  static void fft_fwd(Plan* p, const void* phys, void* spec) {
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((kf_x_r2c<T, N>), dim3(N / 2 / R::RP, N), dim3(R::THREADS), 0, p->launch,
+                       (const T*)phys, B(p), TW(p), (T)(1.0 / ((double)N * N * N)));
+    launched(p, "kf_x_r2c");
+    p->end(KID_FFT);
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((k_y_fwd<T, N, true>), dim3(N * GF::XT * C::SUB), dim3(C::THREADS), 0,
+                       p->launch, (const cx<T>*)B(p), A(p), TW(p));
+    launched(p, "k_y_fwd full");
+    p->end(KID_FFT);
+    p->begin(KID_FFT);
+    hipLaunchKernelGGL((k3f_z_fwd<T, N>), dim3(N * GF::XT * C::SUB), dim3(C::THREADS), 0,
+                       p->launch, (const cx<T>*)A(p), (cx<T>*)spec, TW(p));
+    launched(p, "k3f_z_fwd");
+    p->end(KID_FFT);
+  }
+  static Ops ops() {
+    Ops o{};
+    o.p1 = p1;
+    o.stage = stage;
+    o.tendency = tendency;
+    o.fft_fwd = fft_fwd;
+    o.fft_inv = fft_inv;
+    o.alpha = launch_alpha<T>;
+    o.diag = launch_diag<T>;
+    const size_t wm6 = (size_t)6 * N * G::XT * G::M * kTile;
+    const size_t wn6 = (size_t)6 * N * G::XT * N * kTile;
+    const size_t wfull = (size_t)N * GF::XT * N * kTile;
+    o.elems_a = wm6 > wfull ? wm6 : wfull;
+    o.elems_b = wn6 > wfull ? wn6 : wfull;
+    o.elems_acc = (size_t)3 * G::XT * G::M * G::M * kTile;
+    return o;
+  }
+};
+
+}  // namespace
+
+template <typename T>
+Ops make_ops3(int n) {
+  switch (n) {
+    case 16: return L3<T, 16>::ops();
+    case 32: return L3<T, 32>::ops();
+    case 64: return L3<T, 64>::ops();
+    case 128: return L3<T, 128>::ops();
+    case 256: return L3<T, 256>::ops();
+    case 512: return L3<T, 512>::ops();
+    case 1024: return L3<T, 1024>::ops();
+    default: return Ops{};
+  }
+}
+
+template Ops make_ops3<float>(int);
+template Ops make_ops3<double>(int);
+
+}  // namespace fs

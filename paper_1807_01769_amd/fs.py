@@ -1,0 +1,214 @@
+"""ctypes binding of libfs.so (include/fs.h): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; torch supplies device
+memory and the stream.  Importing this module fails loudly when the library
+has not been built, and creating a plan fails when no HIP device is present.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfs.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1807_01769_amd/build.py")
+
+lib = C.CDLL(LIB_PATH)
+
+FS_OK, FS_E_INVALID, FS_E_UNSUPPORTED, FS_E_NOMEM, FS_E_DEVICE, FS_E_NONFINITE = 0, -1, -2, -3, -4, -5
+FS_F32, FS_F64 = 0, 1
+FS_NO_GRAPH, FS_PROFILE = 0x1, 0x2
+KERNEL_NAMES = ["p1", "y_inverse", "x_c2r_product_r2c", "y_forward", "z_stage",
+                "forcing_alpha", "fill", "fft_only", "diagnostics"]
+
+
+class Opts(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int),
+        ("precision", C.c_int),
+        ("stream", C.c_void_p),
+        ("forcing_power", C.c_double),
+        ("forcing_kmin", C.c_double),
+        ("forcing_kmax", C.c_double),
+        ("flags", C.c_uint),
+    ]
+
+
+_vp, _i, _d = C.c_void_p, C.c_int, C.c_double
+lib.fs_plan_opts_default.argtypes = [C.POINTER(Opts)]
+lib.fs_plan_opts_default.restype = None
+lib.fs_plan_create.argtypes = [C.POINTER(_vp), _i, _d, _d, _d, C.POINTER(Opts)]
+lib.fs_plan_destroy.argtypes = [_vp]
+lib.fs_plan_set_stream.argtypes = [_vp, _vp]
+lib.fs_state_elems.argtypes = [_vp, C.POINTER(C.c_size_t)]
+lib.fs_workspace_bytes.argtypes = [_vp, C.POINTER(C.c_size_t)]
+lib.fs_spectrum_bins.argtypes = [_vp, C.POINTER(_i)]
+lib.fs_fft_forward.argtypes = [_vp, _vp, _vp]
+lib.fs_fft_inverse.argtypes = [_vp, _vp, _vp]
+lib.fs_tendency.argtypes = [_vp, _vp, _vp]
+lib.fs_step_rk4.argtypes = [_vp, _vp, _i]
+lib.fs_energy_spectrum.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
+lib.fs_profile_read.argtypes = [_vp, C.POINTER(_d), C.POINTER(C.c_long), C.POINTER(C.c_char_p), _i]
+lib.fs_status_str.argtypes = [_i]
+lib.fs_status_str.restype = C.c_char_p
+lib.fs_last_error.argtypes = []
+lib.fs_last_error.restype = C.c_char_p
+for _f in ("fs_plan_create", "fs_plan_destroy", "fs_plan_set_stream", "fs_state_elems",
+           "fs_workspace_bytes", "fs_spectrum_bins", "fs_fft_forward", "fs_fft_inverse",
+           "fs_tendency", "fs_step_rk4", "fs_energy_spectrum", "fs_profile_read"):
+    getattr(lib, _f).restype = _i
+
+
+class FsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.fs_last_error().decode()
+        super().__init__(f"{where}: {lib.fs_status_str(status).decode()} ({msg})")
+
+
+def _check(status: int, where: str) -> None:
+    if status != FS_OK:
+        raise FsError(status, where)
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Plan:
+    """One solver configuration: grid n, box length L, viscosity nu, step dt."""
+
+    def __init__(self, n: int, L: float = 2 * math.pi, nu: float = 0.0, dt: float = 1e-3,
+                 ndim: int = 3, precision: str = "f32", stream=None, forcing_power: float = 0.0,
+                 forcing_kmin: float = 2.0, forcing_kmax: float = 3.0, graphs: bool = True,
+                 profile: bool = False):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1807_01769_amd.fs needs a HIP device")
+        self.n, self.L, self.nu, self.dt, self.ndim = int(n), float(L), float(nu), float(dt), int(ndim)
+        self.precision = precision
+        self.real_dtype = {"f32": torch.float32, "f64": torch.float64}[precision]
+        self.complex_dtype = {"f32": torch.complex64, "f64": torch.complex128}[precision]
+        self.stream = stream
+        o = Opts()
+        lib.fs_plan_opts_default(C.byref(o))
+        o.ndim = self.ndim
+        o.precision = FS_F32 if precision == "f32" else FS_F64
+        o.stream = _stream_ptr(stream)
+        o.forcing_power = float(forcing_power)
+        o.forcing_kmin = float(forcing_kmin)
+        o.forcing_kmax = float(forcing_kmax)
+        o.flags = (0 if graphs else FS_NO_GRAPH) | (FS_PROFILE if profile else 0)
+        h = _vp()
+        _check(lib.fs_plan_create(C.byref(h), self.n, self.L, self.nu, self.dt, C.byref(o)),
+               "fs_plan_create")
+        self._h = h
+
+    # -- shapes ------------------------------------------------------------
+    @property
+    def state_shape(self):
+        n = self.n
+        return (3, n, n, n // 2 + 1) if self.ndim == 3 else (n, n // 2 + 1)
+
+    @property
+    def spec_shape(self):
+        n = self.n
+        return (n,) * (self.ndim - 1) + (n // 2 + 1,)
+
+    @property
+    def phys_shape(self):
+        return (self.n,) * self.ndim
+
+    def workspace_bytes(self) -> int:
+        b = C.c_size_t()
+        _check(lib.fs_workspace_bytes(self._h, C.byref(b)), "fs_workspace_bytes")
+        return int(b.value)
+
+    def spectrum_bins(self) -> int:
+        b = _i()
+        _check(lib.fs_spectrum_bins(self._h, C.byref(b)), "fs_spectrum_bins")
+        return int(b.value)
+
+    def _arg(self, t: torch.Tensor, shape, dtype, name: str) -> int:
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t.data_ptr()
+
+    def new_state(self) -> torch.Tensor:
+        return torch.zeros(self.state_shape, dtype=self.complex_dtype, device="cuda")
+
+    # -- entry points ------------------------------------------------------
+    def fft_forward(self, phys: torch.Tensor, spec: torch.Tensor | None = None) -> torch.Tensor:
+        if spec is None:
+            spec = torch.empty(self.spec_shape, dtype=self.complex_dtype, device=phys.device)
+        _check(lib.fs_fft_forward(self._h, self._arg(phys, self.phys_shape, self.real_dtype, "phys"),
+                                  self._arg(spec, self.spec_shape, self.complex_dtype, "spec")),
+               "fs_fft_forward")
+        return spec
+
+    def fft_inverse(self, spec: torch.Tensor, phys: torch.Tensor | None = None) -> torch.Tensor:
+        if phys is None:
+            phys = torch.empty(self.phys_shape, dtype=self.real_dtype, device=spec.device)
+        _check(lib.fs_fft_inverse(self._h, self._arg(spec, self.spec_shape, self.complex_dtype, "spec"),
+                                  self._arg(phys, self.phys_shape, self.real_dtype, "phys")),
+               "fs_fft_inverse")
+        return phys
+
+    def tendency(self, state: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.state_shape, dtype=self.complex_dtype, device=state.device)
+        _check(lib.fs_tendency(self._h, self._arg(state, self.state_shape, self.complex_dtype, "state"),
+                               self._arg(out, self.state_shape, self.complex_dtype, "out")),
+               "fs_tendency")
+        return out
+
+    def step(self, state: torch.Tensor, nsteps: int = 1) -> torch.Tensor:
+        _check(lib.fs_step_rk4(self._h, self._arg(state, self.state_shape, self.complex_dtype, "state"),
+                               int(nsteps)), "fs_step_rk4")
+        return state
+
+    def energy_spectrum(self, state: torch.Tensor, nbins: int | None = None):
+        """Returns device tensors (spectrum[nbins], energy[1], enstrophy[1]) in float64."""
+        nbins = self.spectrum_bins() if nbins is None else int(nbins)
+        spec = torch.empty(nbins, dtype=torch.float64, device=state.device)
+        ez = torch.empty(2, dtype=torch.float64, device=state.device)
+        _check(lib.fs_energy_spectrum(self._h, self._arg(state, self.state_shape, self.complex_dtype, "state"),
+                                      spec.data_ptr(), nbins, ez.data_ptr(), ez.data_ptr() + 8),
+               "fs_energy_spectrum")
+        return spec, ez[0:1], ez[1:2]
+
+    def profile_read(self) -> dict:
+        """Per-kernel (total ms, launches) since the previous read (profile=True plans)."""
+        nk = len(KERNEL_NAMES)
+        ms = (_d * nk)()
+        cnt = (C.c_long * nk)()
+        _check(lib.fs_profile_read(self._h, ms, cnt, None, nk), "fs_profile_read")
+        return {KERNEL_NAMES[k]: (ms[k], cnt[k]) for k in range(nk) if cnt[k] > 0}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.fs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

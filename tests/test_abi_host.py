@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/fs.h declares, and rejects bad arguments before touching a
+device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fs.h")
+LIB = os.path.join(ROOT, "paper_1807_01769_amd", "libfs.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fs_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libfs.so is not built (run paper_1807_01769_amd/build.py)")
+    return C.CDLL(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+class Opts(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("precision", C.c_int), ("stream", C.c_void_p),
+                ("forcing_power", C.c_double), ("forcing_kmin", C.c_double),
+                ("forcing_kmax", C.c_double), ("flags", C.c_uint)]
+
+
+def _create(lib, n, L, nu, dt, **kw):
+    lib.fs_plan_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_double, C.c_double,
+                                   C.c_double, C.POINTER(Opts)]
+    lib.fs_plan_opts_default.argtypes = [C.POINTER(Opts)]
+    o = Opts()
+    lib.fs_plan_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = C.c_void_p()
+    st = lib.fs_plan_create(C.byref(h), n, L, nu, dt, C.byref(o))
+    return st, h
+
+
+@pytest.mark.parametrize("args,kw,expect", [
+    ((0, 6.28, 0.1, 0.01), {}, -1),
+    ((-8, 6.28, 0.1, 0.01), {}, -1),
+    ((48, 6.28, 0.1, 0.01), {}, -2),
+    ((8, 6.28, 0.1, 0.01), {}, -2),
+    ((2048, 6.28, 0.1, 0.01), {}, -2),
+    ((64, 0.0, 0.1, 0.01), {}, -1),
+    ((64, float("nan"), 0.1, 0.01), {}, -1),
+    ((64, 6.28, -1.0, 0.01), {}, -1),
+    ((64, 6.28, 0.1, 0.0), {}, -1),
+    ((64, 6.28, 0.1, float("inf")), {}, -1),
+    ((64, 6.28, 0.1, 0.01), {"ndim": 4}, -1),
+    ((64, 6.28, 0.1, 0.01), {"precision": 7}, -1),
+    ((64, 6.28, 0.1, 0.01), {"flags": 0x100}, -1),
+    ((64, 6.28, 0.1, 0.01), {"forcing_power": -1.0}, -1),
+    ((64, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "ndim": 2}, -2),
+    ((64, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 3.0, "forcing_kmax": 2.0}, -1),
+    ((16, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 2.0, "forcing_kmax": 9.0}, -1),
+    ((64, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 1.1, "forcing_kmax": 1.2}, -1),
+])
+def test_create_validates_before_device(lib, args, kw, expect):
+    st, h = _create(lib, *args, **kw)
+    assert st == expect
+    assert not h.value
+    lib.fs_last_error.restype = C.c_char_p
+    assert lib.fs_last_error()
+
+
+def test_null_arguments(lib):
+    lib.fs_plan_create.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_double, C.c_void_p]
+    assert lib.fs_plan_create(None, 64, 6.28, 0.1, 0.01, None) == -1
+    for fn, nargs in [("fs_step_rk4", 3), ("fs_tendency", 3), ("fs_fft_forward", 3),
+                      ("fs_fft_inverse", 3), ("fs_energy_spectrum", 6), ("fs_plan_set_stream", 2),
+                      ("fs_profile_read", 5)]:
+        f = getattr(lib, fn)
+        f.argtypes = [C.c_void_p] * nargs
+        assert f(*([None] * nargs)) == -1, fn
+    lib.fs_plan_destroy.argtypes = [C.c_void_p]
+    assert lib.fs_plan_destroy(None) == 0
+
+
+def test_status_strings(lib):
+    lib.fs_status_str.restype = C.c_char_p
+    assert lib.fs_status_str(0) == b"FS_OK"
+    assert lib.fs_status_str(-2) == b"FS_E_UNSUPPORTED"
+    assert lib.fs_status_str(-99) == b"FS_E_UNKNOWN"
+
+
+def test_binding_imports_and_needs_device():
+    from paper_1807_01769_amd import fs
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("device present")
+    with pytest.raises(RuntimeError):
+        fs.Plan(16)
