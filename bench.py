@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark: one RK4 step of 3D forced isotropic turbulence at 512^3 in FP32.
+
+Workload (synthetic, seeded): random-phase solenoidal velocity with
+E(k) ~ k^4 exp(-2 (k/4)^2), unit energy (seed 1); nu = 2e-4, dt = 1e-3;
+constant-power forcing P = 5e-3 on 2 <= |k| <= 3; 2/3-rule dealiasing.
+
+Prints ONE JSON line on stdout.  `value` is nanoseconds per grid point per
+RK4 step (lower is better).  Inputs are resident in device memory before the
+timed region.  Every kernel of the timed steps is bracketed by HIP events on
+the stream it runs on; the per-kernel averages give the roofline figures of
+the dominant kernel.  The FP64 CPU oracle is timed on a bounded sample on the
+host's cores for reference.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RK4 step ns/gridpoint at 512³ FP32, % HBM roofline; closure-LES vs DNS speedup"
+HBM_PEAK_GBS = 8000.0
+NU, DT, POWER, KMIN, KMAX, SEED = 2e-4, 1e-3, 5e-3, 2.0, 3.0, 1
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3d_512.json")
+KERNEL_SOURCES = ["fft_core.h", "ns_common.h", "ns3d_kernels.h", "ops3d.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1807_01769_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n: int, steps: int, elem: int = 8) -> dict:
+    """Bytes each kernel class must move in `steps` steps if only kept modes
+    travel (the dealias-pruned model): per field, Us = M*M*H (state), Uzm =
+    N*M*H (after the z pass), Uzn = N*N*H (after the y pass) complex values,
+    with K = (N-1)//3, M = 2K+1, H = K+1."""
+    K = (n - 1) // 3
+    M, H = 2 * K + 1, K + 1
+    Us, Uzm, Uzn = M * M * H * elem, n * M * H * elem, n * n * H * elem
+    launches = {"y_inverse": 4 * steps, "x_c2r_product_r2c": 4 * steps,
+                "y_forward": 4 * steps, "z_stage": 4 * steps, "p1": 1}
+    total = {
+        "y_inverse": 4 * steps * (6 * Uzm + 6 * Uzn),
+        "x_c2r_product_r2c": 4 * steps * (6 * Uzn + 3 * Uzn),
+        "y_forward": 4 * steps * (3 * Uzn + 3 * Uzm),
+        # read the products, write the next stage's six fields (not after the
+        # last stage), RK4 state/accumulator traffic 30 Us per step
+        "z_stage": 4 * steps * 3 * Uzm + (4 * steps - 1) * 6 * Uzm + steps * 30 * Us,
+        "p1": 3 * Us + 6 * Uzm,
+    }
+    return {k: (total[k], launches[k]) for k in total}
+
+
+def cpu_baseline(seconds: float, n: int = 128) -> dict:
+    import numpy as np
+    import oracle
+    from paper_1807_01769_amd import inputs as I
+
+    u = I.random_solenoidal_3d(n, seed=SEED).astype(np.complex64).astype(np.complex128)
+    cores = oracle.get_threads()
+    steps, t = 0, 0.0
+    while t < seconds:
+        t0 = time.perf_counter()
+        u = oracle.step3d(u, NU, DT, 1, power=POWER, kf_min=KMIN, kf_max=KMAX)
+        t += time.perf_counter() - t0
+        steps += 1
+    ns = t / steps / n ** 3 * 1e9
+    return {"value": ns, "unit": "ns/gridpoint/step", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} FP64 RK4 step(s) of the same forced-turbulence recipe at {n}^3 "
+                      f"({t:.1f} s); per-point FFT work at {n}^3 is log2({n})/9 of 512^3's"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--graphs", action="store_true",
+                    help="time graph-launched steps (no per-kernel events)")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world})", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1807_01769_amd import fs, inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 1
+    n = args.n
+    dev = torch.device("cuda:0")
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * 2 ** 30) // 4
+        a = torch.ones(nb, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nb * 4} bytes read, {nb * 4} bytes written")
+        del a, b
+    log(f"generating the {n}^3 initial field")
+    t0 = time.perf_counter()
+    u0 = I.random_solenoidal_3d(n, seed=SEED, dtype=np.complex64)
+    state = torch.from_numpy(u0).to(dev)
+    del u0
+    log(f"initial field ready ({time.perf_counter() - t0:.1f} s)")
+    plan = fs.Plan(n, nu=NU, dt=DT, ndim=3, precision="f32", forcing_power=POWER,
+                   forcing_kmin=KMIN, forcing_kmax=KMAX, profile=not args.graphs)
+    plan.step(state, args.warmup)
+    torch.cuda.synchronize()
+    if not args.graphs:
+        plan.profile_read()
+    log(f"warmup done ({args.warmup} steps)")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(state, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+
+    _, e, z = plan.energy_spectrum(state)
+    energy, enstrophy = float(e.cpu()), float(z.cpu())
+    if not (math.isfinite(energy) and math.isfinite(enstrophy)):
+        print("non-finite state after the timed steps", file=sys.stderr)
+        return 1
+
+    kernels, roofline = {}, None
+    if not args.graphs:
+        prof = plan.profile_read()
+        alg = algorithmic_bytes(n, args.steps)
+        for name, (ms, cnt) in prof.items():
+            rec = {"ms_total": ms, "launches": cnt, "ms_avg": ms / cnt}
+            if name in alg and alg[name][1] == cnt:
+                tot, _ = alg[name]
+                rec["alg_bytes_per_launch"] = tot / cnt
+                rec["alg_GBps"] = tot / cnt / (ms / cnt * 1e-3) / 1e9
+            kernels[name] = rec
+        dom = max((k for k in kernels if "alg_GBps" in kernels[k]), key=lambda k: kernels[k]["ms_total"])
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            with open(TRAFFIC_FILE) as fh:
+                tr = json.load(fh)
+            if tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
+                traffic = tr.get("bytes_per_launch", {}).get(dom)
+        ach = kernels[dom]["alg_GBps"]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "alg_bytes_per_launch": kernels[dom]["alg_bytes_per_launch"],
+                    "ms_avg": kernels[dom]["ms_avg"]}
+        step_alg = sum(v[0] for k, v in alg.items() if k != "p1") / args.steps
+        roofline["step_alg_GBps"] = round(step_alg / (ms_per_step * 1e-3) / 1e9, 1)
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the FP64 CPU oracle on a bounded sample")
+        cpu = cpu_baseline(args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": ms_per_step * 1e6 / n ** 3,
+        "unit": "ns/gridpoint/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"3D forced isotropic turbulence {n}^3, velocity form, FP32, "
+                               "nu=2e-4, dt=1e-3, random solenoidal E(k)~k^4 exp(-2(k/4)^2) unit "
+                               "energy seed 1, constant-power forcing 5e-3 on 2<=|k|<=3, "
+                               "2/3 dealiasing, Lawson IF-RK4",
+                   "n": n, "timing": "graph" if args.graphs else "per-kernel events"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "energy_after": energy,
+        "enstrophy_after": enstrophy,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -78,7 +78,7 @@ def _hermitian_kx0(a: np.ndarray, ndim: int) -> None:
         a[0, 0] = 0.0
         return
     # a: [..., kz, ky, kx]; positive half of the plane = (ky > 0) or (ky == 0, kz > 0)
-    plane = a[..., 0]
+    plane = np.ascontiguousarray(a[..., 0])
     kz = np.arange(n)[:, None]
     ky = np.arange(n)[None, :]
     pos = ((ky >= 1) & (ky < n // 2)) | ((ky == 0) & (kz >= 1) & (kz < n // 2))
@@ -88,6 +88,7 @@ def _hermitian_kx0(a: np.ndarray, ndim: int) -> None:
     plane[..., n // 2, :] = 0.0
     plane[..., :, n // 2] = 0.0
     plane[..., 0, 0] = 0.0
+    a[..., 0] = plane
 
 
 def taylor_green_2d(n: int) -> np.ndarray:
@@ -207,30 +208,61 @@ def random_solenoidal_3d(n: int, seed: int = 1, energy: float = 1.0,
 
     Per stored mode two complex Gaussians (a, b) are drawn and placed on two
     unit vectors orthogonal to k, so the field is divergence free by
-    construction."""
+    construction.  Planes of constant kz are generated one after the other
+    (the random stream is the same as one draw over the whole array)."""
     rng = np.random.default_rng(seed)
-    kx, ky, kz = _grids(n, 3)
-    e1, e2 = _craya_basis(kx, ky, kz)
-    g = rng.standard_normal((n, n, n // 2 + 1, 2, 2))
-    a = g[..., 0, 0] + 1j * g[..., 0, 1]
-    b = g[..., 1, 0] + 1j * g[..., 1, 1]
-    del g
-    s, kmag = _shell(kx, ky, kz)
-    sup = kept_cube(n, 3) & (kmag > 0)
-    a = np.where(sup, a, 0.0)
-    b = np.where(sup, b, 0.0)
-    u = a[None] * e1 + b[None] * e2
-    del a, b, e1, e2
+    h = n // 2 + 1
+    full, half = mode_numbers(n)
+    kept_full = 3 * np.abs(full) < n
+    ky, kx = np.meshgrid(full.astype(np.float64), half.astype(np.float64), indexing="ij")
+    keep_plane = kept_full[:, None] & (3 * half < n)[None, :]
+    # Craya basis: e1 = (ky, -kx, 0)/|k_perp| (x_hat on the kz axis) does not
+    # depend on kz; e2 = k x e1 / |k|
+    kp = np.sqrt(kx * kx + ky * ky)
+    on_axis = kp == 0
+    kps = np.where(on_axis, 1.0, kp)
+    e1x = np.where(on_axis, 1.0, ky / kps)
+    e1y = np.where(on_axis, 0.0, -kx / kps)
+    u = np.zeros((3, n, n, h), np.complex128)
+    ur = u.view(np.float64).reshape(3, n, n, h, 2)
+    for iz in range(n):
+        g = rng.standard_normal((n, h, 2, 2))
+        if not kept_full[iz]:
+            continue
+        kz = float(full[iz])
+        kmag = np.sqrt(kp * kp + kz * kz)
+        sup = keep_plane & (kmag > 0)
+        ik = np.where(sup, 1.0 / np.where(kmag > 0, kmag, 1.0), 0.0)
+        f1x, f1y = e1x * sup, e1y * sup
+        e2x = np.where(on_axis, 0.0, kz * kx / kps) * ik
+        e2y = np.where(on_axis, kz, kz * ky / kps) * ik
+        e2z = np.where(on_axis, 0.0, -kp) * ik
+        for ri in range(2):  # real, imaginary
+            ga, gb = g[..., 0, ri], g[..., 1, ri]
+            ur[0, iz, :, :, ri] = ga * f1x + gb * e2x
+            ur[1, iz, :, :, ri] = ga * f1y + gb * e2y
+            ur[2, iz, :, :, ri] = gb * e2z
     _hermitian_kx0(u, 3)
-    e_mode = 0.5 * _half_weight(kx) * np.sum(np.abs(u) ** 2, axis=0)
-    nb = int(s.max()) + 1
-    e_shell = np.bincount(s.ravel(), weights=e_mode.ravel(), minlength=nb)
+    nb = int(np.floor(np.sqrt(3.0) * (n // 2) + 0.5)) + 2
+    e_shell = np.zeros(nb)
+    w = _half_weight(kx)
+    for iz in range(n):
+        if not kept_full[iz]:
+            continue
+        k2 = kx * kx + ky * ky + float(full[iz]) ** 2
+        s = np.floor(np.sqrt(k2) + 0.5).astype(np.int64)
+        e_mode = 0.5 * w * np.sum(np.abs(u[:, iz]) ** 2, axis=0)
+        e_shell += np.bincount(s.ravel(), weights=e_mode.ravel(), minlength=nb)
     target = np.array([shape_fn(float(q)) if q > 0 else 0.0 for q in range(nb)])
     target = np.where(e_shell > 0, target, 0.0)
     target *= energy / target.sum()
     scale = np.sqrt(np.where(e_shell > 0, target / np.where(e_shell > 0, e_shell, 1.0), 0.0))
-    u *= scale[s][None]
-    return u.astype(dtype, copy=False)
+    out = np.empty((3, n, n, h), dtype)
+    for iz in range(n):
+        k2 = kx * kx + ky * ky + float(full[iz]) ** 2
+        s = np.floor(np.sqrt(k2) + 0.5).astype(np.int64)
+        out[:, iz] = u[:, iz] * scale[s][None]
+    return out
 
 
 def ensemble_sizes(counts=((128, 128), (96, 256), (32, 512))):
