@@ -9,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libfs.so")
 SOURCES = ["ops3d.hip", "ops2d.hip", "diag.hip", "fs_api.cpp"]
 ARCH = os.environ.get("FS_OFFLOAD_ARCH", "gfx950")
@@ -22,7 +23,7 @@ FLAGS = [
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-x", "hip", "-c", os.path.join(SRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, "-I", INCLUDE, "-x", "hip", "-c", os.path.join(SRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -31,18 +32,26 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+def build(verbose: bool = False, jobs: int | None = None, src: str | None = None,
+          out: str | None = None, objdir: str | None = None) -> str:
+    """Compile the sources in `src` (default csrc/) into `out` (default libfs.so)."""
+    global SRC, BUILD
+    if src:
+        SRC = src
+    if objdir:
+        BUILD = objdir
+    lib = out or LIB
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -101,22 +101,76 @@ struct StageRadix {
   static constexpr int value = (N / NS >= 8) ? 8 : N / NS;
 };
 
+// Stage bookkeeping: stage s starts with sub-transform length NS(s) = 8^s
+// (the last stage may have radix 4 or 2).
+template <int N>
+struct Stages {
+  static constexpr int count() {
+    int c = 0;
+    for (int ns = 1; ns < N; ns *= (N / ns >= 8 ? 8 : N / ns)) c++;
+    return c;
+  }
+  static constexpr int C = count();
+};
+
+// Per-lane twiddles.  With REGS every lane loads the twiddles of all its
+// butterflies once (w[s][q*(R-1) + r-1] = W^{r k N/(NS R)}, k = (t + qP) mod
+// NS) and keeps them in registers for every transform of the kernel (worth
+// it when a kernel runs several transforms); otherwise they are read from
+// the table when used.  FP64 always reads the table (register budget).
+template <typename T, int N, bool REGS = true>
+struct Twiddles {
+  static constexpr bool kRegs = REGS && sizeof(T) == 4;
+  static constexpr int C = Stages<N>::C;
+  cx<T> w[kRegs ? C : 1][7];
+  const cx<T>* __restrict__ tab;
+
+  __device__ __forceinline__ Twiddles(const cx<T>* __restrict__ table, int t) : tab(table) {
+    if constexpr (kRegs) load_stage<1, 0>(t);
+  }
+  template <int NS, int S_>
+  __device__ __forceinline__ void load_stage(int t) {
+    constexpr int P = N / 8;
+    constexpr int R = StageRadix<N, NS>::value;
+    constexpr int NB = 8 / R;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) {
+        const int k = (t + q * P) & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < R; r++) w[S_][q * (R - 1) + r - 1] = tab[r * k * (N / (NS * R))];
+      }
+    }
+    if constexpr (NS * R < N) load_stage<NS * R, (NS > 1 ? S_ + 1 : S_)>(t);
+  }
+  // twiddle of register (q, r) of stage S_ (index NS) for lane t
+  template <int NS, int S_>
+  __device__ __forceinline__ cx<T> get(int t, int q, int r) const {
+    if constexpr (kRegs) {
+      constexpr int R = StageRadix<N, NS>::value;
+      return w[S_][q * (R - 1) + r - 1];
+    } else {
+      constexpr int P = N / 8;
+      constexpr int R = StageRadix<N, NS>::value;
+      const int k = (t + q * P) & (NS - 1);
+      return tab[r * k * (N / (NS * R))];
+    }
+  }
+};
+
 // Butterflies of one Stockham stage on lane t's 8 registers.  A radix-R
 // stage does 8/R butterflies per lane: butterfly q is j = t + q*P and uses
 // registers q + (8/R)*r, r = 0..R-1.
-template <typename T, int N, int S, int NS>
-__host__ __device__ __forceinline__ void stage_bfly(cx<T> (&v)[8], int t,
-                                                    const cx<T>* __restrict__ tw) {
-  constexpr int P = N / 8;
+template <typename T, int N, int S, int NS, int SI, class TW>
+__host__ __device__ __forceinline__ void stage_bfly(cx<T> (&v)[8], int t, const TW& tw) {
   constexpr int R = StageRadix<N, NS>::value;
   constexpr int NB = 8 / R;
 #pragma unroll
   for (int q = 0; q < NB; q++) {
     if constexpr (NS > 1) {
-      const int k = (t + q * P) & (NS - 1);
 #pragma unroll
       for (int r = 1; r < R; r++) {
-        cx<T> w = tw[r * k * (N / (NS * R))];
+        cx<T> w = tw.template get<NS, SI>(t, q, r);
         if constexpr (S > 0) w.im = -w.im;
         v[q + NB * r] = cmul(v[q + NB * r], w);
       }
@@ -146,13 +200,13 @@ __host__ __device__ __forceinline__ int stage_out_pos(int t, int e) {
 // `idx(f, pos)` maps (line f of this lane, position) to an LDS element
 // offset; the caller owns disjoint LDS for every (lane group, line).
 // Every lane of the block must call this (it contains __syncthreads).
-template <typename T, int N, int S, int F, int NS = 1, class Idx>
+template <typename T, int N, int S, int F, int NS = 1, int SI = 0, class Idx, class TW>
 __device__ __forceinline__ void fft_lines(cx<T> (&v)[F][8], int t, cx<T>* lds, Idx idx,
-                                          const cx<T>* __restrict__ tw) {
+                                          const TW& tw) {
   constexpr int P = N / 8;
   constexpr int R = StageRadix<N, NS>::value;
 #pragma unroll
-  for (int f = 0; f < F; f++) stage_bfly<T, N, S, NS>(v[f], t, tw);
+  for (int f = 0; f < F; f++) stage_bfly<T, N, S, NS, SI>(v[f], t, tw);
   if constexpr (NS * R < N) {
 #pragma unroll
     for (int f = 0; f < F; f++)
@@ -164,7 +218,7 @@ __device__ __forceinline__ void fft_lines(cx<T> (&v)[F][8], int t, cx<T>* lds, I
 #pragma unroll
       for (int e = 0; e < 8; e++) v[f][e] = lds[idx(f, t + e * P)];
     __syncthreads();
-    fft_lines<T, N, S, F, NS * R>(v, t, lds, idx, tw);
+    fft_lines<T, N, S, F, NS * R, (NS > 1 ? SI + 1 : SI)>(v, t, lds, idx, tw);
   }
 }
 

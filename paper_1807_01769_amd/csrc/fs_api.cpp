@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fs.h"
+#include "fs.h"
 #include "fft_core.h"
 #include "fs_internal.h"
 
@@ -189,6 +189,9 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
     if (m2max < 0) return fail(FS_E_INVALID, "forcing band contains no mode");
     if (bw < 1) bw = 1;
   }
+
+  if (o.ndim == 3 && o.precision == FS_F64 && n > 512)
+    return fail(FS_E_UNSUPPORTED, "3D FP64 plans support n <= 512");
 
   fs_plan* h = new (std::nothrow) fs_plan();
   if (!h) return fail(FS_E_NOMEM, "host allocation failed");

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fs.h"
+#include "fs.h"
 
 namespace fs {
 

@@ -17,10 +17,10 @@ namespace fs {
 
 // three inverse y transforms of (u, v, w) derived from w_hat held as
 // v[e] at y-position t + e*P of line b (kx = mx); writes Wn[3][XT][N][16]
-template <typename T, int N>
+template <typename T, int N, class TW>
 __device__ __forceinline__ void y_inverse_three(cx<T> (&w)[8], int t, int b, int xt, int sub,
                                                 int mx, T kb, cx<T>* __restrict__ w1,
-                                                cx<T>* lds, const cx<T>* __restrict__ tw) {
+                                                cx<T>* lds, const TW& tw) {
   using G = Geo<N, false>;
   using C = Strided<T, N>;
   constexpr int P = G::P;
@@ -57,6 +57,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   constexpr int P = G::P, NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N> twr(a.tw, t);
   const int sub = blockIdx.x % C::SUB, xt = blockIdx.x / C::SUB;
   const int mx = xt * kTile + sub * C::LB + b;
   cx<T> w[8];
@@ -66,7 +67,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     const bool kept = mx < G::H && G::i2j(iy) >= 0;
     w[e] = kept ? state[(size_t)iy * NH + mx] : cx<T>{0, 0};
   }
-  y_inverse_three<T, N>(w, t, b, xt, sub, mx, a.kb, w1, lds, a.tw);
+  y_inverse_three<T, N>(w, t, b, xt, sub, mx, a.kb, w1, lds, twr);
 }
 
 // X pass: rows (y0, y0+1); in Wn[3][XT][N][16] (u, v, w), out Wn[2][XT][N][16]
@@ -80,6 +81,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   constexpr int P = G::P;
   __shared__ cx<T> lds[R::RP * 3 * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
+  const Twiddles<T, N> twr(tw, t);
   const int y0 = 2 * (blockIdx.x * R::RP + rp);
   cx<T>* my_lds = lds + rp * 3 * R::NPAD;
   auto lidx = [=](int f, int pos) { return f * R::NPAD + R::pad(pos); };
@@ -98,7 +100,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
     v[2][e] = c2r_pair_at<T, N, false>(k, [&](int m) { return at(2, y0, m); },
                                        [&](int m) { return at(2, y0 + 1, m); });
   }
-  fft_lines<T, N, +1, 3>(v, t, my_lds, lidx, tw);
+  fft_lines<T, N, +1, 3>(v, t, my_lds, lidx, twr);
   cx<T> q[2][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
     q[0][e] = {v[0][e].re * w0, v[0][e].im * w0};
     q[1][e] = {v[1][e].re * w1, v[1][e].im * w1};
   }
-  fft_lines<T, N, -1, 2>(q, t, my_lds, lidx, tw);
+  fft_lines<T, N, -1, 2>(q, t, my_lds, lidx, twr);
 #pragma unroll
   for (int f = 0; f < 2; f++)
 #pragma unroll
@@ -134,6 +136,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   constexpr int P = G::P, NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N> twr(a.tw, t);
   const int sub = blockIdx.x % C::SUB, xt = blockIdx.x / C::SUB;
   const int mx = xt * kTile + sub * C::LB + b;
   auto lidx = [=](int, int pos) { return pos * C::LB + b; };
@@ -142,10 +145,10 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   cx<T> f1[1][8], f2[1][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) f1[0][e] = src[(size_t)(t + e * P) * kTile];
-  fft_lines<T, N, -1, 1>(f1, t, lds, lidx, a.tw);
+  fft_lines<T, N, -1, 1>(f1, t, lds, lidx, twr);
 #pragma unroll
   for (int e = 0; e < 8; e++) f2[0][e] = src[fstride + (size_t)(t + e * P) * kTile];
-  fft_lines<T, N, -1, 1>(f2, t, lds, lidx, a.tw);
+  fft_lines<T, N, -1, 1>(f2, t, lds, lidx, twr);
 
   const T kx = a.kb * (T)mx;
   cx<T> w[8];
@@ -180,7 +183,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     }
   }
   if constexpr (MODE != kModeTend) {
-    if (do_p1) y_inverse_three<T, N>(w, t, b, xt, sub, mx, a.kb, w1, lds, a.tw);
+    if (do_p1) y_inverse_three<T, N>(w, t, b, xt, sub, mx, a.kb, w1, lds, twr);
   }
 }
 
@@ -194,13 +197,14 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   constexpr int P = G::P, NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N, false> twr(tw, t);
   const int sub = blockIdx.x % C::SUB, xt = blockIdx.x / C::SUB;
   const int mx = xt * kTile + sub * C::LB + b;
   cx<T> v[1][8];
 #pragma unroll
   for (int e = 0; e < 8; e++)
     v[0][e] = mx < G::H ? spec[(size_t)(t + e * P) * NH + mx] : cx<T>{0, 0};
-  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
   cx<T>* dst = w + (size_t)xt * N * kTile + sub * C::LB + b;
 #pragma unroll
   for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * kTile] = v[0][e];
@@ -215,13 +219,14 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   constexpr int P = G::P, NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N, false> twr(tw, t);
   const int sub = blockIdx.x % C::SUB, xt = blockIdx.x / C::SUB;
   const int mx = xt * kTile + sub * C::LB + b;
   const cx<T>* src = w + (size_t)xt * N * kTile + sub * C::LB + b;
   cx<T> v[1][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) v[0][e] = src[(size_t)(t + e * P) * kTile];
-  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
   if (mx < G::H) {
 #pragma unroll
     for (int e = 0; e < 8; e++) spec[(size_t)(t + e * P) * NH + mx] = v[0][e];

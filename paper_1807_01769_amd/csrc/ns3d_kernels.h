@@ -21,8 +21,11 @@ namespace fs {
 
 // ---------------------------------------------------------------------------
 // X pass: for each row pair (y0, y0+1) at height z, inverse-transform
-// (ux,uy) (uz,wx) (wy,wz) of both rows, form p = (u x w) * scale, forward
+// (ux,uy) (uz,wx) (wy,wz) of each row, form p = (u x w) * scale, forward
 // transform (px + i py) of each row and (pz(y0) + i pz(y1)), store kept kx.
+// One transform line is in flight at a time and the cross product is built
+// as its factors arrive (u kept, partial products accumulated), so a row
+// pair needs one LDS line and about 100 VGPRs.
 // in : Wn[6][N][XT][N][16]   out: Wn[3][N][XT][N][16]
 // Grid: (N/2/RP, N).
 // ---------------------------------------------------------------------------
@@ -33,97 +36,142 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   using G = Geo<N, false>;
   using R = RowPairs<N>;
   constexpr int P = G::P;
-  __shared__ cx<T> lds[R::RP * 3 * R::NPAD];
+  // staging: the row pair's kept coefficients, [field][xt][row][16]
+  constexpr int SPAIR = 6 * G::XT * 2 * kTile;
+  __shared__ cx<T> stage[R::RP * SPAIR];
+  __shared__ cx<T> lds[R::RP * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
+  const Twiddles<T, N> twr(tw, t);
   const int z = blockIdx.y;
   const int y0 = 2 * (blockIdx.x * R::RP + rp);
-  cx<T>* my_lds = lds + rp * 3 * R::NPAD;
-  auto lidx = [=](int f, int pos) { return f * R::NPAD + R::pad(pos); };
-
+  cx<T>* line = lds + rp * R::NPAD;
+  cx<T>* st = stage + rp * SPAIR;
+  auto lidx = [=](int, int pos) { return R::pad(pos); };
   const size_t fstride = (size_t)N * G::XT * N * kTile;  // one field
-  const cx<T>* inz = in + (size_t)z * G::XT * N * kTile;
-  auto at = [=](int f, int y, int m) -> cx<T> {
-    return inz[f * fstride + ((size_t)(m >> 4) * N + y) * kTile + (m & 15)];
-  };
 
-  // u (3) and w (3) of both rows, two real fields per complex line
-  cx<T> uw[6][8];
+  // Phase 1: for each (field, tile) the two rows are 2*16 contiguous
+  // coefficients in memory; move them with 16-byte loads, all in flight.
+  {
+    constexpr int PER = 16 / (int)sizeof(cx<T>);        // coefficients per load
+    constexpr int LOADS = 6 * G::XT * 2 * kTile / PER;  // per row pair
+    const uint4* src4 = reinterpret_cast<const uint4*>(in);
+    uint4* st4 = reinterpret_cast<uint4*>(st);
 #pragma unroll
-  for (int g = 0; g < 3; g++) {
-    cx<T> v[2][8];
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-      const int y = y0 + r;
-#pragma unroll
-      for (int e = 0; e < 8; e++)
-        v[r][e] = c2r_pair_at<T, N, false>(
-            t + e * P, [&](int m) { return at(2 * g, y, m); },
-            [&](int m) { return at(2 * g + 1, y, m); });
-    }
-    fft_lines<T, N, +1, 2>(v, t, my_lds, lidx, tw);
-#pragma unroll
-    for (int e = 0; e < 8; e++) {
-      uw[g][e] = v[0][e];
-      uw[3 + g][e] = v[1][e];
-    }
-  }
-  // uw[0] = (ux, uy)(y0)  uw[1] = (uz, wx)(y0)  uw[2] = (wy, wz)(y0); +3 for y1
-  cx<T> pp[3][8];
-#pragma unroll
-  for (int e = 0; e < 8; e++) {
-    T pz[2];
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-      const cx<T> a = uw[3 * r][e], b = uw[3 * r + 1][e], c = uw[3 * r + 2][e];
-      const T ux = a.re, uy = a.im, uz = b.re, wx = b.im, wy = c.re, wz = c.im;
-      const T px = (uy * wz - uz * wy) * scale;
-      const T py = (uz * wx - ux * wz) * scale;
-      pz[r] = (ux * wy - uy * wx) * scale;
-      pp[r][e] = {px, py};
-    }
-    pp[2][e] = {pz[0], pz[1]};
-  }
-  fft_lines<T, N, -1, 3>(pp, t, my_lds, lidx, tw);
-#pragma unroll
-  for (int f = 0; f < 3; f++)
-#pragma unroll
-    for (int e = 0; e < 8; e++) my_lds[lidx(f, t + e * P)] = pp[f][e];
-  __syncthreads();
-  cx<T>* outz = out + (size_t)z * G::XT * N * kTile;
-  for (int m = t; m < G::XT * kTile; m += P) {
-    cx<T> a[3], bq[3];
-#pragma unroll
-    for (int f = 0; f < 3; f++) {
-      if (m < G::H) {
-        r2c_untangle(my_lds[lidx(f, m)], my_lds[lidx(f, (N - m) & (N - 1))], a[f], bq[f]);
-      } else {
-        a[f] = {0, 0};
-        bq[f] = {0, 0};
+    for (int i0 = 0; i0 < LOADS; i0 += P) {
+      const int i = i0 + t;
+      if (i < LOADS) {
+        const int c = i / (2 * kTile / PER), l = i % (2 * kTile / PER);
+        const int f = c / G::XT, xt = c % G::XT;
+        const size_t g = ((((size_t)f * N + z) * G::XT + xt) * N + y0) * kTile;  // coefficient
+        st4[i] = src4[g / PER + l];
       }
     }
-    const size_t o = ((size_t)(m >> 4) * N) * kTile + (m & 15);
-    // px, py, pz of row y0 and y1
-    outz[0 * fstride + o + (size_t)y0 * kTile] = a[0];
-    outz[1 * fstride + o + (size_t)y0 * kTile] = bq[0];
-    outz[0 * fstride + o + (size_t)(y0 + 1) * kTile] = a[1];
-    outz[1 * fstride + o + (size_t)(y0 + 1) * kTile] = bq[1];
-    outz[2 * fstride + o + (size_t)y0 * kTile] = a[2];
-    outz[2 * fstride + o + (size_t)(y0 + 1) * kTile] = bq[2];
+  }
+  __syncthreads();
+
+  // Register e holds position k = t + e*P of the complex line a + i b; it
+  // needs coefficient m = k (k <= K) or the conjugate mirror m = N - k
+  // (k >= N - K) of both half spectra.
+  int off[8], kind[8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int k = t + e * P;
+    const int m = k <= G::K ? k : (k >= N - G::K ? N - k : 0);
+    kind[e] = k <= G::K ? (k == 0 ? 2 : 1) : (k >= N - G::K ? -1 : 0);
+    off[e] = (m >> 4) * 2 * kTile + (m & 15);
+  }
+  // inverse transform of fields (2g, 2g+1) of row r into v
+  auto inverse_pair = [&](int g, int r, cx<T> (&v)[1][8]) {
+    const cx<T>* ba = st + (2 * g) * G::XT * 2 * kTile + r * kTile;
+    const cx<T>* bb = ba + G::XT * 2 * kTile;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      cx<T> res = {0, 0};
+      if (kind[e] != 0) {
+        cx<T> A = ba[off[e]], B = bb[off[e]];
+        if (kind[e] == 2) A.im = B.im = 0;
+        res = kind[e] > 0 ? cx<T>{A.re - B.im, A.im + B.re} : cx<T>{A.re + B.im, B.re - A.im};
+      }
+      v[0][e] = res;
+    }
+    fft_lines<T, N, +1, 1>(v, t, line, lidx, twr);
+  };
+
+  cx<T>* outz = out + (size_t)z * G::XT * N * kTile;
+  // forward transform of v, untangled into kept kx of the two real lines
+  // (field fa, row ya) and (field fb, row yb)
+  auto forward_store = [&](cx<T> (&v)[1][8], int fa, int ya, int fb, int yb) {
+    fft_lines<T, N, -1, 1>(v, t, line, lidx, twr);
+#pragma unroll
+    for (int e = 0; e < 8; e++) line[lidx(0, t + e * P)] = v[0][e];
+    __syncthreads();
+    for (int m = t; m < G::XT * kTile; m += P) {
+      cx<T> A = {0, 0}, B = {0, 0};
+      if (m < G::H) r2c_untangle(line[lidx(0, m)], line[lidx(0, (N - m) & (N - 1))], A, B);
+      const size_t o = ((size_t)(m >> 4) * N) * kTile + (m & 15);
+      outz[fa * fstride + o + (size_t)ya * kTile] = A;
+      outz[fb * fstride + o + (size_t)yb * kTile] = B;
+    }
+    __syncthreads();
+  };
+
+  // Row by row: three inverse transforms build p = (u x w) * scale as the
+  // factors arrive; (px + i py) is transformed at once, pz of the first row
+  // waits to be paired with pz of the second.
+  T pz0[8];
+#pragma unroll
+  for (int r = 0; r < 2; r++) {
+    T ux[8], uy[8], uz[8], qy[8], qz[8];
+    cx<T> v[1][8];
+    inverse_pair(0, r, v);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      ux[e] = v[0][e].re;
+      uy[e] = v[0][e].im;
+    }
+    inverse_pair(1, r, v);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      uz[e] = v[0][e].re;
+      const T wx = v[0][e].im;
+      qy[e] = uz[e] * wx;   // py = uz wx - ux wz
+      qz[e] = -uy[e] * wx;  // pz = ux wy - uy wx
+    }
+    inverse_pair(2, r, v);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const T wy = v[0][e].re, wz = v[0][e].im;
+      const T pz = (qz[e] + ux[e] * wy) * scale;
+      v[0][e] = {(uy[e] * wz - uz[e] * wy) * scale, (qy[e] - ux[e] * wz) * scale};
+      if (r == 0) pz0[e] = pz;
+      else qz[e] = pz;
+    }
+    forward_store(v, 0, y0 + r, 1, y0 + r);
+    if (r == 1) {
+#pragma unroll
+      for (int e = 0; e < 8; e++) v[0][e] = {pz0[e], qz[e]};
+      forward_store(v, 2, y0, 2, y0 + 1);
+    }
   }
 }
+
+// The fused z passes keep three components plus a transform line in registers;
+// at most 512 threads per block leaves them up to 256 VGPRs (no spills).
+template <typename T, int N>
+using ZCfg = Strided<T, N, cmin(kTile, cmax(1, 512 / (N / 8)))>;
 
 // ---------------------------------------------------------------------------
 // Inverse z transforms of the six fields (u, w = i k x v) of a stage input v
 // held in registers as v[c][e] at z-position t + e*P of line b; writes
 // Wm[6][N][XT][M][16] (fields ordered ux uy uz wx wy wz).
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, class TW>
 __device__ __forceinline__ void z_inverse_six(cx<T> (&v)[3][8], int t, int b, int jy, int xt,
                                               int sub, int mx, int my, T kb,
                                               cx<T>* __restrict__ w1, cx<T>* lds,
-                                              const cx<T>* __restrict__ tw) {
+                                              const TW& tw) {
   using G = Geo<N, false>;
-  using C = Strided<T, N>;
+  using C = ZCfg<T, N>;
   constexpr int P = G::P;
   const size_t fstride = (size_t)N * G::XT * G::M * kTile;
   cx<T>* dst0 = w1 + (size_t)xt * G::M * kTile + (size_t)jy * kTile + sub * C::LB + b;
@@ -180,14 +228,15 @@ __device__ __forceinline__ bool in_band(const StageArgs<T>& a, int mx, int my, i
 // writes the six inverse-z-transformed fields.  Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
-__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+__global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
     k3_p1(const cx<T>* __restrict__ state, cx<T>* __restrict__ w1, StageArgs<T> a) {
   using G = Geo<N, false>;
-  using C = Strided<T, N>;
+  using C = ZCfg<T, N>;
   constexpr int P = G::P;
   constexpr int NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N> twr(a.tw, t);
   int blk = blockIdx.x;
   const int sub = blk % C::SUB;
   blk /= C::SUB;
@@ -214,7 +263,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
       }
     }
   }
-  z_inverse_six<T, N>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, a.tw);
+  z_inverse_six<T, N>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
 }
 
 // ---------------------------------------------------------------------------
@@ -224,14 +273,15 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
 // MODE kModeTend writes the tendency to a.tend instead.  Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+__global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
     k3_z(const cx<T>* __restrict__ w4, cx<T>* __restrict__ w1, StageArgs<T> a, int do_p1) {
   using G = Geo<N, false>;
-  using C = Strided<T, N>;
+  using C = ZCfg<T, N>;
   constexpr int P = G::P;
   constexpr int NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N> twr(a.tw, t);
   int blk = blockIdx.x;
   const int sub = blk % C::SUB;
   blk /= C::SUB;
@@ -245,16 +295,15 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   const size_t fstride = (size_t)N * G::XT * G::M * kTile;
   const size_t zstride = (size_t)G::XT * G::M * kTile;
   const cx<T>* src0 = w4 + (size_t)xt * G::M * kTile + (size_t)jy * kTile + sub * C::LB + b;
+  // all three components' loads are issued before the first transform
   cx<T> v[3][8];
 #pragma unroll
-  for (int c = 0; c < 3; c++) {
-    cx<T> w[1][8];
+  for (int c = 0; c < 3; c++)
 #pragma unroll
-    for (int e = 0; e < 8; e++) w[0][e] = src0[c * fstride + (size_t)(t + e * P) * zstride];
-    fft_lines<T, N, -1, 1>(w, t, lds, lidx, a.tw);
+    for (int e = 0; e < 8; e++) v[c][e] = src0[c * fstride + (size_t)(t + e * P) * zstride];
 #pragma unroll
-    for (int e = 0; e < 8; e++) v[c][e] = w[0][e];
-  }
+  for (int c = 0; c < 3; c++)
+    fft_lines<T, N, -1, 1>(reinterpret_cast<cx<T>(&)[1][8]>(v[c]), t, lds, lidx, twr);
 
   const size_t cstride = (size_t)N * N * NH;
   const size_t acstride = (size_t)G::XT * G::M * G::M * kTile;
@@ -319,7 +368,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     }
   }
   if constexpr (MODE != kModeTend) {
-    if (do_p1) z_inverse_six<T, N>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, a.tw);
+    if (do_p1) z_inverse_six<T, N>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
   }
 }
 
@@ -336,6 +385,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   constexpr int P = G::P, NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N, false> twr(tw, t);
   int blk = blockIdx.x;
   const int sub = blk % C::SUB;
   blk /= C::SUB;
@@ -345,7 +395,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
 #pragma unroll
   for (int e = 0; e < 8; e++)
     v[0][e] = mx < G::H ? spec[((size_t)(t + e * P) * N + iy) * NH + mx] : cx<T>{0, 0};
-  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
   const size_t zstride = (size_t)G::XT * N * kTile;
   cx<T>* dst = w + ((size_t)xt * N + iy) * kTile + sub * C::LB + b;
 #pragma unroll
@@ -361,6 +411,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   constexpr int P = G::P, NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N, false> twr(tw, t);
   int blk = blockIdx.x;
   const int sub = blk % C::SUB;
   blk /= C::SUB;
@@ -371,7 +422,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   cx<T> v[1][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) v[0][e] = src[(size_t)(t + e * P) * zstride];
-  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
   if (mx < G::H) {
 #pragma unroll
     for (int e = 0; e < 8; e++) spec[((size_t)(t + e * P) * N + iy) * NH + mx] = v[0][e];
@@ -388,6 +439,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   constexpr int P = G::P;
   __shared__ cx<T> lds[R::RP * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
+  const Twiddles<T, N, false> twr(tw, t);
   const int z = blockIdx.y, y0 = 2 * (blockIdx.x * R::RP + rp);
   const cx<T>* wz = w + (size_t)z * G::XT * N * kTile;
   auto at = [=](int y, int m) { return wz[((size_t)(m >> 4) * N + y) * kTile + (m & 15)]; };
@@ -397,7 +449,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
     v[0][e] = c2r_pair_at<T, N, true>(
         t + e * P, [&](int m) { return at(y0, m); }, [&](int m) { return at(y0 + 1, m); });
   fft_lines<T, N, +1, 1>(v, t, lds + rp * R::NPAD,
-                         [=](int, int pos) { return R::pad(pos); }, tw);
+                         [=](int, int pos) { return R::pad(pos); }, twr);
   T* row = phys + ((size_t)z * N + y0) * N;
 #pragma unroll
   for (int e = 0; e < 8; e++) {
@@ -416,6 +468,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   constexpr int P = G::P;
   __shared__ cx<T> lds[R::RP * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
+  const Twiddles<T, N, false> twr(tw, t);
   const int z = blockIdx.y, y0 = 2 * (blockIdx.x * R::RP + rp);
   const T* row = phys + ((size_t)z * N + y0) * N;
   cx<T> v[1][8];
@@ -423,7 +476,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   for (int e = 0; e < 8; e++) v[0][e] = {row[t + e * P] * scale, row[N + t + e * P] * scale};
   cx<T>* my = lds + rp * R::NPAD;
   auto lidx = [=](int, int pos) { return R::pad(pos); };
-  fft_lines<T, N, -1, 1>(v, t, my, lidx, tw);
+  fft_lines<T, N, -1, 1>(v, t, my, lidx, twr);
 #pragma unroll
   for (int e = 0; e < 8; e++) my[lidx(0, t + e * P)] = v[0][e];
   __syncthreads();

@@ -42,13 +42,13 @@ struct Geo {
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
-// Lines per block of a strided (y or z) pass: at most 16 (one tile), at most
-// 1024 threads and at most 64 KiB of LDS.
-template <typename T, int N>
+// Lines per block of a strided (y or z) pass: at most CAP (<= 16, one tile),
+// at most 1024 threads and at most 64 KiB of LDS.
+template <typename T, int N, int CAP = kTile>
 struct Strided {
   static constexpr int P = N / 8;
   static constexpr int LB =
-      cmin(kTile, cmin(65536 / (N * (int)sizeof(cx<T>)), 1024 / P));
+      cmin(CAP, cmin(65536 / (N * (int)sizeof(cx<T>)), 1024 / P));
   static constexpr int SUB = kTile / LB;
   static constexpr int THREADS = LB * P;
 };
@@ -118,6 +118,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   using C = Strided<T, N>;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N, false> twr(tw, t);
   int blk = blockIdx.x;
   const int sub = blk % C::SUB;
   blk /= C::SUB;
@@ -129,7 +130,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     const int j = G::i2j(t + e * G::P);
     v[0][e] = j >= 0 ? src[j * kTile] : cx<T>{0, 0};
   }
-  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
   cx<T>* dst = out + tile * N * kTile + sub * C::LB + b;
 #pragma unroll
   for (int e = 0; e < 8; e++) dst[(t + e * G::P) * kTile] = v[0][e];
@@ -143,6 +144,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   using C = Strided<T, N>;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N, false> twr(tw, t);
   int blk = blockIdx.x;
   const int sub = blk % C::SUB;
   blk /= C::SUB;
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   cx<T> v[1][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) v[0][e] = src[(t + e * G::P) * kTile];
-  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, tw);
+  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
   cx<T>* dst = out + tile * G::M * kTile + sub * C::LB + b;
 #pragma unroll
   for (int e = 0; e < 8; e++) {

@@ -31,6 +31,7 @@ struct L3 {
   using G = Geo<N, false>;
   using GF = Geo<N, true>;
   using C = Strided<T, N>;
+  using ZC = ZCfg<T, N>;
   using R = RowPairs<N>;
   static cx<T>* A(Plan* p) { return (cx<T>*)p->bufA; }
   static cx<T>* B(Plan* p) { return (cx<T>*)p->bufB; }
@@ -38,7 +39,7 @@ struct L3 {
 
   static void p1(Plan* p, const void* state) {
     p->begin(KID_P1);
-    hipLaunchKernelGGL((k3_p1<T, N>), dim3(G::M * G::XT * C::SUB), dim3(C::THREADS), 0,
+    hipLaunchKernelGGL((k3_p1<T, N>), dim3(G::M * G::XT * ZC::SUB), dim3(ZC::THREADS), 0,
                        p->launch, (const cx<T>*)state, A(p),
                        stage_args<T>(p, (void*)state, nullptr));
     launched(p, "k3_p1");
@@ -68,7 +69,7 @@ struct L3 {
   template <int MODE>
   static void zk(Plan* p, void* state, void* tend, int do_p1) {
     p->begin(KID_Z);
-    hipLaunchKernelGGL((k3_z<T, N, MODE>), dim3(G::M * G::XT * C::SUB), dim3(C::THREADS), 0,
+    hipLaunchKernelGGL((k3_z<T, N, MODE>), dim3(G::M * G::XT * ZC::SUB), dim3(ZC::THREADS), 0,
                        p->launch, (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend),
                        do_p1);
     launched(p, "k3_z");

@@ -13,7 +13,7 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfs.so")
+LIB_PATH = os.environ.get("FS_LIBRARY") or os.path.join(_HERE, "libfs.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_1807_01769_amd/build.py")
 
