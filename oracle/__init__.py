@@ -14,6 +14,7 @@ projection, with part of the linear terms treated exactly).
 Pins (tests/test_oracle_*.py, all CPU):
   fft / rfftn / irfftn   brute-force DFT, round trip, Parseval, single modes,
                          numpy.fft cross-check
+  dft_mode3d             brute-force DFT (every mode of a small cube)
   tendency3d             exact Galerkin triad sum (dealiasing), closed-form
                          Taylor-Green vorticity/product, energy and helicity
                          conservation at nu = 0, solenoidality, ABC flow N = 0
@@ -64,6 +65,7 @@ def lib():
         L.or_get_threads.restype = i
         L.or_kept.argtypes = [i, i]
         L.or_kept.restype = i
+        L.or_dft_mode3d.argtypes = [i, vp, i, i, i, vp, vp]
         L.or_lawson_scalar.argtypes = [d, d, d, i]
         L.or_lawson_scalar.restype = d
         _LIB = L
@@ -175,3 +177,11 @@ def kept(m: int, n: int) -> bool:
 def lawson_scalar(lam, y0, dt, nsteps):
     """Lawson RK4 on y' = -lam y + y^2 (the scheme used by step2d/step3d)."""
     return float(lib().or_lawson_scalar(float(lam), float(y0), float(dt), int(nsteps)))
+
+
+def dft_mode3d(phys, m):
+    """Forward coefficient N^-3 sum u(x) exp(-i m.x) of one mode m = (mx, my, mz)."""
+    p = np.ascontiguousarray(phys, dtype=np.float64)
+    re, im = C.c_double(), C.c_double()
+    lib().or_dft_mode3d(p.shape[0], _p(p), int(m[0]), int(m[1]), int(m[2]), C.byref(re), C.byref(im))
+    return complex(re.value, im.value)

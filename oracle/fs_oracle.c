@@ -188,6 +188,37 @@ void or_irfftn(int ndim, int n, const cplx *spec, double *phys) {
   free(a);
 }
 
+/* One forward coefficient by the direct sum, for checks at sizes where a
+ * whole transform is too expensive: N^-3 sum_x u(x) exp(-i k.x), with
+ * exp(-i k.x) = exp(-i kx x) exp(-i ky y) exp(-i kz z) and every factor from
+ * libm.  phys: real[n][n][n] (z, y, x). */
+void or_dft_mode3d(int n, const double *phys, int mx, int my, int mz, double *re, double *im) {
+  cplx *ex = malloc(sizeof(cplx) * n), *ey = malloc(sizeof(cplx) * n), *ez = malloc(sizeof(cplx) * n);
+  for (int j = 0; j < n; j++) {
+    double a = 2.0 * M_PI * (double)j / (double)n;
+    ex[j] = cos(a * mx) - I * sin(a * mx);
+    ey[j] = cos(a * my) - I * sin(a * my);
+    ez[j] = cos(a * mz) - I * sin(a * mz);
+  }
+  cplx total = 0;
+  for (int z = 0; z < n; z++) {
+    cplx sy = 0;
+    for (int y = 0; y < n; y++) {
+      const double *row = phys + ((int64_t)z * n + y) * n;
+      cplx sx = 0;
+      for (int x = 0; x < n; x++) sx += row[x] * ex[x];
+      sy += sx * ey[y];
+    }
+    total += sy * ez[z];
+  }
+  total /= (double)n * n * n;
+  *re = creal(total);
+  *im = cimag(total);
+  free(ex);
+  free(ey);
+  free(ez);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Wavenumbers and the dealiasing set                                        */
 /* ------------------------------------------------------------------------ */

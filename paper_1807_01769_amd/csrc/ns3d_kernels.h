@@ -36,7 +36,9 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   using G = Geo<N, false>;
   using R = RowPairs<N>;
   constexpr int P = G::P;
-  // staging: the row pair's kept coefficients, [field][xt][row][16]
+  // staging: the row pair's kept coefficients, [field][row][xt][16] (tiles
+  // of one row 128 bytes apart, so 32 lanes reading consecutive kx of a row
+  // hit distinct LDS banks)
   constexpr int SPAIR = 6 * G::XT * 2 * kTile;
   __shared__ cx<T> stage[R::RP * SPAIR];
   __shared__ cx<T> lds[R::RP * R::NPAD];
@@ -62,8 +64,9 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
       if (i < LOADS) {
         const int c = i / (2 * kTile / PER), l = i % (2 * kTile / PER);
         const int f = c / G::XT, xt = c % G::XT;
+        const int r = l / (kTile / PER), lo = l % (kTile / PER);
         const size_t g = ((((size_t)f * N + z) * G::XT + xt) * N + y0) * kTile;  // coefficient
-        st4[i] = src4[g / PER + l];
+        st4[((f * 2 + r) * G::XT + xt) * (kTile / PER) + lo] = src4[g / PER + l];
       }
     }
   }
@@ -78,12 +81,12 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
     const int k = t + e * P;
     const int m = k <= G::K ? k : (k >= N - G::K ? N - k : 0);
     kind[e] = k <= G::K ? (k == 0 ? 2 : 1) : (k >= N - G::K ? -1 : 0);
-    off[e] = (m >> 4) * 2 * kTile + (m & 15);
+    off[e] = m;
   }
   // inverse transform of fields (2g, 2g+1) of row r into v
   auto inverse_pair = [&](int g, int r, cx<T> (&v)[1][8]) {
-    const cx<T>* ba = st + (2 * g) * G::XT * 2 * kTile + r * kTile;
-    const cx<T>* bb = ba + G::XT * 2 * kTile;
+    const cx<T>* ba = st + ((2 * g) * 2 + r) * G::XT * kTile;
+    const cx<T>* bb = ba + 2 * G::XT * kTile;
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       cx<T> res = {0, 0};
@@ -237,10 +240,9 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
   const Twiddles<T, N> twr(a.tw, t);
-  int blk = blockIdx.x;
-  const int sub = blk % C::SUB;
-  blk /= C::SUB;
-  const int xt = blk % G::XT, jy = blk / G::XT;
+  int jy, rem;
+  if (!xcd_row_block(G::M, G::XT * C::SUB, jy, rem)) return;  // whole block
+  const int xt = rem / C::SUB, sub = rem % C::SUB;
   const int mx = xt * kTile + sub * C::LB + b;
   const int iy = G::j2i(jy), my = G::jmode(jy);
   const bool col = mx < G::H;
@@ -282,10 +284,9 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
   const Twiddles<T, N> twr(a.tw, t);
-  int blk = blockIdx.x;
-  const int sub = blk % C::SUB;
-  blk /= C::SUB;
-  const int xt = blk % G::XT, jy = blk / G::XT;
+  int jy, rem;
+  if (!xcd_row_block(G::M, G::XT * C::SUB, jy, rem)) return;  // whole block
+  const int xt = rem / C::SUB, sub = rem % C::SUB;
   const int mx = xt * kTile + sub * C::LB + b;
   const int iy = G::j2i(jy), my = G::jmode(jy);
   const bool col = mx < G::H;

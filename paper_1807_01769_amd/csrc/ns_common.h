@@ -53,6 +53,9 @@ struct Strided {
   static constexpr int THREADS = LB * P;
 };
 
+// Lines per block of the y passes.
+constexpr int kYLines = kTile;
+
 // Row pairs per block of an x pass (a row pair is owned by P lanes).
 template <int N>
 struct RowPairs {
@@ -62,6 +65,23 @@ struct RowPairs {
   static constexpr int NPAD = N + N / 8;  // LDS line stride, +1 slot per 8
   __host__ __device__ static constexpr int pad(int pos) { return pos + (pos >> 3); }
 };
+
+// Workgroups are dealt to the chip's XCDs round-robin by linear block id,
+// and every XCD has its own L2.  Passes whose blocks cover part of a
+// 128-byte line (or whose rows are not line aligned) order their blocks so
+// that all blocks of one row go to the same XCD, consecutively: linear id B
+// runs on XCD B % kXcd as that XCD's (B / kXcd)-th block.  Returns false for
+// the padding blocks of the last round.
+constexpr int kXcd = 8;
+__host__ __device__ constexpr int xcd_grid(int rows, int per_row) {
+  return kXcd * ((rows + kXcd - 1) / kXcd) * per_row;
+}
+__device__ __forceinline__ bool xcd_row_block(int rows, int per_row, int& row, int& rem) {
+  const int xcd = blockIdx.x % kXcd, q = blockIdx.x / kXcd;
+  row = (q / per_row) * kXcd + xcd;
+  rem = q % per_row;
+  return row < rows;
+}
 
 // Parameters of a fused RK4 stage epilogue.
 template <typename T>
@@ -108,21 +128,21 @@ __device__ __forceinline__ cx<T> rk4_combine(cx<T> u, cx<T>& a, cx<T> nl, T E, T
 
 // ---------------------------------------------------------------------------
 // Strided passes along y: blocks of [XT][M][16] <-> [XT][N][16].
-// Grid: nblk * XT * SUB blocks, nblk = fields * z extent.
+// rows = fields * z extent; grid xcd_grid(rows, XT * SUB).
 // ---------------------------------------------------------------------------
 template <typename T, int N, bool FULL>
-__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+__global__ void __launch_bounds__((Strided<T, N, kYLines>::THREADS))
     k_y_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-            const cx<T>* __restrict__ tw) {
+            const cx<T>* __restrict__ tw, int rows) {
   using G = Geo<N, FULL>;
-  using C = Strided<T, N>;
+  using C = Strided<T, N, kYLines>;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
   const Twiddles<T, N, false> twr(tw, t);
-  int blk = blockIdx.x;
-  const int sub = blk % C::SUB;
-  blk /= C::SUB;
-  const size_t tile = (size_t)blk;  // = (field*nz + z)*XT + xt
+  int row, rem;
+  if (!xcd_row_block(rows, G::XT * C::SUB, row, rem)) return;  // whole block
+  const int sub = rem % C::SUB;
+  const size_t tile = (size_t)row * G::XT + rem / C::SUB;  // row = field*nz + z
   const cx<T>* src = in + tile * G::M * kTile + sub * C::LB + b;
   cx<T> v[1][8];
 #pragma unroll
@@ -137,18 +157,18 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
 }
 
 template <typename T, int N, bool FULL>
-__global__ void __launch_bounds__((Strided<T, N>::THREADS))
+__global__ void __launch_bounds__((Strided<T, N, kYLines>::THREADS))
     k_y_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-            const cx<T>* __restrict__ tw) {
+            const cx<T>* __restrict__ tw, int rows) {
   using G = Geo<N, FULL>;
-  using C = Strided<T, N>;
+  using C = Strided<T, N, kYLines>;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
   const Twiddles<T, N, false> twr(tw, t);
-  int blk = blockIdx.x;
-  const int sub = blk % C::SUB;
-  blk /= C::SUB;
-  const size_t tile = (size_t)blk;
+  int row, rem;
+  if (!xcd_row_block(rows, G::XT * C::SUB, row, rem)) return;  // whole block
+  const int sub = rem % C::SUB;
+  const size_t tile = (size_t)row * G::XT + rem / C::SUB;  // row = field*nz + z
   const cx<T>* src = in + tile * N * kTile + sub * C::LB + b;
   cx<T> v[1][8];
 #pragma unroll

@@ -31,6 +31,7 @@ struct L3 {
   using G = Geo<N, false>;
   using GF = Geo<N, true>;
   using C = Strided<T, N>;
+  using YC = Strided<T, N, kYLines>;
   using ZC = ZCfg<T, N>;
   using R = RowPairs<N>;
   static cx<T>* A(Plan* p) { return (cx<T>*)p->bufA; }
@@ -39,7 +40,7 @@ struct L3 {
 
   static void p1(Plan* p, const void* state) {
     p->begin(KID_P1);
-    hipLaunchKernelGGL((k3_p1<T, N>), dim3(G::M * G::XT * ZC::SUB), dim3(ZC::THREADS), 0,
+    hipLaunchKernelGGL((k3_p1<T, N>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)), dim3(ZC::THREADS), 0,
                        p->launch, (const cx<T>*)state, A(p),
                        stage_args<T>(p, (void*)state, nullptr));
     launched(p, "k3_p1");
@@ -47,8 +48,8 @@ struct L3 {
   }
   static void yinv(Plan* p) {
     p->begin(KID_YINV);
-    hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(6 * N * G::XT * C::SUB), dim3(C::THREADS),
-                       0, p->launch, (const cx<T>*)A(p), B(p), TW(p));
+    hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(xcd_grid(6 * N, G::XT * YC::SUB)),
+                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), 6 * N);
     launched(p, "k_y_inv");
     p->end(KID_YINV);
   }
@@ -61,15 +62,15 @@ struct L3 {
   }
   static void yfwd(Plan* p) {
     p->begin(KID_YFWD);
-    hipLaunchKernelGGL((k_y_fwd<T, N, false>), dim3(3 * N * G::XT * C::SUB), dim3(C::THREADS),
-                       0, p->launch, (const cx<T>*)A(p), B(p), TW(p));
+    hipLaunchKernelGGL((k_y_fwd<T, N, false>), dim3(xcd_grid(3 * N, G::XT * YC::SUB)),
+                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), 3 * N);
     launched(p, "k_y_fwd");
     p->end(KID_YFWD);
   }
   template <int MODE>
   static void zk(Plan* p, void* state, void* tend, int do_p1) {
     p->begin(KID_Z);
-    hipLaunchKernelGGL((k3_z<T, N, MODE>), dim3(G::M * G::XT * ZC::SUB), dim3(ZC::THREADS), 0,
+    hipLaunchKernelGGL((k3_z<T, N, MODE>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)), dim3(ZC::THREADS), 0,
                        p->launch, (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend),
                        do_p1);
     launched(p, "k3_z");
@@ -102,8 +103,8 @@ struct L3 {
     launched(p, "k3f_z_inv");
     p->end(KID_FFT);
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(N * GF::XT * C::SUB), dim3(C::THREADS), 0,
-                       p->launch, (const cx<T>*)A(p), B(p), TW(p));
+    hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(xcd_grid(N, GF::XT * YC::SUB)),
+                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), N);
     launched(p, "k_y_inv full");
     p->end(KID_FFT);
     p->begin(KID_FFT);
@@ -119,8 +120,8 @@ struct L3 {
     launched(p, "kf_x_r2c");
     p->end(KID_FFT);
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((k_y_fwd<T, N, true>), dim3(N * GF::XT * C::SUB), dim3(C::THREADS), 0,
-                       p->launch, (const cx<T>*)B(p), A(p), TW(p));
+    hipLaunchKernelGGL((k_y_fwd<T, N, true>), dim3(xcd_grid(N, GF::XT * YC::SUB)),
+                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)B(p), A(p), TW(p), N);
     launched(p, "k_y_fwd full");
     p->end(KID_FFT);
     p->begin(KID_FFT);

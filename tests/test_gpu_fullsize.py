@@ -1,0 +1,110 @@
+"""Full-size checks in the configuration the benchmark times (512^3 FP32,
+forced isotropic turbulence, nu = 2e-4, dt = 1e-3, P = 5e-3 on 2 <= |k| <= 3).
+
+At 512^3 a whole FP64 reference step is too costly for a test, so:
+  * transform: sampled coefficients against the oracle's direct DFT sum;
+  * tendency: properties that hold at any size -- the nonlinear term moves no
+    energy, so sum w Re(u* . N) equals the injected power exactly; N is
+    solenoidal and vanishes outside the kept cube;
+  * one step: the energy budget dE/dt = P - 2 nu Z over the step.
+At 256^3 the oracle runs two whole steps of the same recipe."""
+import numpy as np
+import pytest
+
+from helpers import kept_mask, kept_weight, kmesh
+from paper_1807_01769_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NU, DT, POWER = 2e-4, 1e-3, 5e-3
+
+
+@pytest.fixture(scope="module")
+def fs():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1807_01769_amd import fs as _fs
+    return _fs
+
+
+@pytest.fixture(scope="module")
+def u512():
+    return I.random_solenoidal_3d(512, seed=1, dtype=np.complex64)
+
+
+def test_fft_512_sampled_modes(fs, oracle_mod):
+    print("case fft 512^3 sampled", flush=True)
+    n = 512
+    rng = np.random.default_rng(512)
+    phys = rng.standard_normal((n, n, n), dtype=np.float32)
+    with fs.Plan(n, ndim=3, precision="f32") as p:
+        d = torch.from_numpy(phys).cuda()
+        spec = p.fft_forward(d)
+        back = p.fft_inverse(spec)
+        torch.cuda.synchronize()
+        rt = float((back - d).abs().max().cpu())
+        s = spec.cpu().numpy()
+    assert rt <= 1e-5 * float(np.abs(phys).max())
+    p64 = phys.astype(np.float64)
+    scale = np.sqrt(np.mean(p64 ** 2) / n ** 3)  # rms of a coefficient
+    for m in [(0, 0, 0), (1, 0, 0), (0, 255, 0), (17, -5, 200), (256, 3, -256), (170, -170, 170)]:
+        ref = oracle_mod.dft_mode3d(p64, m)
+        got = s[m[2] % n, m[1] % n, m[0]]
+        assert abs(got - ref) <= 2e-5 * scale, (m, got, ref)
+
+
+def test_tendency_512_invariants(fs, u512):
+    print("case tendency 512^3 forced invariants", flush=True)
+    n = 512
+    with fs.Plan(n, ndim=3, precision="f32", nu=NU, dt=DT, forcing_power=POWER) as p:
+        st = torch.from_numpy(u512).cuda()
+        out = p.tendency(st)
+        torch.cuda.synchronize()
+        nh = out.cpu().numpy().astype(np.complex128)
+    u = u512.astype(np.complex128)
+    w = kept_weight(n, 3)
+    injected = float(np.sum(w * np.real(np.conj(u) * nh)))
+    bound = float(np.sqrt(np.sum(w * np.abs(u) ** 2) * np.sum(w * np.abs(nh) ** 2)))
+    print(f"injected {injected:.6e} (P = {POWER}), bound {bound:.3e}", flush=True)
+    assert abs(injected - POWER) <= 1e-5 * bound
+    kx, ky, kz = kmesh(n, 3)
+    div = np.abs(kx * nh[0] + ky * nh[1] + kz * nh[2])
+    kn = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2) * np.sqrt(np.sum(np.abs(nh) ** 2, axis=0))
+    assert div.max() <= 1e-5 * kn.max()
+    assert np.abs(nh[:, ~kept_mask(n, 3)]).max() == 0.0
+
+
+def test_step_512_energy_budget(fs, u512):
+    print("case step 512^3 forced energy budget", flush=True)
+    n = 512
+    with fs.Plan(n, ndim=3, precision="f32", nu=NU, dt=DT, forcing_power=POWER) as p:
+        st = torch.from_numpy(u512).cuda()
+        _, e0, z0 = p.energy_spectrum(st)
+        e0, z0 = float(e0.cpu()), float(z0.cpu())
+        p.step(st, 1)
+        _, e1, z1 = p.energy_spectrum(st)
+        e1, z1 = float(e1.cpu()), float(z1.cpu())
+        assert np.isfinite(e1) and np.isfinite(z1)
+    rate = (e1 - e0) / DT
+    model = POWER - NU * (z0 + z1)
+    print(f"dE/dt {rate:.6e} model {model:.6e}", flush=True)
+    assert abs(rate - model) <= 0.05 * max(abs(POWER), 2 * NU * z0)
+
+
+def test_step_256_forced_vs_oracle(fs, oracle_mod):
+    print("case step 256^3 forced x2 vs oracle", flush=True)
+    n, steps = 256, 2
+    u = I.random_solenoidal_3d(n, seed=1, dtype=np.complex64)
+    with fs.Plan(n, ndim=3, precision="f32", nu=NU, dt=DT, forcing_power=POWER) as p:
+        st = torch.from_numpy(u).cuda()
+        p.step(st, steps)
+        torch.cuda.synchronize()
+        got = st.cpu().numpy().astype(np.complex128)
+    ref = oracle_mod.step3d(u.astype(np.complex128), NU, DT, steps, power=POWER)
+    w = kept_weight(n, 3)
+    m = kept_mask(n, 3)
+    err = np.sqrt(np.sum(w * np.abs(np.where(m, got - ref, 0)) ** 2) /
+                  np.sum(w * np.abs(np.where(m, ref, 0)) ** 2))
+    print(f"256^3 forced 2 steps rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-5

@@ -105,3 +105,14 @@ def test_vs_numpy_fft(oracle_mod, n):
     assert np.abs(s - ref).max() <= 1e-15 * np.abs(ref).max() * 50
     back = oracle_mod.irfftn(ref)
     assert np.abs(back - p).max() <= 1e-13
+
+
+def test_dft_mode3d_vs_bruteforce(oracle_mod):
+    n = 8
+    rng = np.random.default_rng(2)
+    p = rng.standard_normal((n, n, n))
+    ref = brute_dft(p, -1) / n ** 3
+    for m in [(0, 0, 0), (1, 0, 0), (0, 3, 0), (0, 0, 5), (2, -3, 1), (4, 4, -4), (3, 7, 2)]:
+        got = oracle_mod.dft_mode3d(p, m)
+        want = ref[m[2] % n, m[1] % n, m[0] % n]
+        assert abs(got - want) <= 1e-14 * np.abs(ref).max() * 10
