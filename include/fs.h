@@ -65,6 +65,7 @@ enum { FS_F32 = 0, FS_F64 = 1 };
 /* flags */
 #define FS_NO_GRAPH 0x1u /* launch kernels one by one instead of a captured graph */
 #define FS_PROFILE 0x2u  /* time every kernel with events (see fs_profile_read) */
+#define FS_NO_AUTOTUNE 0x4u /* ensembles: keep the default schedules */
 
 typedef struct fs_plan fs_plan;
 
@@ -75,7 +76,7 @@ typedef struct {
   double forcing_power; /* 3D only: constant injected power P; 0 = no forcing */
   double forcing_kmin;  /* forcing band kmin <= |k| <= kmax (default 2, 3) */
   double forcing_kmax;
-  unsigned flags;       /* FS_NO_GRAPH | FS_PROFILE */
+  unsigned flags;       /* FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE */
 } fs_plan_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -175,6 +176,37 @@ fs_status fs_energy_spectrum(fs_plan *plan, const void *state, double *spectrum,
  * 6 fill, 7 transform-only passes, 8 diagnostics.  Any pointer may be NULL.
  */
 fs_status fs_profile_read(fs_plan *plan, double *ms, long *counts, const char **names, int nk);
+
+/*
+ * Ensembles of independent 2D runs of uneven sizes (the 2D benchmark setup
+ * of the paper's "Performance" section, many runs at once), FP32.
+ *
+ * fs_ensemble_create: nruns runs with grid sizes n[r] in {64, 128, 256, 512}
+ * sharing L, nu, dt (opts: ndim must be 2, precision FS_F32, no forcing;
+ * flags FS_NO_GRAPH, FS_NO_AUTOTUNE).  The packed state is the concatenation
+ * of the runs' 2D states, run r at complex offset offsets[r] (see
+ * fs_ensemble_offsets).  Runs of equal size form a class; at creation the
+ * block schedule of every class is chosen by timing candidates on the
+ * device (unless FS_NO_AUTOTUNE).  Owns its workspace.
+ */
+typedef struct fs_ensemble fs_ensemble;
+fs_status fs_ensemble_create(fs_ensemble **out, int nruns, const int *n, double L, double nu,
+                             double dt, const fs_plan_opts *opts);
+/* Host array of nruns + 1 complex offsets; offsets[nruns] is the total size. */
+fs_status fs_ensemble_offsets(const fs_ensemble *ens, int64_t *offsets);
+/*
+ * Advance every run of the packed state (device memory) by nsteps Lawson
+ * IF-RK4 steps, exactly as fs_step_rk4 would advance each run alone.  All
+ * steps of all classes are captured as parallel branches of one hipGraph
+ * and launched once (reused while the pointer and nsteps are unchanged).
+ */
+fs_status fs_ensemble_step_rk4(fs_ensemble *ens, void *packed_state, int nsteps);
+/* Chosen schedule of class cls (classes in increasing size): its size, run
+ * count, y-pass lines per block, x-pass row pairs per block and the tuned
+ * per-launch times in microseconds (0 when taken from the cache). */
+fs_status fs_ensemble_schedule(const fs_ensemble *ens, int cls, int *n, int *nruns, int *y_lines,
+                               int *x_rowpairs, double *us_y, double *us_x);
+fs_status fs_ensemble_destroy(fs_ensemble *ens); /* NULL is a no-op */
 
 /* Status name and last error message of the calling thread. */
 const char *fs_status_str(fs_status s);

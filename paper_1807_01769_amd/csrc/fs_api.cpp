@@ -164,7 +164,7 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   if (o.ndim != 2 && o.ndim != 3) return fail(FS_E_INVALID, "ndim = %d must be 2 or 3", o.ndim);
   if (o.precision != FS_F32 && o.precision != FS_F64)
     return fail(FS_E_INVALID, "precision = %d must be FS_F32 or FS_F64", o.precision);
-  if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE)) return fail(FS_E_INVALID, "unknown flags");
+  if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE)) return fail(FS_E_INVALID, "unknown flags");
   if (!(isfin(o.forcing_power) && o.forcing_power >= 0))
     return fail(FS_E_INVALID, "forcing_power must be finite and >= 0");
   const double kb = 2.0 * M_PI / L;

@@ -10,23 +10,37 @@
 //                  combine -> next stage input -> (u, v, w) -> three inverse
 //                  y transforms                               [k2_y]
 //   X (c2r / r2c)  three C2R, products, two R2C               [k2_x]
+//
+// Every kernel works on a batch of equal-size runs: block b handles part
+// b % bpr of local run b / bpr; the run's state sits at state_off[run] in
+// a packed array (offset 0 without a table) and its workspace at
+// run * stride.  A single plan is the batch of one run.
+//
+// Y passes use LB lines (kx columns) per block, LB * N/8 threads, line
+// mx = part * LB + b of the padded kx range [0, 16 XT); X passes use RP row
+// pairs per block, RP * N/8 threads.
 #pragma once
 #include "ns_common.h"
 
 namespace fs {
 
-// three inverse y transforms of (u, v, w) derived from w_hat held as
-// v[e] at y-position t + e*P of line b (kx = mx); writes Wn[3][XT][N][16]
-template <typename T, int N, class TW>
-__device__ __forceinline__ void y_inverse_three(cx<T> (&w)[8], int t, int b, int xt, int sub,
-                                                int mx, T kb, cx<T>* __restrict__ w1,
-                                                cx<T>* lds, const TW& tw) {
+struct Batch {
+  const long long* state_off;  // per-run state offsets (complex elements) or null
+  size_t in_stride, out_stride, acc_stride;  // per-run workspace strides
+  int bpr;                     // blocks per run
+};
+
+// three inverse y transforms of (u, v, w) derived from w_hat held as w[e]
+// at y-position t + e*P of line b (kx = mx); writes Wn[3][XT][N][16]
+template <typename T, int N, int LB, class TW>
+__device__ __forceinline__ void y_inverse_three(cx<T> (&w)[8], int t, int b, int mx, T kb,
+                                                cx<T>* __restrict__ w1, cx<T>* lds,
+                                                const TW& tw) {
   using G = Geo<N, false>;
-  using C = Strided<T, N>;
   constexpr int P = G::P;
   const size_t fstride = (size_t)G::XT * N * kTile;
-  cx<T>* dst0 = w1 + (size_t)xt * N * kTile + sub * C::LB + b;
-  auto lidx = [=](int, int pos) { return pos * C::LB + b; };
+  cx<T>* dst0 = w1 + (size_t)(mx >> 4) * N * kTile + (mx & 15);
+  auto lidx = [=](int, int pos) { return pos * LB + b; };
   const T kx = kb * (T)mx;
 #pragma unroll
   for (int f = 0; f < 3; f++) {
@@ -48,18 +62,20 @@ __device__ __forceinline__ void y_inverse_three(cx<T> (&w)[8], int t, int b, int
   }
 }
 
-// First pass of a stage from the caller's state; grid XT * SUB.
-template <typename T, int N>
-__global__ void __launch_bounds__((Strided<T, N>::THREADS))
-    k2_p1(const cx<T>* __restrict__ state, cx<T>* __restrict__ w1, StageArgs<T> a) {
+// First pass of a stage from the state: W1 = inverse y transforms of
+// (u, v, w).  Grid: runs * bpr, bpr = 16 XT / LB.
+template <typename T, int N, int LB>
+__global__ void __launch_bounds__(LB * N / 8)
+    k2_p1(const cx<T>* __restrict__ state, cx<T>* __restrict__ w1, StageArgs<T> a, Batch bt) {
   using G = Geo<N, false>;
-  using C = Strided<T, N>;
   constexpr int P = G::P, NH = N / 2 + 1;
-  __shared__ cx<T> lds[C::LB * N];
-  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  __shared__ cx<T> lds[LB * N];
+  const int b = threadIdx.x % LB, t = threadIdx.x / LB;
   const Twiddles<T, N> twr(a.tw, t);
-  const int sub = blockIdx.x % C::SUB, xt = blockIdx.x / C::SUB;
-  const int mx = xt * kTile + sub * C::LB + b;
+  const int run = blockIdx.x / bt.bpr, part = blockIdx.x % bt.bpr;
+  state += bt.state_off ? bt.state_off[run] : 0;
+  w1 += run * bt.out_stride;
+  const int mx = part * LB + b;
   cx<T> w[8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
@@ -67,22 +83,25 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     const bool kept = mx < G::H && G::i2j(iy) >= 0;
     w[e] = kept ? state[(size_t)iy * NH + mx] : cx<T>{0, 0};
   }
-  y_inverse_three<T, N>(w, t, b, xt, sub, mx, a.kb, w1, lds, twr);
+  y_inverse_three<T, N, LB>(w, t, b, mx, a.kb, w1, lds, twr);
 }
 
 // X pass: rows (y0, y0+1); in Wn[3][XT][N][16] (u, v, w), out Wn[2][XT][N][16]
-// ((u w), (v w)) scaled by `scale`.  Grid N/2/RP.
-template <typename T, int N>
-__global__ void __launch_bounds__((RowPairs<N>::THREADS))
+// ((u w), (v w)) scaled by `scale`.  Grid: runs * bpr, bpr = N/2/RP.
+template <typename T, int N, int RP>
+__global__ void __launch_bounds__(RP * N / 8)
     k2_x(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
-         T scale) {
+         T scale, Batch bt) {
   using G = Geo<N, false>;
   using R = RowPairs<N>;
   constexpr int P = G::P;
-  __shared__ cx<T> lds[R::RP * 3 * R::NPAD];
+  __shared__ cx<T> lds[RP * 3 * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
   const Twiddles<T, N> twr(tw, t);
-  const int y0 = 2 * (blockIdx.x * R::RP + rp);
+  const int run = blockIdx.x / bt.bpr, part = blockIdx.x % bt.bpr;
+  in += run * bt.in_stride;
+  out += run * bt.out_stride;
+  const int y0 = 2 * (part * RP + rp);
   cx<T>* my_lds = lds + rp * 3 * R::NPAD;
   auto lidx = [=](int f, int pos) { return f * R::NPAD + R::pad(pos); };
   const size_t fstride = (size_t)G::XT * N * kTile;
@@ -127,27 +146,32 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
 }
 
 // Y pass: forward y transforms of (u w, v w), tendency, RK4 combine and the
-// next stage's inverse transforms.  acc: [XT][M][16].  Grid XT * SUB.
-template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((Strided<T, N>::THREADS))
-    k2_y(const cx<T>* __restrict__ w2, cx<T>* __restrict__ w1, StageArgs<T> a, int do_p1) {
+// next stage's inverse transforms.  acc: [XT][M][16] per run.
+// Grid: runs * bpr, bpr = 16 XT / LB.
+template <typename T, int N, int LB, int MODE>
+__global__ void __launch_bounds__(LB * N / 8)
+    k2_y(const cx<T>* __restrict__ w2, cx<T>* __restrict__ w1, StageArgs<T> a, Batch bt,
+         int do_p1) {
   using G = Geo<N, false>;
-  using C = Strided<T, N>;
   constexpr int P = G::P, NH = N / 2 + 1;
-  __shared__ cx<T> lds[C::LB * N];
-  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  __shared__ cx<T> lds[LB * N];
+  const int b = threadIdx.x % LB, t = threadIdx.x / LB;
   const Twiddles<T, N> twr(a.tw, t);
-  const int sub = blockIdx.x % C::SUB, xt = blockIdx.x / C::SUB;
-  const int mx = xt * kTile + sub * C::LB + b;
-  auto lidx = [=](int, int pos) { return pos * C::LB + b; };
+  const int run = blockIdx.x / bt.bpr, part = blockIdx.x % bt.bpr;
+  w2 += run * bt.in_stride;
+  w1 += run * bt.out_stride;
+  const size_t soff = bt.state_off ? bt.state_off[run] : 0;
+  const int mx = part * LB + b;
+  auto lidx = [=](int, int pos) { return pos * LB + b; };
   const size_t fstride = (size_t)G::XT * N * kTile;
-  const cx<T>* src = w2 + (size_t)xt * N * kTile + sub * C::LB + b;
+  const cx<T>* src = w2 + (size_t)(mx >> 4) * N * kTile + (mx & 15);
   cx<T> f1[1][8], f2[1][8];
 #pragma unroll
-  for (int e = 0; e < 8; e++) f1[0][e] = src[(size_t)(t + e * P) * kTile];
+  for (int e = 0; e < 8; e++) {
+    f1[0][e] = src[(size_t)(t + e * P) * kTile];
+    f2[0][e] = src[fstride + (size_t)(t + e * P) * kTile];
+  }
   fft_lines<T, N, -1, 1>(f1, t, lds, lidx, twr);
-#pragma unroll
-  for (int e = 0; e < 8; e++) f2[0][e] = src[fstride + (size_t)(t + e * P) * kTile];
   fft_lines<T, N, -1, 1>(f2, t, lds, lidx, twr);
 
   const T kx = a.kb * (T)mx;
@@ -164,13 +188,13 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     const T ky = a.kb * (T)my;
     cx<T> nl = {0, 0};
     if (mx != 0 || my != 0) nl = mul_i(cscale(f1[0][e], -kx) - cscale(f2[0][e], ky));
-    const size_t so = (size_t)iy * NH + mx;
+    const size_t so = soff + (size_t)iy * NH + mx;
     if constexpr (MODE == kModeTend) {
       a.tend[so] = nl;
     } else {
       const T E = a.e1[mx] * a.e1[iy];
       const T Eh = a.eh1[mx] * a.eh1[iy];
-      const size_t ao = ((size_t)xt * G::M + jy) * kTile + sub * C::LB + b;
+      const size_t ao = run * bt.acc_stride + ((size_t)(mx >> 4) * G::M + jy) * kTile + (mx & 15);
       cx<T> acc = {0, 0}, u = {0, 0};
       if constexpr (MODE != kStage4) u = a.state[so];
       if constexpr (MODE != kStage1) acc = a.acc[ao];
@@ -183,7 +207,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     }
   }
   if constexpr (MODE != kModeTend) {
-    if (do_p1) y_inverse_three<T, N>(w, t, b, xt, sub, mx, a.kb, w1, lds, twr);
+    if (do_p1) y_inverse_three<T, N, LB>(w, t, b, mx, a.kb, w1, lds, twr);
   }
 }
 

@@ -33,29 +33,33 @@ struct L2 {
   using GF = Geo<N, true>;
   using C = Strided<T, N>;
   using R = RowPairs<N>;
+  static constexpr int LB = C::LB, RP = R::RP;
   static cx<T>* A(Plan* p) { return (cx<T>*)p->bufA; }
   static cx<T>* B(Plan* p) { return (cx<T>*)p->bufB; }
   static const cx<T>* TW(Plan* p) { return (const cx<T>*)p->tw; }
+  static Batch one(int bpr) { return Batch{nullptr, 0, 0, 0, bpr}; }
 
   static void p1(Plan* p, const void* state) {
     p->begin(KID_P1);
-    hipLaunchKernelGGL((k2_p1<T, N>), dim3(G::XT * C::SUB), dim3(C::THREADS), 0, p->launch,
-                       (const cx<T>*)state, A(p), stage_args2<T>(p, (void*)state, nullptr));
+    hipLaunchKernelGGL((k2_p1<T, N, LB>), dim3(G::XT * kTile / LB), dim3(LB * N / 8), 0,
+                       p->launch, (const cx<T>*)state, A(p),
+                       stage_args2<T>(p, (void*)state, nullptr), one(G::XT * kTile / LB));
     launched(p, "k2_p1");
     p->end(KID_P1);
   }
   static void x(Plan* p) {
     p->begin(KID_X);
-    hipLaunchKernelGGL((k2_x<T, N>), dim3(N / 2 / R::RP), dim3(R::THREADS), 0, p->launch,
-                       (const cx<T>*)A(p), B(p), TW(p), (T)(1.0 / ((double)N * N)));
+    hipLaunchKernelGGL((k2_x<T, N, RP>), dim3(N / 2 / RP), dim3(RP * N / 8), 0, p->launch,
+                       (const cx<T>*)A(p), B(p), TW(p), (T)(1.0 / ((double)N * N)), one(N / 2 / RP));
     launched(p, "k2_x");
     p->end(KID_X);
   }
   template <int MODE>
   static void yk(Plan* p, void* state, void* tend, int do_p1) {
     p->begin(KID_Z);
-    hipLaunchKernelGGL((k2_y<T, N, MODE>), dim3(G::XT * C::SUB), dim3(C::THREADS), 0, p->launch,
-                       (const cx<T>*)B(p), A(p), stage_args2<T>(p, state, tend), do_p1);
+    hipLaunchKernelGGL((k2_y<T, N, LB, MODE>), dim3(G::XT * kTile / LB), dim3(LB * N / 8), 0,
+                       p->launch, (const cx<T>*)B(p), A(p), stage_args2<T>(p, state, tend),
+                       one(G::XT * kTile / LB), do_p1);
     launched(p, "k2_y");
     p->end(KID_Z);
   }

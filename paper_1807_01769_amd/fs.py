@@ -212,3 +212,93 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+FS_NO_AUTOTUNE = 0x4
+lib.fs_ensemble_create.argtypes = [C.POINTER(_vp), _i, C.POINTER(_i), _d, _d, _d, C.POINTER(Opts)]
+lib.fs_ensemble_offsets.argtypes = [_vp, C.POINTER(C.c_int64)]
+lib.fs_ensemble_step_rk4.argtypes = [_vp, _vp, _i]
+lib.fs_ensemble_schedule.argtypes = [_vp, _i, C.POINTER(_i), C.POINTER(_i), C.POINTER(_i),
+                                     C.POINTER(_i), C.POINTER(_d), C.POINTER(_d)]
+lib.fs_ensemble_destroy.argtypes = [_vp]
+for _f in ("fs_ensemble_create", "fs_ensemble_offsets", "fs_ensemble_step_rk4",
+           "fs_ensemble_schedule", "fs_ensemble_destroy"):
+    getattr(lib, _f).restype = _i
+
+
+class Ensemble:
+    """Independent 2D FP32 runs of uneven sizes (64/128/256/512) advanced together."""
+
+    def __init__(self, sizes, L: float = 2 * math.pi, nu: float = 0.0, dt: float = 1e-3,
+                 stream=None, autotune: bool = True, graphs: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1807_01769_amd.fs needs a HIP device")
+        self.sizes = [int(s) for s in sizes]
+        o = Opts()
+        lib.fs_plan_opts_default(C.byref(o))
+        o.ndim = 2
+        o.precision = FS_F32
+        o.stream = _stream_ptr(stream)
+        o.flags = (0 if autotune else FS_NO_AUTOTUNE) | (0 if graphs else FS_NO_GRAPH)
+        arr = (_i * len(self.sizes))(*self.sizes)
+        h = _vp()
+        _check(lib.fs_ensemble_create(C.byref(h), len(self.sizes), arr, float(L), float(nu),
+                                      float(dt), C.byref(o)), "fs_ensemble_create")
+        self._h = h
+        off = (C.c_int64 * (len(self.sizes) + 1))()
+        _check(lib.fs_ensemble_offsets(self._h, off), "fs_ensemble_offsets")
+        self.offsets = [int(v) for v in off]
+
+    def new_state(self) -> torch.Tensor:
+        return torch.zeros(self.offsets[-1], dtype=torch.complex64, device="cuda")
+
+    def pack(self, fields) -> torch.Tensor:
+        """Packed device state from per-run [n][n/2+1] arrays (numpy or torch)."""
+        st = self.new_state()
+        for r, f in enumerate(fields):
+            t = torch.as_tensor(f).to(torch.complex64).reshape(-1)
+            st[self.offsets[r]:self.offsets[r + 1]] = t.to(st.device)
+        return st
+
+    def unpack(self, state: torch.Tensor, r: int) -> torch.Tensor:
+        n = self.sizes[r]
+        return state[self.offsets[r]:self.offsets[r + 1]].reshape(n, n // 2 + 1)
+
+    def step(self, state: torch.Tensor, nsteps: int = 1) -> torch.Tensor:
+        if not (state.is_cuda and state.dtype == torch.complex64 and state.is_contiguous()
+                and state.numel() == self.offsets[-1]):
+            raise ValueError("state must be a contiguous complex64 device tensor of the packed size")
+        _check(lib.fs_ensemble_step_rk4(self._h, state.data_ptr(), int(nsteps)),
+               "fs_ensemble_step_rk4")
+        return state
+
+    def schedule(self) -> list:
+        out, c = [], 0
+        while True:
+            n, nr, yl, xr = _i(), _i(), _i(), _i()
+            uy, ux = _d(), _d()
+            st = lib.fs_ensemble_schedule(self._h, c, C.byref(n), C.byref(nr), C.byref(yl),
+                                          C.byref(xr), C.byref(uy), C.byref(ux))
+            if st != FS_OK:
+                break
+            out.append({"n": n.value, "runs": nr.value, "y_lines": yl.value,
+                        "x_rowpairs": xr.value, "us_y": uy.value, "us_x": ux.value})
+            c += 1
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.fs_ensemble_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

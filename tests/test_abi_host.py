@@ -106,3 +106,27 @@ def test_binding_imports_and_needs_device():
         pytest.skip("device present")
     with pytest.raises(RuntimeError):
         fs.Plan(16)
+
+
+@pytest.mark.parametrize("nruns,sizes,kw,expect", [
+    (0, [64], {}, -1),
+    (1, [100], {}, -2),
+    (2, [64, 32], {}, -2),
+    (1, [64], {"precision": 1}, -2),
+    (1, [64], {"ndim": 3}, -1),
+    (1, [64], {"forcing_power": 1.0}, -2),
+    (1, [64], {"flags": 0x2}, -1),
+])
+def test_ensemble_create_validates(lib, nruns, sizes, kw, expect):
+    lib.fs_ensemble_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int),
+                                       C.c_double, C.c_double, C.c_double, C.POINTER(Opts)]
+    lib.fs_plan_opts_default.argtypes = [C.POINTER(Opts)]
+    o = Opts()
+    lib.fs_plan_opts_default(C.byref(o))
+    o.ndim = 2
+    for k, v in kw.items():
+        setattr(o, k, v)
+    arr = (C.c_int * max(1, len(sizes)))(*sizes)
+    h = C.c_void_p()
+    assert lib.fs_ensemble_create(C.byref(h), nruns, arr, 6.28, 1e-3, 1e-3, C.byref(o)) == expect
+    assert not h.value
