@@ -26,6 +26,14 @@ Pins (tests/test_oracle_*.py, all CPU):
   forcing_alpha3d        injected power equals the prescribed power
   diag2d / diag3d        closed-form Taylor-Green energy, enstrophy and shell,
                          sum of the spectrum equals the energy
+  cutoff3d / grad3d      tr A = 0 for solenoidal fields, closed-form gradient
+                         of Taylor-Green, cutoff idempotent and exact on kept
+  sgs_tau3d              zero for band-limited fields, symmetric, traceless,
+                         equals the triad definition on a small grid
+  mlp_forward/loss_grad  central finite differences
+  adam                   closed form of the first step (sign descent by lr)
+  tendency3d_les         zero stress reduces to tendency3d; the stress term
+                         alone equals the projected divergence
 Beyond those pins, long nonlinear runs are "parity unpinned": the reference
 and the GPU path are compared with each other only.
 """
@@ -67,6 +75,15 @@ def lib():
         L.or_kept.restype = i
         L.or_dft_mode3d.argtypes = [i, vp, i, i, i, vp, vp]
         L.or_lawson_scalar.argtypes = [d, d, d, i]
+        L.or_cutoff3d.argtypes = [i, vp, i, vp]
+        L.or_grad3d.argtypes = [i, d, vp, vp]
+        L.or_sgs_tau3d.argtypes = [i, vp, i, vp]
+        L.or_mlp_nparams.restype = i
+        L.or_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
+        L.or_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.or_mlp_loss_grad.restype = d
+        L.or_adam.argtypes = [vp, vp, vp, vp, i, i, d, d, d, d]
+        L.or_tendency3d_les.argtypes = [i, d, vp, vp, vp]
         L.or_lawson_scalar.restype = d
         _LIB = L
     return _LIB
@@ -185,3 +202,74 @@ def dft_mode3d(phys, m):
     re, im = C.c_double(), C.c_double()
     lib().or_dft_mode3d(p.shape[0], _p(p), int(m[0]), int(m[1]), int(m[2]), C.byref(re), C.byref(im))
     return complex(re.value, im.value)
+
+
+# ---- learned closure -------------------------------------------------------
+TAU_COMPONENTS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+
+
+def cutoff3d(fine, nc):
+    """Sharp cube cutoff of a fine spectral field (or [3] stack) to the nc grid."""
+    f = _c128(fine)
+    lead = f.shape[:-3]
+    nf = f.shape[-3]
+    ff = f.reshape((-1,) + f.shape[-3:])
+    out = np.empty((ff.shape[0], nc, nc, nc // 2 + 1), np.complex128)
+    for c in range(ff.shape[0]):
+        fc = np.ascontiguousarray(ff[c])
+        oc = np.empty((nc, nc, nc // 2 + 1), np.complex128)
+        lib().or_cutoff3d(nf, _p(fc), nc, _p(oc))
+        out[c] = oc
+    return out.reshape(lead + (nc, nc, nc // 2 + 1))
+
+
+def grad3d(uh, L=2 * np.pi):
+    """A[3i+j] = d u_i/d x_j on the n^3 grid (9 real fields)."""
+    u = _c128(uh)
+    n = u.shape[1]
+    A = np.empty((9, n, n, n), np.float64)
+    lib().or_grad3d(n, float(L), _p(u), _p(A))
+    return A
+
+
+def sgs_tau3d(uf, nc):
+    """Deviatoric subgrid stress on the nc grid from a fine spectral velocity."""
+    u = _c128(uf)
+    tau = np.empty((6, nc, nc, nc), np.float64)
+    lib().or_sgs_tau3d(u.shape[1], _p(u), nc, _p(tau))
+    return tau
+
+
+def mlp_nparams():
+    return int(lib().or_mlp_nparams())
+
+
+def mlp_forward(params, x):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.empty((xx.shape[0], 6), np.float64)
+    lib().or_mlp_forward(_p(p), _p(xx), xx.shape[0], _p(y))
+    return y
+
+
+def mlp_loss_grad(params, x, t):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    tt = np.ascontiguousarray(t, dtype=np.float64)
+    g = np.empty(p.size, np.float64)
+    loss = lib().or_mlp_loss_grad(_p(p), _p(xx), _p(tt), xx.shape[0], _p(g))
+    return float(loss), g
+
+
+def adam(w, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays w, m, v."""
+    lib().or_adam(_p(w), _p(m), _p(v), _p(np.ascontiguousarray(g, dtype=np.float64)), w.size,
+                  int(step), float(lr), float(b1), float(b2), float(eps))
+
+
+def tendency3d_les(uh, tau, L=2 * np.pi):
+    u = _c128(uh)
+    t = np.ascontiguousarray(tau, dtype=np.float64)
+    out = np.empty_like(u)
+    lib().or_tendency3d_les(u.shape[1], float(L), _p(u), _p(t), _p(out))
+    return out

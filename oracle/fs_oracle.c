@@ -533,3 +533,209 @@ void or_diag2d(int n, double L, const cplx *wh, int nbins, double *spec, double 
   *E = e;
   *Z = z;
 }
+
+/* ======================================================================== */
+/* Learned-closure building blocks (filtered DNS -> coarse LES).              */
+/* A coarse grid nc keeps |m_a| <= Kc = floor((nc-1)/3): exactly its own      */
+/* dealiased set, so the sharp cube cutoff of a fine field is the coarse      */
+/* state.  Stress components are ordered xx, yy, zz, xy, xz, yz.              */
+/* ======================================================================== */
+static const int TAU_I[6] = {0, 1, 2, 0, 0, 1}, TAU_J[6] = {0, 1, 2, 1, 2, 2};
+
+/* sharp cube cutoff: coarse(m) = fine(m) for |m_a| <= Kc, else 0.
+ * fine: [nf][nf][nf/2+1] (one field), coarse: [nc][nc][nc/2+1]. */
+void or_cutoff3d(int nf, const cplx *fine, int nc, cplx *coarse) {
+  const int Kc = (nc - 1) / 3;
+  const int64_t hf = nf / 2 + 1, hc = nc / 2 + 1;
+  for (int iz = 0; iz < nc; iz++)
+    for (int iy = 0; iy < nc; iy++)
+      for (int ix = 0; ix < hc; ix++) {
+        const int mz = mode_full(iz, nc), my = mode_full(iy, nc), mx = ix;
+        cplx v = 0;
+        if (abs(mz) <= Kc && abs(my) <= Kc && mx <= Kc) {
+          const int fz = (mz + nf) % nf, fy = (my + nf) % nf;
+          v = fine[((int64_t)fz * nf + fy) * hf + mx];
+        }
+        coarse[((int64_t)iz * nc + iy) * hc + ix] = v;
+      }
+}
+
+/* A[3i+j] = d u_i / d x_j on the n^3 grid, from the spectral velocity u
+ * [3][n][n][n/2+1] (modes outside the kept cube ignored): C2R of i k_j u_i. */
+void or_grad3d(int n, double L, const cplx *u, double *A) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h, np = (int64_t)n * n * n;
+  const double kb = 2.0 * M_PI / L;
+  cplx *g = malloc(sizeof(cplx) * ns);
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) {
+      for (int64_t q = 0; q < ns; q++) {
+        int iz = (int)(q / (n * h)), iy = (int)((q / h) % n), ix = (int)(q % h);
+        int m[3] = {ix, mode_full(iy, n), mode_full(iz, n)};
+        int keep = keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n);
+        g[q] = keep ? I * kb * m[j] * u[i * ns + q] : 0;
+      }
+      or_irfftn(3, n, g, A + (3 * i + j) * np);
+    }
+  free(g);
+}
+
+/* Subgrid stress on the coarse grid from a fine spectral velocity:
+ * tau_ij = cutoff(u_i u_j) - ubar_i ubar_j at the coarse points, with the
+ * fine product formed on the fine grid; the trace is then removed. */
+void or_sgs_tau3d(int nf, const cplx *uf, int nc, double *tau) {
+  const int64_t hf = nf / 2 + 1, nsf = (int64_t)nf * nf * hf, npf = (int64_t)nf * nf * nf;
+  const int64_t hc = nc / 2 + 1, nsc = (int64_t)nc * nc * hc, npc = (int64_t)nc * nc * nc;
+  double *uphys = malloc(sizeof(double) * 3 * npf), *prod = malloc(sizeof(double) * npf);
+  cplx *pf = malloc(sizeof(cplx) * nsf), *pc = malloc(sizeof(cplx) * nsc);
+  double *ub = malloc(sizeof(double) * 3 * npc);
+  for (int c = 0; c < 3; c++) {
+    /* fine physical velocity (masked to the fine kept set) */
+    cplx *tmp = malloc(sizeof(cplx) * nsf);
+    for (int64_t q = 0; q < nsf; q++) {
+      int iz = (int)(q / (nf * hf)), iy = (int)((q / hf) % nf), ix = (int)(q % hf);
+      int keep = keep1(ix, nf) && keep1(mode_full(iy, nf), nf) && keep1(mode_full(iz, nf), nf);
+      tmp[q] = keep ? uf[c * nsf + q] : 0;
+    }
+    or_irfftn(3, nf, tmp, uphys + c * npf);
+    or_cutoff3d(nf, tmp, nc, pc);
+    or_irfftn(3, nc, pc, ub + c * npc);
+    free(tmp);
+  }
+  for (int s = 0; s < 6; s++) {
+    const int i = TAU_I[s], j = TAU_J[s];
+    for (int64_t q = 0; q < npf; q++) prod[q] = uphys[i * npf + q] * uphys[j * npf + q];
+    or_rfftn(3, nf, prod, pf);
+    or_cutoff3d(nf, pf, nc, pc);
+    or_irfftn(3, nc, pc, tau + s * npc);
+    for (int64_t q = 0; q < npc; q++) tau[s * npc + q] -= ub[i * npc + q] * ub[j * npc + q];
+  }
+  for (int64_t q = 0; q < npc; q++) {
+    const double tr = (tau[q] + tau[npc + q] + tau[2 * npc + q]) / 3.0;
+    for (int s = 0; s < 3; s++) tau[s * npc + q] -= tr;
+  }
+  free(uphys);
+  free(prod);
+  free(pf);
+  free(pc);
+  free(ub);
+}
+
+/* ---- MLP 9 -> 64 -> 64 -> 6 with GELU(x) = x Phi(x) (exact, erf) -------- */
+/* params: W1[64][9] b1[64] W2[64][64] b2[64] W3[6][64] b3[6] (5190 values)  */
+enum { MI = 9, MH = 64, MO = 6 };
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + MH * MI)
+#define OFF_W2 (OFF_B1 + MH)
+#define OFF_B2 (OFF_W2 + MH * MH)
+#define OFF_W3 (OFF_B2 + MH)
+#define OFF_B3 (OFF_W3 + MO * MH)
+#define NPARAM (OFF_B3 + MO)
+
+int or_mlp_nparams(void) { return NPARAM; }
+
+static double gelu(double x) { return 0.5 * x * (1.0 + erf(x / sqrt(2.0))); }
+static double gelu_d(double x) {
+  return 0.5 * (1.0 + erf(x / sqrt(2.0))) + x * exp(-0.5 * x * x) / sqrt(2.0 * M_PI);
+}
+
+/* one point: pre-activations z1, z2, activations h1, h2, output y */
+static void mlp_point(const double *p, const double *x, double *z1, double *h1, double *z2,
+                      double *h2, double *y) {
+  for (int o = 0; o < MH; o++) {
+    double s = p[OFF_B1 + o];
+    for (int k = 0; k < MI; k++) s += p[OFF_W1 + o * MI + k] * x[k];
+    z1[o] = s;
+    h1[o] = gelu(s);
+  }
+  for (int o = 0; o < MH; o++) {
+    double s = p[OFF_B2 + o];
+    for (int k = 0; k < MH; k++) s += p[OFF_W2 + o * MH + k] * h1[k];
+    z2[o] = s;
+    h2[o] = gelu(s);
+  }
+  for (int o = 0; o < MO; o++) {
+    double s = p[OFF_B3 + o];
+    for (int k = 0; k < MH; k++) s += p[OFF_W3 + o * MH + k] * h2[k];
+    y[o] = s;
+  }
+}
+
+void or_mlp_forward(const double *p, const double *x, int64_t P, double *y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < P; q++) {
+    double z1[MH], h1[MH], z2[MH], h2[MH];
+    mlp_point(p, x + q * MI, z1, h1, z2, h2, y + q * MO);
+  }
+}
+
+/* mean squared error over all P*6 outputs and its gradient (back propagation) */
+double or_mlp_loss_grad(const double *p, const double *x, const double *t, int64_t P,
+                        double *grad) {
+  for (int i = 0; i < NPARAM; i++) grad[i] = 0.0;
+  double loss = 0.0;
+  const double scale = 1.0 / ((double)P * MO);
+  for (int64_t q = 0; q < P; q++) {
+    double z1[MH], h1[MH], z2[MH], h2[MH], y[MO], dy[MO], dz2[MH], dz1[MH];
+    mlp_point(p, x + q * MI, z1, h1, z2, h2, y);
+    for (int o = 0; o < MO; o++) {
+      const double d = y[o] - t[q * MO + o];
+      loss += d * d * scale;
+      dy[o] = 2.0 * d * scale;
+      grad[OFF_B3 + o] += dy[o];
+      for (int k = 0; k < MH; k++) grad[OFF_W3 + o * MH + k] += dy[o] * h2[k];
+    }
+    for (int k = 0; k < MH; k++) {
+      double s = 0.0;
+      for (int o = 0; o < MO; o++) s += p[OFF_W3 + o * MH + k] * dy[o];
+      dz2[k] = s * gelu_d(z2[k]);
+      grad[OFF_B2 + k] += dz2[k];
+      for (int m = 0; m < MH; m++) grad[OFF_W2 + k * MH + m] += dz2[k] * h1[m];
+    }
+    for (int k = 0; k < MH; k++) {
+      double s = 0.0;
+      for (int o = 0; o < MH; o++) s += p[OFF_W2 + o * MH + k] * dz2[o];
+      dz1[k] = s * gelu_d(z1[k]);
+      grad[OFF_B1 + k] += dz1[k];
+      for (int m = 0; m < MI; m++) grad[OFF_W1 + k * MI + m] += dz1[k] * x[q * MI + m];
+    }
+  }
+  return loss;
+}
+
+/* Adam (Kingma & Ba): step counts from 1 */
+void or_adam(double *w, double *m, double *v, const double *g, int n, int step, double lr,
+             double b1, double b2, double eps) {
+  const double c1 = 1.0 - pow(b1, step), c2 = 1.0 - pow(b2, step);
+  for (int i = 0; i < n; i++) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+  }
+}
+
+/* LES tendency with a given physical stress: N = P[(u x w)^ - i k_j tau_ij^],
+ * tau: [6][n^3] in xx, yy, zz, xy, xz, yz order. */
+void or_tendency3d_les(int n, double L, const cplx *uh, const double *tau, cplx *nh) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h, np = (int64_t)n * n * n;
+  const double kb = 2.0 * M_PI / L;
+  or_tendency3d(n, L, uh, 0.0, 0.0, 0.0, nh);
+  cplx *th = malloc(sizeof(cplx) * 6 * ns);
+  for (int s = 0; s < 6; s++) or_rfftn(3, n, tau + s * np, th + s * ns);
+  for (int64_t q = 0; q < ns; q++) {
+    int iz = (int)(q / (n * h)), iy = (int)((q / h) % n), ix = (int)(q % h);
+    int m[3] = {ix, mode_full(iy, n), mode_full(iz, n)};
+    if (!(keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n))) continue;
+    double k[3] = {kb * m[0], kb * m[1], kb * m[2]};
+    double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    if (k2 == 0) continue;
+    cplx s[3] = {0, 0, 0};
+    for (int c = 0; c < 6; c++) {
+      const int i = TAU_I[c], j = TAU_J[c];
+      s[i] += -I * k[j] * th[c * ns + q];
+      if (i != j) s[j] += -I * k[i] * th[c * ns + q];
+    }
+    cplx ks = (k[0] * s[0] + k[1] * s[1] + k[2] * s[2]) / k2;
+    for (int c = 0; c < 3; c++) nh[c * ns + q] += s[c] - k[c] * ks;
+  }
+  free(th);
+}

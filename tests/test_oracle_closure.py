@@ -1,0 +1,135 @@
+"""Pins of the FP64 reference closure pieces (CPU only): the sharp cutoff
+filter, velocity gradients, subgrid stress, the MLP and its gradient, Adam,
+and the LES tendency."""
+import numpy as np
+import pytest
+
+from helpers import kept_mask, modes
+from paper_1807_01769_amd import inputs as I
+
+
+def test_cutoff_exact_and_idempotent(oracle_mod):
+    nf, nc = 32, 16
+    u = I.random_solenoidal_3d(nf, seed=21)
+    c = oracle_mod.cutoff3d(u, nc)
+    Kc = (nc - 1) // 3
+    mf, mc = modes(nf), modes(nc)
+    for iz in range(nc):
+        for iy in range(nc):
+            for ix in range(nc // 2 + 1):
+                m = (mc[iz], mc[iy], ix)
+                inside = max(abs(m[0]), abs(m[1]), m[2]) <= Kc
+                want = u[:, m[0] % nf, m[1] % nf, ix] if inside else 0
+                assert np.all(c[:, iz, iy, ix] == want)
+    assert np.array_equal(oracle_mod.cutoff3d(c, nc), c)
+
+
+def test_gradient_closed_form_and_trace(oracle_mod):
+    n = 16
+    A = oracle_mod.grad3d(I.taylor_green_3d(n))
+    x = 2 * np.pi * np.arange(n) / n
+    z, y, xx = np.meshgrid(x, x, x, indexing="ij")
+    # u = (sin x cos y cos z, -cos x sin y cos z, 0)
+    assert np.abs(A[0] - np.cos(xx) * np.cos(y) * np.cos(z)).max() < 1e-14
+    assert np.abs(A[1] + np.sin(xx) * np.sin(y) * np.cos(z)).max() < 1e-14
+    assert np.abs(A[2] + np.sin(xx) * np.cos(y) * np.sin(z)).max() < 1e-14
+    assert np.abs(A[4] + np.cos(xx) * np.cos(y) * np.cos(z)).max() < 1e-14
+    assert np.abs(A[6:]).max() < 1e-14
+    R = oracle_mod.grad3d(I.random_solenoidal_3d(n, seed=5))
+    assert np.abs(R[0] + R[4] + R[8]).max() < 1e-13 * np.abs(R).max()
+
+
+def test_sgs_tau_zero_for_band_limited_field(oracle_mod):
+    nf, nc = 32, 16
+    u = I.random_solenoidal_3d(nf, seed=3)
+    kz, ky, kx = np.meshgrid(modes(nf), modes(nf), np.arange(nf // 2 + 1), indexing="ij")
+    band = (np.abs(kx) <= 2) & (np.abs(ky) <= 2) & (np.abs(kz) <= 2)
+    u = np.where(band[None], u, 0)
+    tau = oracle_mod.sgs_tau3d(u, nc)
+    assert np.abs(tau).max() < 1e-15
+
+
+def test_sgs_tau_matches_galerkin_definition(oracle_mod):
+    """cutoff(u_i u_j) from the exact triad sum of the fine field, evaluated at
+    the coarse points, minus the product of the filtered fields there, trace
+    removed."""
+    from test_oracle_ns import _convolve, _cube_from_half
+    nf, nc = 16, 8
+    Kf, Kc = (nf - 1) // 3, (nc - 1) // 3
+    u = I.random_solenoidal_3d(nf, seed=4, shape_fn=lambda k: np.exp(-0.2 * k))
+    tau = oracle_mod.sgs_tau3d(u, nc)
+    uc = _cube_from_half(u, nf, 3)  # [3][x][y][z], modes -Kf..Kf
+    x = 2 * np.pi * np.arange(nc) / nc
+    z, y, xx = np.meshgrid(x, x, x, indexing="ij")
+
+    def at_points(cube, K):  # sum of the cube's coefficients |m_a| <= Kc at the coarse points
+        out = np.zeros((nc, nc, nc), np.complex128)
+        for a in range(-Kc, Kc + 1):
+            for b in range(-Kc, Kc + 1):
+                for c in range(-Kc, Kc + 1):
+                    v = cube[a + K, b + K, c + K]
+                    if v != 0:
+                        out += v * np.exp(1j * (a * xx + b * y + c * z))
+        return out.real
+
+    ubar = [at_points(uc[c], Kf) for c in range(3)]
+    raw = []
+    for (i, j) in oracle_mod.TAU_COMPONENTS:
+        prod = _convolve(uc[i], uc[j], Kf, 3)  # modes -Kf..Kf of u_i u_j (exact)
+        raw.append(at_points(prod, Kf) - ubar[i] * ubar[j])
+    tr = (raw[0] + raw[1] + raw[2]) / 3.0
+    for s in range(6):
+        ref = raw[s] - (tr if s < 3 else 0.0)
+        assert np.abs(tau[s] - ref).max() <= 1e-12 * np.abs(ref).max() + 1e-16
+
+
+def test_mlp_gradient_matches_finite_differences(oracle_mod):
+    rng = np.random.default_rng(0)
+    npar = oracle_mod.mlp_nparams()
+    assert npar == 5190
+    p = rng.standard_normal(npar) * 0.3
+    x = rng.standard_normal((7, 9))
+    t = rng.standard_normal((7, 6))
+    loss, g = oracle_mod.mlp_loss_grad(p, x, t)
+    y = oracle_mod.mlp_forward(p, x)
+    assert abs(loss - np.mean((y - t) ** 2)) <= 1e-14 * loss
+    h = 1e-6
+    for idx in list(rng.choice(npar, 40, replace=False)) + [0, 575, 576, 639, 640, 4799, 4800, 5183, 5189]:
+        pp, pm = p.copy(), p.copy()
+        pp[idx] += h
+        pm[idx] -= h
+        fd = (oracle_mod.mlp_loss_grad(pp, x, t)[0] - oracle_mod.mlp_loss_grad(pm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-7 * max(1.0, abs(g[idx])) + 1e-9, idx
+
+
+def test_adam_first_step_closed_form(oracle_mod):
+    g = np.array([0.5, -2.0, 1e-3, -7.0])
+    w = np.zeros(4)
+    m = np.zeros(4)
+    v = np.zeros(4)
+    oracle_mod.adam(w, m, v, g, 1, lr=1e-2)
+    # m_hat = g, v_hat = g^2: the step is lr * g / (|g| + eps)
+    assert np.allclose(w, -1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-14, atol=0)
+
+
+def test_les_tendency_reductions(oracle_mod):
+    n = 16
+    u = I.random_solenoidal_3d(n, seed=8)
+    zero = np.zeros((6, n, n, n))
+    assert np.array_equal(oracle_mod.tendency3d_les(u, zero), oracle_mod.tendency3d(u))
+    # isotropic stress is a pressure: projected away
+    iso = np.zeros((6, n, n, n))
+    rng = np.random.default_rng(1)
+    iso[0] = iso[1] = iso[2] = rng.standard_normal((n, n, n))
+    nz = np.zeros_like(u)
+    assert np.abs(oracle_mod.tendency3d_les(nz, iso)).max() < 1e-15
+    # tau_xy = sin y: -d_j tau_ij = (-cos y, 0, 0), already solenoidal
+    x = 2 * np.pi * np.arange(n) / n
+    z, y, xx = np.meshgrid(x, x, x, indexing="ij")
+    t = np.zeros((6, n, n, n))
+    t[3] = np.sin(y)
+    got = oracle_mod.tendency3d_les(nz, t)
+    ref = np.zeros_like(got)
+    ref[0, 0, 1, 0] = -0.5
+    ref[0, 0, n - 1, 0] = -0.5
+    assert np.abs(got - ref).max() < 1e-15
