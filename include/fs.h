@@ -208,6 +208,41 @@ fs_status fs_ensemble_schedule(const fs_ensemble *ens, int cls, int *n, int *nru
                                int *x_rowpairs, double *us_y, double *us_x);
 fs_status fs_ensemble_destroy(fs_ensemble *ens); /* NULL is a no-op */
 
+/*
+ * Learned subgrid-stress closure network (a small MLP: 9 filtered velocity
+ * gradients -> 6 deviatoric subgrid stresses, two hidden layers of 64 with
+ * GELU(x) = x Phi(x)), evaluated and trained with BF16 matrix-core products
+ * accumulated in FP32; FP32 master weights and Adam moments.
+ *
+ * Parameter vector (FP32, fs_mlp_nparams() = 5190 values):
+ *   W1[64][9] b1[64] W2[64][64] b2[64] W3[6][64] b3[6]   (W[out][in]).
+ * Features: BF16 [npts][16], the 9 inputs in slots 0..8, slots 9..15 zero.
+ * Targets and outputs: FP32 [npts][6].  All arrays are device memory.
+ * The network owns its parameters, moments and scratch (allocated once).
+ */
+typedef struct fs_mlp fs_mlp;
+/* Xavier-uniform weights from a counter-based hash of (seed, index), zero
+ * biases; work is enqueued on `stream` (hipStream_t, NULL = null stream). */
+fs_status fs_mlp_create(fs_mlp **out, uint64_t seed, void *stream);
+fs_status fs_mlp_destroy(fs_mlp *net); /* NULL is a no-op */
+fs_status fs_mlp_nparams(int *n);
+/* Copy the FP32 master parameters from / to device memory (set resets Adam's
+ * step count, not its moments). */
+fs_status fs_mlp_set_params(fs_mlp *net, const float *params);
+fs_status fs_mlp_get_params(const fs_mlp *net, float *params);
+/* y = net(x) for npts points. */
+fs_status fs_mlp_forward(fs_mlp *net, const void *x_bf16, float *y, int64_t npts);
+/* Gradient of the mean squared error over all npts*6 outputs into grad
+ * (5190 floats, device) and the loss into *loss (device double, nullable);
+ * reduced deterministically. */
+fs_status fs_mlp_grad(fs_mlp *net, const void *x_bf16, const float *y_target, int64_t npts,
+                      float *grad, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * gradient of the batch; *loss (nullable) receives the batch loss before
+ * the step. */
+fs_status fs_mlp_train_step(fs_mlp *net, const void *x_bf16, const float *y_target, int64_t npts,
+                            float lr, double *loss);
+
 /* Status name and last error message of the calling thread. */
 const char *fs_status_str(fs_status s);
 const char *fs_last_error(void);

@@ -302,3 +302,87 @@ class Ensemble:
 
     def __exit__(self, *exc):
         self.close()
+
+
+lib.fs_mlp_create.argtypes = [C.POINTER(_vp), C.c_uint64, _vp]
+lib.fs_mlp_destroy.argtypes = [_vp]
+lib.fs_mlp_nparams.argtypes = [C.POINTER(_i)]
+lib.fs_mlp_set_params.argtypes = [_vp, _vp]
+lib.fs_mlp_get_params.argtypes = [_vp, _vp]
+lib.fs_mlp_forward.argtypes = [_vp, _vp, _vp, C.c_int64]
+lib.fs_mlp_grad.argtypes = [_vp, _vp, _vp, C.c_int64, _vp, _vp]
+lib.fs_mlp_train_step.argtypes = [_vp, _vp, _vp, C.c_int64, C.c_float, _vp]
+for _f in ("fs_mlp_create", "fs_mlp_destroy", "fs_mlp_nparams", "fs_mlp_set_params",
+           "fs_mlp_get_params", "fs_mlp_forward", "fs_mlp_grad", "fs_mlp_train_step"):
+    getattr(lib, _f).restype = _i
+
+
+def bf16_features(x) -> torch.Tensor:
+    """[P][9] float array -> device BF16 [P][16] feature tensor (zero padded)."""
+    t = torch.as_tensor(x, dtype=torch.float32)
+    out = torch.zeros((t.shape[0], 16), dtype=torch.bfloat16)
+    out[:, :9] = t.to(torch.bfloat16)
+    return out.cuda()
+
+
+class Mlp:
+    """The 9-64-64-6 GELU closure network on BF16 matrix cores."""
+
+    def __init__(self, seed: int = 7, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1807_01769_amd.fs needs a HIP device")
+        h = _vp()
+        _check(lib.fs_mlp_create(C.byref(h), int(seed), _stream_ptr(stream)), "fs_mlp_create")
+        self._h = h
+        n = _i()
+        _check(lib.fs_mlp_nparams(C.byref(n)), "fs_mlp_nparams")
+        self.nparams = n.value
+
+    def get_params(self) -> torch.Tensor:
+        p = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        _check(lib.fs_mlp_get_params(self._h, p.data_ptr()), "fs_mlp_get_params")
+        return p
+
+    def set_params(self, p: torch.Tensor) -> None:
+        p = p.to(device="cuda", dtype=torch.float32).contiguous()
+        if p.numel() != self.nparams:
+            raise ValueError("wrong parameter count")
+        _check(lib.fs_mlp_set_params(self._h, p.data_ptr()), "fs_mlp_set_params")
+        torch.cuda.synchronize()
+
+    def _x(self, x):
+        if not (x.is_cuda and x.dtype == torch.bfloat16 and x.dim() == 2 and x.shape[1] == 16
+                and x.is_contiguous()):
+            raise ValueError("features must be a contiguous device bfloat16 [P][16] tensor")
+        return x.data_ptr()
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device="cuda")
+        _check(lib.fs_mlp_forward(self._h, self._x(x), y.data_ptr(), x.shape[0]), "fs_mlp_forward")
+        return y
+
+    def grad(self, x: torch.Tensor, t: torch.Tensor):
+        t = t.contiguous()
+        g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        _check(lib.fs_mlp_grad(self._h, self._x(x), t.data_ptr(), x.shape[0], g.data_ptr(),
+                               loss.data_ptr()), "fs_mlp_grad")
+        return g, loss
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, lr: float = 1e-3) -> torch.Tensor:
+        t = t.contiguous()
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        _check(lib.fs_mlp_train_step(self._h, self._x(x), t.data_ptr(), x.shape[0], float(lr),
+                                     loss.data_ptr()), "fs_mlp_train_step")
+        return loss
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.fs_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
