@@ -34,6 +34,13 @@ Pins (tests/test_oracle_*.py, all CPU):
   adam                   closed form of the first step (sign descent by lr)
   tendency3d_les         zero stress reduces to tendency3d; the stress term
                          alone equals the projected divergence
+  round_bf16             ties-to-even cases, torch's bfloat16 conversion
+  les_tendency3d         an exactly linear network (GELU(z) - GELU(-z) = z)
+                         that outputs the eddy-viscosity stress
+                         -nu_e (A + A^T) gives tendency3d - nu_e |k|^2 u
+  step3d_les             that network reproduces step3d at nu + nu_e (to the
+                         scheme's order); zero or isotropic output leaves
+                         step3d unchanged
 Beyond those pins, long nonlinear runs are "parity unpinned": the reference
 and the GPU path are compared with each other only.
 """
@@ -85,6 +92,12 @@ def lib():
         L.or_adam.argtypes = [vp, vp, vp, vp, i, i, d, d, d, d]
         L.or_tendency3d_les.argtypes = [i, d, vp, vp, vp]
         L.or_lawson_scalar.restype = d
+        L.or_round_bf16.argtypes = [d]
+        L.or_round_bf16.restype = d
+        L.or_round_bf16_array.argtypes = [vp, C.c_int64]
+        L.or_les_tau3d.argtypes = [i, d, vp, vp, d, vp, d, i, vp]
+        L.or_les_tendency3d.argtypes = [i, d, vp, d, d, d, vp, d, vp, d, i, vp]
+        L.or_step3d_les.argtypes = [i, d, d, d, d, d, d, vp, d, vp, d, i, vp, i]
         _LIB = L
     return _LIB
 
@@ -273,3 +286,49 @@ def tendency3d_les(uh, tau, L=2 * np.pi):
     out = np.empty_like(u)
     lib().or_tendency3d_les(u.shape[1], float(L), _p(u), _p(t), _p(out))
     return out
+
+
+def round_bf16(x):
+    """Nearest BF16 value (8 significant bits, ties to even), as float64."""
+    a = np.array(x, dtype=np.float64, copy=True, order="C")
+    lib().or_round_bf16_array(_p(a), a.size)
+    return a
+
+
+def _net_args(params, a_scale, tau_scale):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    ts = np.ascontiguousarray(tau_scale, dtype=np.float64)
+    assert p.size == mlp_nparams() and ts.size == 6 and a_scale > 0
+    return p, ts
+
+
+def les_tau3d(uh, params, a_scale, tau_scale, clip=0.0, bf16=True, L=2 * np.pi):
+    """Network stress tau_s = clip(net(A / a_scale))_s * tau_scale[s], [6][n^3]."""
+    u = _c128(uh)
+    n = u.shape[1]
+    p, ts = _net_args(params, a_scale, tau_scale)
+    tau = np.empty((6, n, n, n), np.float64)
+    lib().or_les_tau3d(n, float(L), _p(u), _p(p), float(a_scale), _p(ts), float(clip), int(bf16),
+                       _p(tau))
+    return tau
+
+
+def les_tendency3d(uh, params, a_scale, tau_scale, clip=0.0, bf16=True, L=2 * np.pi,
+                   alpha=0.0, kf_min=2.0, kf_max=3.0):
+    u = _c128(uh)
+    p, ts = _net_args(params, a_scale, tau_scale)
+    out = np.empty_like(u)
+    lib().or_les_tendency3d(u.shape[1], float(L), _p(u), float(alpha), float(kf_min),
+                            float(kf_max), _p(p), float(a_scale), _p(ts), float(clip), int(bf16),
+                            _p(out))
+    return out
+
+
+def step3d_les(uh, nu, dt, nsteps, params, a_scale, tau_scale, clip=0.0, bf16=True,
+               L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0):
+    u = _c128(uh).copy()
+    p, ts = _net_args(params, a_scale, tau_scale)
+    lib().or_step3d_les(u.shape[1], float(L), float(nu), float(dt), float(power), float(kf_min),
+                        float(kf_max), _p(p), float(a_scale), _p(ts), float(clip), int(bf16),
+                        _p(u), int(nsteps))
+    return u

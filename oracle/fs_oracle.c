@@ -713,12 +713,11 @@ void or_adam(double *w, double *m, double *v, const double *g, int n, int step, 
   }
 }
 
-/* LES tendency with a given physical stress: N = P[(u x w)^ - i k_j tau_ij^],
- * tau: [6][n^3] in xx, yy, zz, xy, xz, yz order. */
-void or_tendency3d_les(int n, double L, const cplx *uh, const double *tau, cplx *nh) {
+/* P[-i k_j tau_ij^] added to nh on the kept set, k != 0 (tau physical,
+ * [6][n^3], xx, yy, zz, xy, xz, yz order) */
+static void add_sgs(int n, double L, const double *tau, cplx *nh) {
   const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h, np = (int64_t)n * n * n;
   const double kb = 2.0 * M_PI / L;
-  or_tendency3d(n, L, uh, 0.0, 0.0, 0.0, nh);
   cplx *th = malloc(sizeof(cplx) * 6 * ns);
   for (int s = 0; s < 6; s++) or_rfftn(3, n, tau + s * np, th + s * ns);
   for (int64_t q = 0; q < ns; q++) {
@@ -738,4 +737,105 @@ void or_tendency3d_les(int n, double L, const cplx *uh, const double *tau, cplx 
     for (int c = 0; c < 3; c++) nh[c * ns + q] += s[c] - k[c] * ks;
   }
   free(th);
+}
+
+/* LES tendency with a given physical stress: N = P[(u x w)^ - i k_j tau_ij^],
+ * tau: [6][n^3] in xx, yy, zz, xy, xz, yz order. */
+void or_tendency3d_les(int n, double L, const cplx *uh, const double *tau, cplx *nh) {
+  or_tendency3d(n, L, uh, 0.0, 0.0, 0.0, nh);
+  add_sgs(n, L, tau, nh);
+}
+
+/* Round to the nearest BF16 value (8 significant bits), ties to even; the
+ * closure stores its features in this format.  Normal range only. */
+double or_round_bf16(double x) {
+  if (x == 0.0 || !isfinite(x)) return x;
+  int e;
+  const double f = frexp(x, &e); /* x = f 2^e, 0.5 <= |f| < 1 */
+  return ldexp(nearbyint(ldexp(f, 8)), e - 8);
+}
+
+void or_round_bf16_array(double *x, int64_t n) {
+  for (int64_t i = 0; i < n; i++) x[i] = or_round_bf16(x[i]);
+}
+
+/* The network's stress for a coarse spectral velocity: features
+ * x_k = A_k / a_scale (A = or_grad3d, optionally rounded to BF16), outputs
+ * y = MLP(x), tau_s = clip(y_s) tau_scale[s] (clip <= 0: none). */
+struct les_net {
+  const double *params, *tau_scale;
+  double a_scale, clip;
+  int round_bf16;
+};
+
+static void les_tau(int n, double L, const cplx *uh, const struct les_net *net, double *tau) {
+  const int64_t np = (int64_t)n * n * n;
+  double *A = malloc(sizeof(double) * 9 * np), *x = malloc(sizeof(double) * MI * np);
+  double *y = malloc(sizeof(double) * MO * np);
+  or_grad3d(n, L, uh, A);
+  for (int64_t q = 0; q < np; q++)
+    for (int k = 0; k < MI; k++) {
+      const double v = A[k * np + q] / net->a_scale;
+      x[q * MI + k] = net->round_bf16 ? or_round_bf16(v) : v;
+    }
+  or_mlp_forward(net->params, x, np, y);
+  for (int64_t q = 0; q < np; q++)
+    for (int s = 0; s < MO; s++) {
+      double v = y[q * MO + s];
+      if (net->clip > 0) v = fmin(fmax(v, -net->clip), net->clip);
+      tau[s * np + q] = v * net->tau_scale[s];
+    }
+  free(A);
+  free(x);
+  free(y);
+}
+
+void or_les_tau3d(int n, double L, const cplx *uh, const double *params, double a_scale,
+                  const double *tau_scale, double clip, int round_bf16, double *tau) {
+  struct les_net net = {params, tau_scale, a_scale, clip, round_bf16};
+  les_tau(n, L, uh, &net, tau);
+}
+
+/* LES nonlinear term with the network closure: the resolved tendency
+ * (forcing coefficient alpha on the band) plus P[-i k_j tau_ij^]. */
+void or_les_tendency3d(int n, double L, const cplx *uh, double alpha, double kf_min,
+                       double kf_max, const double *params, double a_scale,
+                       const double *tau_scale, double clip, int round_bf16, cplx *nh) {
+  const int64_t np = (int64_t)n * n * n;
+  struct les_net net = {params, tau_scale, a_scale, clip, round_bf16};
+  double *tau = malloc(sizeof(double) * 6 * np);
+  les_tau(n, L, uh, &net, tau);
+  or_tendency3d(n, L, uh, alpha, kf_min, kf_max, nh);
+  add_sgs(n, L, tau, nh);
+  free(tau);
+}
+
+struct les_ctx {
+  struct grid_ctx g;
+  struct les_net net;
+};
+
+static void tend_les(const cplx *u, cplx *out, void *ctx) {
+  struct les_ctx *c = ctx;
+  or_les_tendency3d(c->g.n, c->g.L, u, c->g.alpha, c->g.kf_min, c->g.kf_max, c->net.params,
+                    c->net.a_scale, c->net.tau_scale, c->net.clip, c->net.round_bf16, out);
+}
+
+static void alpha_les(const cplx *u, void *ctx) { alpha3(u, &((struct les_ctx *)ctx)->g); }
+
+/* LES steps: the Lawson RK4 scheme of or_step3d with the closure term. */
+void or_step3d_les(int n, double L, double nu, double dt, double power, double kf_min,
+                   double kf_max, const double *params, double a_scale, const double *tau_scale,
+                   double clip, int round_bf16, cplx *uh, int nsteps) {
+  struct les_ctx c = {{n, L, 0.0, power, kf_min, kf_max},
+                      {params, tau_scale, a_scale, clip, round_bf16}};
+  const int64_t nf = (int64_t)n * n * (n / 2 + 1);
+  double *E = malloc(sizeof(double) * nf), *Eh = malloc(sizeof(double) * nf);
+  for (int64_t i = 0; i < nf; i++) {
+    E[i] = decay(3, n, L, nu, dt, i);
+    Eh[i] = decay(3, n, L, nu, 0.5 * dt, i);
+  }
+  lawson_rk4(nf, 3, E, Eh, dt, uh, nsteps, tend_les, alpha_les, &c);
+  free(E);
+  free(Eh);
 }

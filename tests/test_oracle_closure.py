@@ -133,3 +133,114 @@ def test_les_tendency_reductions(oracle_mod):
     ref[0, 0, 1, 0] = -0.5
     ref[0, 0, n - 1, 0] = -0.5
     assert np.abs(got - ref).max() < 1e-15
+
+
+# ---- LES with the network closure -------------------------------------------
+def linear_eddy_net(npar):
+    """Parameters of a network that is exactly linear, y = C x: the pair
+    GELU(z) - GELU(-z) = z carries each feature through both hidden layers.
+    C maps the standardised gradients to -(A + A^T) in xx, yy, zz, xy, xz, yz
+    order, so with tau_scale = nu_e * a_scale the stress is the eddy-viscosity
+    stress -nu_e (A + A^T)."""
+    W1 = np.zeros((64, 9))
+    W2 = np.zeros((64, 64))
+    W3 = np.zeros((6, 64))
+    for k in range(9):
+        W1[2 * k, k], W1[2 * k + 1, k] = 1.0, -1.0
+        W2[2 * k, 2 * k], W2[2 * k, 2 * k + 1] = 1.0, -1.0
+        W2[2 * k + 1, 2 * k], W2[2 * k + 1, 2 * k + 1] = -1.0, 1.0
+    Cm = np.zeros((6, 9))
+    Cm[0, 0] = Cm[1, 4] = Cm[2, 8] = -2.0
+    Cm[3, 1] = Cm[3, 3] = -1.0
+    Cm[4, 2] = Cm[4, 6] = -1.0
+    Cm[5, 5] = Cm[5, 7] = -1.0
+    for k in range(9):
+        W3[:, 2 * k], W3[:, 2 * k + 1] = Cm[:, k], -Cm[:, k]
+    p = np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3.ravel(), np.zeros(6)])
+    assert p.size == npar
+    return p
+
+
+def test_round_bf16_ties_and_torch(oracle_mod):
+    import torch
+    e = 2.0 ** -8
+    cases = {1 + e: 1.0, 1 + 3 * e: 1 + 4 * e, 1 + e + 2.0 ** -20: 1 + 2 * e,
+             -(1 + 3 * e): -(1 + 4 * e), 0.0: 0.0, 3.0: 3.0, 2.0 ** -30 * (1 + e): 2.0 ** -30}
+    for x, want in cases.items():
+        assert oracle_mod.round_bf16(x) == want, x
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal(20000) * np.exp(rng.uniform(-8, 8, 20000))).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(oracle_mod.round_bf16(x.astype(np.float64)), ref)
+
+
+def test_linear_network_is_exactly_linear(oracle_mod):
+    p = linear_eddy_net(oracle_mod.mlp_nparams())
+    x = np.random.default_rng(0).standard_normal((50, 9)) * 3
+    y = oracle_mod.mlp_forward(p, x)
+    assert np.abs(y[:, 0] + 2 * x[:, 0]).max() < 1e-14 * 10
+    assert np.abs(y[:, 3] + x[:, 1] + x[:, 3]).max() < 1e-14 * 10
+    assert np.abs(y[:, 5] + x[:, 5] + x[:, 7]).max() < 1e-14 * 10
+
+
+def test_les_tendency_eddy_viscosity_closed_form(oracle_mod):
+    """-d_j tau_ij with tau = -nu_e (A + A^T) is nu_e lap u for a solenoidal u."""
+    n, nu_e, a = 16, 0.03, 1.7
+    u = I.random_solenoidal_3d(n, seed=12) * kept_mask(n, 3)[None]
+    p = linear_eddy_net(oracle_mod.mlp_nparams())
+    got = oracle_mod.les_tendency3d(u, p, a, [nu_e * a] * 6, bf16=False)
+    base = oracle_mod.tendency3d(u)
+    kz, ky, kx = np.meshgrid(modes(n), modes(n), np.arange(n // 2 + 1), indexing="ij")
+    k2 = (kx ** 2 + ky ** 2 + kz ** 2).astype(np.float64)
+    want = base - nu_e * k2[None] * u
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    # the same with forcing on: the forcing term is untouched by the closure
+    alpha = 0.37
+    got_f = oracle_mod.les_tendency3d(u, p, a, [nu_e * a] * 6, bf16=False, alpha=alpha)
+    want_f = oracle_mod.tendency3d(u, alpha=alpha) - nu_e * k2[None] * u
+    assert np.abs(got_f - want_f).max() <= 1e-13 * np.abs(want_f).max()
+
+
+def test_les_step_eddy_viscosity_equals_higher_viscosity(oracle_mod):
+    """LES with the eddy-viscosity network = DNS at nu + nu_e up to the
+    scheme's error (the extra viscosity is explicit in one and exact in the
+    other): over 5 steps the gap shrinks as dt^5, fourth order globally."""
+    n, nu, nu_e, a = 16, 0.01, 0.02, 1.0
+    u0 = I.random_solenoidal_3d(n, seed=13) * kept_mask(n, 3)[None]
+    p = linear_eddy_net(oracle_mod.mlp_nparams())
+    errs = []
+    for dt in (2e-3, 4e-3):
+        les = oracle_mod.step3d_les(u0, nu, dt, 5, p, a, [nu_e * a] * 6, bf16=False, power=1e-2)
+        dns = oracle_mod.step3d(u0, nu + nu_e, dt, 5, power=1e-2)
+        errs.append(np.linalg.norm(les - dns) / np.linalg.norm(dns))
+    ref = oracle_mod.step3d(u0, nu, 4e-3, 5, power=1e-2)
+    effect = np.linalg.norm(ref - dns) / np.linalg.norm(dns)
+    assert effect > 1e-3          # the closure does something
+    assert errs[0] < 2e-12, errs
+    assert 25 < errs[1] / errs[0] < 40, errs
+
+
+def test_les_step_null_and_isotropic_outputs(oracle_mod):
+    n, nu, dt = 16, 0.01, 2e-3
+    u0 = I.random_solenoidal_3d(n, seed=14) * kept_mask(n, 3)[None]
+    npar = oracle_mod.mlp_nparams()
+    rng = np.random.default_rng(2)
+    p = rng.standard_normal(npar) * 0.2
+    p[4800:5190] = 0.0           # W3 = 0, b3 = 0: zero stress
+    ref = oracle_mod.step3d(u0, nu, dt, 3, power=1e-2)
+    out = oracle_mod.step3d_les(u0, nu, dt, 3, p, 1.0, [1.0] * 6, power=1e-2)
+    assert np.array_equal(out, ref)
+    p[5184:5187] = 4.0           # b3 = (4, 4, 4, 0, 0, 0): a uniform pressure
+    out = oracle_mod.step3d_les(u0, nu, dt, 3, p, 1.0, [0.5] * 6, power=1e-2)
+    assert np.abs(out - ref).max() <= 1e-15 * np.abs(ref).max()
+
+
+def test_les_tau_clip_and_scale(oracle_mod):
+    n = 8
+    u = I.random_solenoidal_3d(n, seed=15)
+    p = np.zeros(oracle_mod.mlp_nparams())
+    p[5184:5190] = [3.0, -3.0, 0.5, -0.25, 2.0, -0.999]
+    ts = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0])
+    tau = oracle_mod.les_tau3d(u, p, 1.0, ts, clip=1.0)
+    want = np.array([1.0, -1.0, 0.5, -0.25, 1.0, -0.999]) * ts
+    assert np.array_equal(tau.reshape(6, -1), np.repeat(want[:, None], n ** 3, axis=1))
