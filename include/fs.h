@@ -243,6 +243,57 @@ fs_status fs_mlp_grad(fs_mlp *net, const void *x_bf16, const float *y_target, in
 fs_status fs_mlp_train_step(fs_mlp *net, const void *x_bf16, const float *y_target, int64_t npts,
                             float lr, double *loss);
 
+/*
+ * Filtered-DNS training samples for the closure.  The coarse grid nc < nf
+ * keeps |m_a| <= Kc = floor((nc-1)/3): the sharp cube cutoff of a fine state
+ * IS a coarse state, so filtered DNS and LES share one space.  Both plans are
+ * 3D FS_F32 with the same L, on one device and one stream; the object owns
+ * fine and coarse scratch (about 4 fine physical fields), allocated once.
+ */
+typedef struct fs_closure fs_closure;
+fs_status fs_closure_create(fs_closure **out, fs_plan *fine, fs_plan *coarse);
+fs_status fs_closure_destroy(fs_closure *c); /* NULL is a no-op */
+/*
+ * From a fine state ([3][nf][nf][nf/2+1], modes outside its kept set
+ * ignored):
+ *   coarse_state [3][nc][nc][nc/2+1]: the cutoff (every element written);
+ *   A   real[9][nc^3]: A[3i+j] = d ubar_i / d x_j at the coarse points;
+ *   tau real[6][nc^3]: tau_ij = cutoff(u_i u_j) - ubar_i ubar_j, with the
+ *       fine product formed on the fine grid, trace removed; order xx, yy,
+ *       zz, xy, xz, yz.
+ */
+fs_status fs_closure_samples(fs_closure *c, const void *fine_state, void *coarse_state, float *A,
+                             float *tau);
+/* msq (device double[15]): mean squares over the coarse grid of the 9 A
+ * fields then the 6 tau fields (fixed summation order). */
+fs_status fs_closure_moments(fs_closure *c, const float *A, const float *tau, double *msq);
+/* Network inputs and targets: x_bf16 [nc^3][16] = BF16(A_k / a_scale) in
+ * slots 0..8 (rest zero); with tau (then t too, and host tau_scale[6]),
+ * t [nc^3][6] = tau_s / tau_scale[s].  Scales must be > 0. */
+fs_status fs_closure_features(fs_closure *c, const float *A, const float *tau, float a_scale,
+                              const float *tau_scale, void *x_bf16, float *t);
+
+/*
+ * LES on a coarse 3D FS_F32 plan with the learned closure.  The nonlinear
+ * term of every RK4 stage becomes N + P[-i k_j tau_ij^] with N the plan's
+ * tendency (forcing included, its coefficient frozen per step) and
+ *   tau_s = clip(net(A(v) / a_scale)_s) * tau_scale[s]
+ * for the stage state v (clip(y) = min(max(y, -clip), clip); clip = 0: none),
+ * the features rounded to BF16 as in training.  The viscous term stays exact
+ * (Lawson).  model = NULL is the no-model LES: the calls then are exactly
+ * fs_tendency / fs_step_rk4 of the plan.  The LES reads the network's
+ * parameters when its work runs; it borrows plan and model (both must
+ * outlive it) and owns ~40 coarse fields of scratch when a model is given.
+ */
+typedef struct fs_les fs_les;
+fs_status fs_les_create(fs_les **out, fs_plan *coarse, fs_mlp *model, float a_scale,
+                        const float *tau_scale, float clip);
+fs_status fs_les_destroy(fs_les *les); /* NULL is a no-op */
+/* LES nonlinear term of `state` (forcing coefficient from `state`). */
+fs_status fs_les_tendency(fs_les *les, const void *state, void *tend);
+/* nsteps >= 0 LES steps in place (one captured graph per state pointer). */
+fs_status fs_les_step_rk4(fs_les *les, void *state, int nsteps);
+
 /* Status name and last error message of the calling thread. */
 const char *fs_status_str(fs_status s);
 const char *fs_last_error(void);

@@ -14,10 +14,6 @@
 #include "fft_core.h"
 #include "fs_internal.h"
 
-struct fs_plan {
-  fs::Plan p;
-};
-
 namespace fs {
 
 static thread_local std::string g_err;
@@ -354,7 +350,7 @@ fs_status fs_tendency(fs_plan* plan, const void* state, void* tend) {
   if (fs_status s = usable(plan)) return s;
   if (!state || !tend) return fail(FS_E_INVALID, "NULL array");
   if (state == tend) return fail(FS_E_INVALID, "state and tend must not overlap");
-  plan->p.ops.tendency(&plan->p, state, tend);
+  plan->p.ops.tendency(&plan->p, state, tend, true);
   return device_status(&plan->p);
 }
 

@@ -33,8 +33,10 @@ struct Ops {
   // one RK4 stage (mode 1..4) after its first pass; do_p1 = 0 skips the next
   // stage's inverse transforms at the end of the last step
   void (*stage)(Plan*, void* state, int mode, int do_p1);
-  // tendency of `state` into `out` (all elements written)
-  void (*tendency)(Plan*, const void* state, void* out);
+  // tendency of `state` into `out` (all elements written); with
+  // fresh_alpha the forcing coefficient is recomputed from `state`,
+  // otherwise the one left on the device by the last `alpha` call is used
+  void (*tendency)(Plan*, const void* state, void* out, bool fresh_alpha);
   void (*fft_fwd)(Plan*, const void* phys, void* spec);
   void (*fft_inv)(Plan*, const void* spec, void* phys);
   // forcing coefficient from the state (3D only; may be null)
@@ -103,8 +105,22 @@ void launch_alpha(Plan* p, const void* state);
 template <typename T>
 void launch_fill(Plan* p, void* ptr, size_t n_complex);
 
+// closure network (mlp.hip)
+struct Mlp;
+void mlp_forward_launch(Mlp* net, const void* x, float* y, int64_t P, const float* out_scale,
+                        hipStream_t s);
+int mlp_nparams();
+
 constexpr int kDiagThreads = 256;
 constexpr int kDiagMaxBins = 1024;
 constexpr int kDiagMaxBlocks = 1024;
 
 }  // namespace fs
+
+struct fs_plan {
+  fs::Plan p;
+};
+struct fs_mlp;
+namespace fs {
+Mlp* mlp_of(fs_mlp* net);
+}

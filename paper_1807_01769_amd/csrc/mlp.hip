@@ -23,6 +23,7 @@
 #include <cstring>
 #include <vector>
 
+#include "bf16.h"
 #include "fs.h"
 #include "fs_internal.h"
 
@@ -39,16 +40,6 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + kHid * kIn, OFF_W2 = OFF_B1 + kHid,
 // lane-ordered BF16 blocks: W1 (4), W2 (4x4), W3 (4), W3^T (4), W2^T (4x4)
 constexpr int BLK_W1 = 0, BLK_W2 = 4, BLK_W3 = 20, BLK_W3T = 24, BLK_W2T = 28, NBLK = 44;
 constexpr int kThreads = 256, kWaves = kThreads / 64;
-
-// FP32 -> BF16, round to nearest even (finite inputs)
-__device__ __forceinline__ short to_bf16(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
-}
-__device__ __forceinline__ float from_bf16(short h) {
-  return __uint_as_float(((uint32_t)(unsigned short)h) << 16);
-}
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float x) {
@@ -396,6 +387,10 @@ int mlp_nparams() { return NPARAM; }
 struct fs_mlp {
   fs::Mlp m;
 };
+
+namespace fs {
+Mlp* mlp_of(fs_mlp* net) { return net ? &net->m : nullptr; }
+}  // namespace fs
 
 extern "C" {
 

@@ -72,7 +72,7 @@ struct L2 {
       default: yk<kStage4>(p, state, nullptr, do_p1); break;
     }
   }
-  static void tendency(Plan* p, const void* state, void* out) {
+  static void tendency(Plan* p, const void* state, void* out, bool) {
     launch_fill<T>(p, out, (size_t)N * (N / 2 + 1));
     p1(p, state);
     x(p);

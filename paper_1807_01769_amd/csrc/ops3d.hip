@@ -87,9 +87,9 @@ struct L3 {
       default: zk<kStage4>(p, state, nullptr, do_p1); break;
     }
   }
-  static void tendency(Plan* p, const void* state, void* out) {
+  static void tendency(Plan* p, const void* state, void* out, bool fresh_alpha) {
     launch_fill<T>(p, out, (size_t)3 * N * N * (N / 2 + 1));
-    if (p->m2max >= 0) launch_alpha<T>(p, state);
+    if (p->m2max >= 0 && fresh_alpha) launch_alpha<T>(p, state);
     p1(p, state);
     yinv(p);
     x(p);

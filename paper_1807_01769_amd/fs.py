@@ -386,3 +386,121 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+# ---- closure samples and LES -------------------------------------------------
+lib.fs_closure_create.argtypes = [C.POINTER(_vp), _vp, _vp]
+lib.fs_closure_destroy.argtypes = [_vp]
+lib.fs_closure_samples.argtypes = [_vp, _vp, _vp, _vp, _vp]
+lib.fs_closure_moments.argtypes = [_vp, _vp, _vp, _vp]
+lib.fs_closure_features.argtypes = [_vp, _vp, _vp, C.c_float, C.POINTER(C.c_float), _vp, _vp]
+lib.fs_les_create.argtypes = [C.POINTER(_vp), _vp, _vp, C.c_float, C.POINTER(C.c_float), C.c_float]
+lib.fs_les_destroy.argtypes = [_vp]
+lib.fs_les_tendency.argtypes = [_vp, _vp, _vp]
+lib.fs_les_step_rk4.argtypes = [_vp, _vp, _i]
+for _f in ("fs_closure_create", "fs_closure_destroy", "fs_closure_samples", "fs_closure_moments",
+           "fs_closure_features", "fs_les_create", "fs_les_destroy", "fs_les_tendency",
+           "fs_les_step_rk4"):
+    getattr(lib, _f).restype = _i
+
+
+def _six(v):
+    v = [float(x) for x in v]
+    if len(v) != 6:
+        raise ValueError("six stress scales expected")
+    return (C.c_float * 6)(*v)
+
+
+class Closure:
+    """Filtered-DNS samples: fine 3D f32 plan -> coarse 3D f32 plan."""
+
+    def __init__(self, fine: Plan, coarse: Plan):
+        h = _vp()
+        _check(lib.fs_closure_create(C.byref(h), fine._h, coarse._h), "fs_closure_create")
+        self._h, self.fine, self.coarse = h, fine, coarse
+        self.np = coarse.n ** 3
+
+    def samples(self, fine_state: torch.Tensor):
+        """-> (coarse_state [3][nc][nc][nc/2+1], A [9][nc^3], tau [6][nc^3]) device tensors."""
+        c = self.coarse
+        uc = torch.empty(c.state_shape, dtype=torch.complex64, device="cuda")
+        A = torch.empty((9, self.np), dtype=torch.float32, device="cuda")
+        tau = torch.empty((6, self.np), dtype=torch.float32, device="cuda")
+        _check(lib.fs_closure_samples(
+            self._h, self.fine._arg(fine_state, self.fine.state_shape, torch.complex64, "fine_state"),
+            uc.data_ptr(), A.data_ptr(), tau.data_ptr()), "fs_closure_samples")
+        return uc, A, tau
+
+    def _field(self, t, rows, name):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                and tuple(t.shape) == (rows, self.np)):
+            raise ValueError(f"{name} must be a contiguous device float32 [{rows}][{self.np}] tensor")
+        return t.data_ptr()
+
+    def moments(self, A: torch.Tensor, tau: torch.Tensor) -> torch.Tensor:
+        """Mean squares (float64 [15]): the 9 gradients then the 6 stresses."""
+        m = torch.empty(15, dtype=torch.float64, device="cuda")
+        _check(lib.fs_closure_moments(self._h, self._field(A, 9, "A"), self._field(tau, 6, "tau"),
+                                      m.data_ptr()), "fs_closure_moments")
+        return m
+
+    def features(self, A: torch.Tensor, a_scale: float, tau: torch.Tensor | None = None,
+                 tau_scale=None):
+        """-> (x bf16 [nc^3][16], t float32 [nc^3][6] or None)."""
+        x = torch.empty((self.np, 16), dtype=torch.bfloat16, device="cuda")
+        t = None
+        if tau is not None:
+            t = torch.empty((self.np, 6), dtype=torch.float32, device="cuda")
+        _check(lib.fs_closure_features(
+            self._h, self._field(A, 9, "A"), None if tau is None else self._field(tau, 6, "tau"),
+            float(a_scale), None if tau is None else _six(tau_scale), x.data_ptr(),
+            None if t is None else t.data_ptr()), "fs_closure_features")
+        return x, t
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.fs_closure_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Les:
+    """LES on a coarse 3D f32 plan with the network closure (model=None: no model)."""
+
+    def __init__(self, plan: Plan, model: Mlp | None, a_scale: float = 1.0,
+                 tau_scale=(1.0,) * 6, clip: float = 0.0):
+        h = _vp()
+        _check(lib.fs_les_create(C.byref(h), plan._h, None if model is None else model._h,
+                                 float(a_scale), _six(tau_scale), float(clip)), "fs_les_create")
+        self._h, self.plan, self.model = h, plan, model
+
+    def tendency(self, state: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        p = self.plan
+        if out is None:
+            out = torch.empty(p.state_shape, dtype=p.complex_dtype, device="cuda")
+        _check(lib.fs_les_tendency(self._h, p._arg(state, p.state_shape, p.complex_dtype, "state"),
+                                   p._arg(out, p.state_shape, p.complex_dtype, "out")),
+               "fs_les_tendency")
+        return out
+
+    def step(self, state: torch.Tensor, nsteps: int = 1) -> torch.Tensor:
+        p = self.plan
+        _check(lib.fs_les_step_rk4(self._h, p._arg(state, p.state_shape, p.complex_dtype, "state"),
+                                   int(nsteps)), "fs_les_step_rk4")
+        return state
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.fs_les_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -130,3 +130,27 @@ def test_ensemble_create_validates(lib, nruns, sizes, kw, expect):
     h = C.c_void_p()
     assert lib.fs_ensemble_create(C.byref(h), nruns, arr, 6.28, 1e-3, 1e-3, C.byref(o)) == expect
     assert not h.value
+
+
+def test_closure_and_les_null_arguments(lib):
+    vp, f = C.c_void_p, C.c_float
+    sigs = {
+        "fs_closure_create": ([vp, vp, vp], (None, None, None)),
+        "fs_closure_samples": ([vp] * 5, (None,) * 5),
+        "fs_closure_moments": ([vp] * 4, (None,) * 4),
+        "fs_closure_features": ([vp, vp, vp, f, vp, vp, vp], (None, None, None, 1.0, None, None, None)),
+        "fs_les_create": ([vp, vp, vp, f, vp, f], (None, None, None, 1.0, None, 0.0)),
+        "fs_les_tendency": ([vp] * 3, (None,) * 3),
+        "fs_les_step_rk4": ([vp, vp, C.c_int], (None, None, 1)),
+        "fs_mlp_create": ([vp, C.c_uint64, vp], (None, 1, None)),
+        "fs_mlp_forward": ([vp, vp, vp, C.c_int64], (None, None, None, 16)),
+        "fs_mlp_train_step": ([vp, vp, vp, C.c_int64, f, vp], (None, None, None, 16, 1e-3, None)),
+    }
+    for name, (argtypes, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = argtypes
+        assert fn(*args) == -1, name
+    for name in ("fs_closure_destroy", "fs_les_destroy", "fs_mlp_destroy"):
+        fn = getattr(lib, name)
+        fn.argtypes = [vp]
+        assert fn(None) == 0, name
