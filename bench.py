@@ -85,6 +85,39 @@ def cpu_baseline(seconds: float, n: int = 128) -> dict:
                       f"({t:.1f} s); per-point FFT work at {n}^3 is log2({n})/9 of 512^3's"}
 
 
+LES_DT_FACTOR = 8  # LES step = 8 DNS steps (grid ratio 512 / 64)
+
+
+def closure_les_speed(fs, torch, plan, state, nc, steps, dns_ms_per_step):
+    """Wall time of the closure LES step (network of the closure's
+    architecture, random initial weights: the cost does not depend on their
+    values) on the nc^3 cutoff of the DNS state, against the DNS step, per
+    unit of simulated time."""
+    coarse = fs.Plan(nc, nu=NU, dt=DT * LES_DT_FACTOR, ndim=3, precision="f32",
+                     forcing_power=POWER, forcing_kmin=KMIN, forcing_kmax=KMAX)
+    closure = fs.Closure(plan, coarse)
+    uc, A, tau = closure.samples(state)
+    m = closure.moments(A, tau).cpu().numpy()
+    net = fs.Mlp(seed=7)
+    les = fs.Les(coarse, net, float(m[:9].mean() ** 0.5), [float(v ** 0.5) for v in m[9:]], 6.0)
+    les.step(uc, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    les.step(uc, steps)
+    torch.cuda.synchronize()
+    les_ms = (time.perf_counter() - t0) * 1e3 / steps
+    _, e, _ = coarse.energy_spectrum(uc)
+    finite = math.isfinite(float(e.cpu()))
+    log(f"closure LES {nc}^3: {les_ms:.3f} ms/step (dt x{LES_DT_FACTOR})")
+    out = {"les_n": nc, "les_dt": DT * LES_DT_FACTOR, "les_ms_per_step": les_ms,
+           "les_steps": steps, "dns_ms_per_step": dns_ms_per_step,
+           "speedup_per_simulated_time": (dns_ms_per_step / DT) / (les_ms / (DT * LES_DT_FACTOR)),
+           "network": "9-64-64-6 GELU, BF16 MFMA, random initial weights", "finite": finite}
+    for o in (les, net, closure, coarse):
+        o.close()
+    return out
+
+
 def bench_ensemble(args) -> int:
     """256 independent 2D runs (128 at 128^2, 96 at 256^2, 32 at 512^2), FP32,
     nu = 1e-4, dt = 5e-4, 200 RK4 steps in one graph launch."""
@@ -112,6 +145,10 @@ def bench_ensemble(args) -> int:
     pts = sum(n * n for n in sizes)
     rate = pts * steps / (t1 - t0)
     finite = bool(torch.isfinite(torch.view_as_real(st)).all())
+    les = None
+    if args.les_n > 0 and args.les_n < n:
+        les = closure_les_speed(fs, torch, plan, state, args.les_n, args.les_steps, ms_per_step)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -148,6 +185,9 @@ def main() -> int:
                     help="time graph-launched steps (no per-kernel events)")
     ap.add_argument("--workload", choices=["3d", "ensemble"], default="3d")
     ap.add_argument("--ens-steps", type=int, default=200)
+    ap.add_argument("--les-n", type=int, default=64,
+                    help="LES grid of the closure speedup measurement (0 = skip)")
+    ap.add_argument("--les-steps", type=int, default=200)
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -231,6 +271,10 @@ def main() -> int:
         step_alg = sum(v[0] for k, v in alg.items() if k != "p1") / args.steps
         roofline["step_alg_GBps"] = round(step_alg / (ms_per_step * 1e-3) / 1e9, 1)
 
+    les = None
+    if args.les_n > 0 and args.les_n < n:
+        les = closure_les_speed(fs, torch, plan, state, args.les_n, args.les_steps, ms_per_step)
+
     cpu = None
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -256,6 +300,7 @@ def main() -> int:
                    "n": n, "timing": "graph" if args.graphs else "per-kernel events"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "closure_les": les,
         "kernels": kernels,
         "energy_after": energy,
         "enstrophy_after": enstrophy,

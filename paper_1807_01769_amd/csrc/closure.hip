@@ -286,6 +286,7 @@ struct fs_closure {
   cf* cspec = nullptr;      // one coarse spectral field
   cf* grad = nullptr;       // 9 coarse spectral gradient fields
   float* ub = nullptr;      // coarse physical filtered velocity [3][nc^3]
+  void *wa = nullptr, *wb = nullptr;  // coarse transform workspaces for 9 fields
 };
 
 extern "C" {
@@ -311,6 +312,8 @@ fs_status fs_closure_create(fs_closure** out, fs_plan* fine, fs_plan* coarse) {
   const size_t o_cspec = cv.take(sizeof(cf) * spec_elems(nc));
   const size_t o_grad = cv.take(sizeof(cf) * 9 * spec_elems(nc));
   const size_t o_ub = cv.take(sizeof(float) * 3 * phys_elems(nc));
+  const size_t wfull = sizeof(cf) * 9 * coarse->p.ops.elems_full;
+  const size_t o_wa = cv.take(wfull), o_wb = cv.take(wfull);
   fs_closure* c = new fs_closure;
   if (hipMalloc(&c->base, cv.total) != hipSuccess) {
     hipGetLastError();
@@ -326,6 +329,8 @@ fs_status fs_closure_create(fs_closure** out, fs_plan* fine, fs_plan* coarse) {
   c->cspec = (cf*)(b + o_cspec);
   c->grad = (cf*)(b + o_grad);
   c->ub = (float*)(b + o_ub);
+  c->wa = b + o_wa;
+  c->wb = b + o_wb;
   *out = c;
   return FS_OK;
 }
@@ -362,11 +367,11 @@ fs_status fs_closure_samples(fs_closure* c, const void* fine_state, void* coarse
   hipLaunchKernelGGL(fs::k_cutoff, dim3(fs::blocks_for(nsc), 3), dim3(fs::kThr), 0, s, us, nf, uc,
                      nc);
   if (!fs::plan_ok(pc, "k_cutoff")) return FS_E_DEVICE;
-  for (int i = 0; i < 3; i++) pc->ops.fft_inv(pc, uc + i * nsc, c->ub + i * npc);
+  pc->ops.fft_inv_n(pc, uc, c->ub, 3, c->wa, c->wb);
   hipLaunchKernelGGL(fs::k_grad, dim3(fs::blocks_for(nsc)), dim3(fs::kThr), 0, s, (const cf*)uc,
                      c->grad, nc, (float)(2.0 * M_PI / pc->L));
   if (!fs::plan_ok(pc, "k_grad")) return FS_E_DEVICE;
-  for (int f = 0; f < 9; f++) pc->ops.fft_inv(pc, c->grad + f * nsc, A + f * npc);
+  pc->ops.fft_inv_n(pc, c->grad, A, 9, c->wa, c->wb);
   // fine physical velocity (kept modes only)
   for (int i = 0; i < 3; i++) {
     hipLaunchKernelGGL(fs::k_mask, dim3(fs::blocks_for(nsf)), dim3(fs::kThr), 0, s, us + i * nsf,
@@ -437,7 +442,7 @@ struct fs_les {
   void* base = nullptr;
   cf *acc = nullptr, *v = nullptr, *k = nullptr, *grad = nullptr, *th = nullptr;
   float *A = nullptr, *tau = nullptr, *y = nullptr;
-  void* x = nullptr;
+  void *x = nullptr, *wa = nullptr, *wb = nullptr;
   hipGraphExec_t graph = nullptr;
   void* gstate = nullptr;
 };
@@ -455,7 +460,7 @@ void les_tendency(fs_les* les, const void* state, cf* tend, bool fresh_alpha) {
   hipLaunchKernelGGL(fs::k_grad, dim3(fs::blocks_for(ns)), dim3(fs::kThr), 0, p->launch,
                      (const cf*)state, les->grad, n, kb);
   fs::plan_ok(p, "k_grad");
-  for (int f = 0; f < 9; f++) p->ops.fft_inv(p, les->grad + f * ns, les->A + f * np);
+  p->ops.fft_inv_n(p, les->grad, les->A, 9, les->wa, les->wb);
   hipLaunchKernelGGL(fs::k_features, dim3(fs::blocks_for(np)), dim3(fs::kThr), 0, p->launch,
                      (const float*)les->A, np, les->inv_a, (uint4*)les->x, (const float*)nullptr,
                      fs::Six{}, (float*)nullptr);
@@ -465,7 +470,7 @@ void les_tendency(fs_les* les, const void* state, cf* tend, bool fresh_alpha) {
   hipLaunchKernelGGL(fs::k_tau_from_y, dim3(fs::blocks_for(np)), dim3(fs::kThr), 0, p->launch,
                      (const float*)les->y, np, les->scale, les->clip, les->tau);
   fs::plan_ok(p, "k_tau_from_y");
-  for (int s = 0; s < 6; s++) p->ops.fft_fwd(p, les->tau + s * np, les->th + s * ns);
+  p->ops.fft_fwd_n(p, les->tau, les->th, 6, les->wa, les->wb);
   hipLaunchKernelGGL(fs::k_sgs, dim3(fs::blocks_for(ns)), dim3(fs::kThr), 0, p->launch, tend,
                      (const cf*)les->th, n, kb);
   fs::plan_ok(p, "k_sgs");
@@ -562,7 +567,9 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
                  o_k = cv.take(sizeof(cf) * 3 * ns), o_grad = cv.take(sizeof(cf) * 9 * ns),
                  o_th = cv.take(sizeof(cf) * 6 * ns), o_A = cv.take(sizeof(float) * 9 * np),
                  o_tau = cv.take(sizeof(float) * 6 * np), o_y = cv.take(sizeof(float) * 6 * np),
-                 o_x = cv.take(sizeof(short) * 16 * np);
+                 o_x = cv.take(sizeof(short) * 16 * np),
+                 o_wa = cv.take(sizeof(cf) * 9 * coarse->p.ops.elems_full),
+                 o_wb = cv.take(sizeof(cf) * 9 * coarse->p.ops.elems_full);
     if (hipMalloc(&les->base, cv.total) != hipSuccess) {
       hipGetLastError();
       delete les;
@@ -578,6 +585,8 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
     les->tau = (float*)(b + o_tau);
     les->y = (float*)(b + o_y);
     les->x = b + o_x;
+    les->wa = b + o_wa;
+    les->wb = b + o_wb;
   }
   *out = les;
   return FS_OK;

@@ -39,6 +39,10 @@ struct Ops {
   void (*tendency)(Plan*, const void* state, void* out, bool fresh_alpha);
   void (*fft_fwd)(Plan*, const void* phys, void* spec);
   void (*fft_inv)(Plan*, const void* spec, void* phys);
+  // nf stacked fields at once through caller workspaces wa, wb of
+  // nf * elems_full complex elements each (3D only; may be null)
+  void (*fft_fwd_n)(Plan*, const void* phys, void* spec, int nf, void* wa, void* wb);
+  void (*fft_inv_n)(Plan*, const void* spec, void* phys, int nf, void* wa, void* wb);
   // forcing coefficient from the state (3D only; may be null)
   void (*alpha)(Plan*, const void* state);
   // diagnostics
@@ -46,6 +50,7 @@ struct Ops {
                double* enstrophy);
   // workspace element counts (complex elements of the plan's precision)
   size_t elems_a, elems_b, elems_acc;
+  size_t elems_full;  // one undealiased field in the transform workspace layout
 };
 
 struct Plan {

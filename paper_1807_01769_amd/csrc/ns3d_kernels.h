@@ -374,10 +374,12 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
 }
 
 // ---------------------------------------------------------------------------
-// Plain (undealiased) 3D transforms, used by the FFT entry points.
-// spec: [N][N][N/2+1] complex; phys: [N][N][N] real.
+// Plain (undealiased) 3D transforms, used by the FFT entry points, for F
+// stacked fields: spec [F][N][N][N/2+1] complex, phys [F][N][N][N] real.  The
+// z passes take the field from blockIdx.y; the y and x passes treat the F*N
+// z-planes of the stack as rows.
 // ---------------------------------------------------------------------------
-// inverse z: spec -> Wm(FULL)[N][XT][N][16]; grid N * XT * SUB
+// inverse z: spec -> Wm(FULL)[F][N][XT][N][16]; grid (N * XT * SUB, F)
 template <typename T, int N>
 __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     k3f_z_inv(const cx<T>* __restrict__ spec, cx<T>* __restrict__ w, const cx<T>* __restrict__ tw) {
@@ -392,6 +394,8 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   blk /= C::SUB;
   const int xt = blk % G::XT, iy = blk / G::XT;
   const int mx = xt * kTile + sub * C::LB + b;
+  spec += (size_t)blockIdx.y * N * N * NH;
+  w += (size_t)blockIdx.y * N * G::XT * N * kTile;
   cx<T> v[1][8];
 #pragma unroll
   for (int e = 0; e < 8; e++)
@@ -403,7 +407,7 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = v[0][e];
 }
 
-// forward z: Wm(FULL) -> spec; grid N * XT * SUB
+// forward z: Wm(FULL) -> spec; grid (N * XT * SUB, fields)
 template <typename T, int N>
 __global__ void __launch_bounds__((Strided<T, N>::THREADS))
     k3f_z_fwd(const cx<T>* __restrict__ w, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw) {
@@ -418,6 +422,8 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   blk /= C::SUB;
   const int xt = blk % G::XT, iy = blk / G::XT;
   const int mx = xt * kTile + sub * C::LB + b;
+  spec += (size_t)blockIdx.y * N * N * NH;
+  w += (size_t)blockIdx.y * N * G::XT * N * kTile;
   const size_t zstride = (size_t)G::XT * N * kTile;
   const cx<T>* src = w + ((size_t)xt * N + iy) * kTile + sub * C::LB + b;
   cx<T> v[1][8];

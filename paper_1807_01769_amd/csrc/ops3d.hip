@@ -96,39 +96,49 @@ struct L3 {
     yfwd(p);
     zk<kModeTend>(p, (void*)state, out, 0);
   }
-  static void fft_inv(Plan* p, const void* spec, void* phys) {
+  // nf stacked fields through caller workspaces wa, wb (elems_full each per field)
+  static void fft_inv_n(Plan* p, const void* spec, void* phys, int nf, void* wa, void* wb) {
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((k3f_z_inv<T, N>), dim3(N * GF::XT * C::SUB), dim3(C::THREADS), 0,
-                       p->launch, (const cx<T>*)spec, A(p), TW(p));
+    hipLaunchKernelGGL((k3f_z_inv<T, N>), dim3(N * GF::XT * C::SUB, nf), dim3(C::THREADS), 0,
+                       p->launch, (const cx<T>*)spec, (cx<T>*)wa, TW(p));
     launched(p, "k3f_z_inv");
     p->end(KID_FFT);
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(xcd_grid(N, GF::XT * YC::SUB)),
-                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), N);
+    hipLaunchKernelGGL((k_y_inv<T, N, true>), dim3(xcd_grid(nf * N, GF::XT * YC::SUB)),
+                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)wa, (cx<T>*)wb, TW(p),
+                       nf * N);
     launched(p, "k_y_inv full");
     p->end(KID_FFT);
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((kf_x_c2r<T, N>), dim3(N / 2 / R::RP, N), dim3(R::THREADS), 0, p->launch,
-                       (const cx<T>*)B(p), (T*)phys, TW(p));
+    hipLaunchKernelGGL((kf_x_c2r<T, N>), dim3(N / 2 / R::RP, nf * N), dim3(R::THREADS), 0,
+                       p->launch, (const cx<T>*)wb, (T*)phys, TW(p));
     launched(p, "kf_x_c2r");
     p->end(KID_FFT);
   }
-  static void fft_fwd(Plan* p, const void* phys, void* spec) {
+  static void fft_fwd_n(Plan* p, const void* phys, void* spec, int nf, void* wa, void* wb) {
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((kf_x_r2c<T, N>), dim3(N / 2 / R::RP, N), dim3(R::THREADS), 0, p->launch,
-                       (const T*)phys, B(p), TW(p), (T)(1.0 / ((double)N * N * N)));
+    hipLaunchKernelGGL((kf_x_r2c<T, N>), dim3(N / 2 / R::RP, nf * N), dim3(R::THREADS), 0,
+                       p->launch, (const T*)phys, (cx<T>*)wb, TW(p),
+                       (T)(1.0 / ((double)N * N * N)));
     launched(p, "kf_x_r2c");
     p->end(KID_FFT);
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((k_y_fwd<T, N, true>), dim3(xcd_grid(N, GF::XT * YC::SUB)),
-                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)B(p), A(p), TW(p), N);
+    hipLaunchKernelGGL((k_y_fwd<T, N, true>), dim3(xcd_grid(nf * N, GF::XT * YC::SUB)),
+                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)wb, (cx<T>*)wa, TW(p),
+                       nf * N);
     launched(p, "k_y_fwd full");
     p->end(KID_FFT);
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((k3f_z_fwd<T, N>), dim3(N * GF::XT * C::SUB), dim3(C::THREADS), 0,
-                       p->launch, (const cx<T>*)A(p), (cx<T>*)spec, TW(p));
+    hipLaunchKernelGGL((k3f_z_fwd<T, N>), dim3(N * GF::XT * C::SUB, nf), dim3(C::THREADS), 0,
+                       p->launch, (const cx<T>*)wa, (cx<T>*)spec, TW(p));
     launched(p, "k3f_z_fwd");
     p->end(KID_FFT);
+  }
+  static void fft_inv(Plan* p, const void* spec, void* phys) {
+    fft_inv_n(p, spec, phys, 1, p->bufA, p->bufB);
+  }
+  static void fft_fwd(Plan* p, const void* phys, void* spec) {
+    fft_fwd_n(p, phys, spec, 1, p->bufA, p->bufB);
   }
   static Ops ops() {
     Ops o{};
@@ -137,6 +147,8 @@ struct L3 {
     o.tendency = tendency;
     o.fft_fwd = fft_fwd;
     o.fft_inv = fft_inv;
+    o.fft_fwd_n = fft_fwd_n;
+    o.fft_inv_n = fft_inv_n;
     o.alpha = launch_alpha<T>;
     o.diag = launch_diag<T>;
     const size_t wm6 = (size_t)6 * N * G::XT * G::M * kTile;
@@ -145,6 +157,7 @@ struct L3 {
     o.elems_a = wm6 > wfull ? wm6 : wfull;
     o.elems_b = wn6 > wfull ? wn6 : wfull;
     o.elems_acc = (size_t)3 * G::XT * G::M * G::M * kTile;
+    o.elems_full = wfull;
     return o;
   }
 };
