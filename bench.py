@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "RK4 step ns/gridpoint at 512³ FP32, % HBM roofline; closure-LES vs DNS speedup"
 HBM_PEAK_GBS = 8000.0
 NU, DT, POWER, KMIN, KMAX, SEED = 2e-4, 1e-3, 5e-3, 2.0, 3.0, 1
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3d_512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3d_512.txt")
 KERNEL_SOURCES = ["fft_core.h", "ns_common.h", "ns3d_kernels.h", "ops3d.hip"]
 
 
@@ -42,6 +42,18 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_1807_01769_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """Measured HBM bytes per launch from the counter summary: its line that
+    starts with "DATA " holds {"n", "source_hash", "bytes_per_launch"}."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("DATA "):
+                return json.loads(line[5:])
+    return None
 
 
 def algorithmic_bytes(n: int, steps: int, elem: int = 8) -> dict:
@@ -258,11 +270,9 @@ def main() -> int:
             kernels[name] = rec
         dom = max((k for k in kernels if "alg_GBps" in kernels[k]), key=lambda k: kernels[k]["ms_total"])
         traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            with open(TRAFFIC_FILE) as fh:
-                tr = json.load(fh)
-            if tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
-                traffic = tr.get("bytes_per_launch", {}).get(dom)
+        tr = read_traffic()
+        if tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
+            traffic = tr.get("bytes_per_launch", {}).get(dom)
         ach = kernels[dom]["alg_GBps"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
