@@ -158,10 +158,29 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   }
 }
 
-// The fused z passes keep three components plus a transform line in registers;
-// at most 512 threads per block leaves them up to 256 VGPRs (no spills).
+// The fused z passes keep three components plus a transform line in registers
+// (at most 512 threads per block).  In single precision their twiddles come
+// from a copy of the table in LDS and the compiler is asked for 4 waves per
+// SIMD (two blocks per CU), so the memory phases of one block overlap the
+// transforms of the other; double precision keeps the register budget.
 template <typename T, int N>
 using ZCfg = Strided<T, N, cmin(kTile, cmax(1, 512 / (N / 8)))>;
+template <typename T>
+constexpr int zpass_waves() {
+  return sizeof(T) == 4 ? 4 : 1;
+}
+// twiddle table of a z pass: the LDS copy `twl` (filled by the block) in single
+// precision, the global table otherwise
+template <typename T, int N, int THREADS>
+__device__ __forceinline__ const cx<T>* zpass_twiddles(const cx<T>* __restrict__ tw, cx<T>* twl) {
+  if constexpr (sizeof(T) == 4) {
+    for (int i = threadIdx.x; i < N; i += THREADS) twl[i] = tw[i];
+    __syncthreads();
+    return twl;
+  } else {
+    return tw;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Inverse z transforms of the six fields (u, w = i k x v) of a stage input v
@@ -239,7 +258,8 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   constexpr int NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
-  const Twiddles<T, N> twr(a.tw, t);
+  __shared__ cx<T> twl[sizeof(T) == 4 ? N : 1];
+  const Twiddles<T, N, false> twr(zpass_twiddles<T, N, C::THREADS>(a.tw, twl), t);
   int jy, rem;
   if (!xcd_row_block(G::M, G::XT * C::SUB, jy, rem)) return;  // whole block
   const int xt = rem / C::SUB, sub = rem % C::SUB;
@@ -275,7 +295,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
 // MODE kModeTend writes the tendency to a.tend instead.  Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
+__global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
     k3_z(const cx<T>* __restrict__ w4, cx<T>* __restrict__ w1, StageArgs<T> a, int do_p1) {
   using G = Geo<N, false>;
   using C = ZCfg<T, N>;
@@ -283,7 +303,8 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   constexpr int NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
-  const Twiddles<T, N> twr(a.tw, t);
+  __shared__ cx<T> twl[sizeof(T) == 4 ? N : 1];
+  const Twiddles<T, N, false> twr(zpass_twiddles<T, N, C::THREADS>(a.tw, twl), t);
   int jy, rem;
   if (!xcd_row_block(G::M, G::XT * C::SUB, jy, rem)) return;  // whole block
   const int xt = rem / C::SUB, sub = rem % C::SUB;
