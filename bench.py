@@ -157,10 +157,6 @@ def bench_ensemble(args) -> int:
     pts = sum(n * n for n in sizes)
     rate = pts * steps / (t1 - t0)
     finite = bool(torch.isfinite(torch.view_as_real(st)).all())
-    les = None
-    if args.les_n > 0 and args.les_n < n:
-        les = closure_les_speed(fs, torch, plan, state, args.les_n, args.les_steps, ms_per_step)
-
     cpu = None
     if not args.no_cpu:
         import oracle

@@ -236,12 +236,27 @@ __device__ __forceinline__ int band_index(int mx, int my, int mz, int bw) {
   return ((mz + bw) * (2 * bw + 1) + (my + bw)) * (bw + 1) + mx;
 }
 
+// Forcing band test split into the part fixed for a lane's column (mx, my):
+// band_column gives mx^2 + my^2 when the column can meet the band, else -1;
+// in_band then checks one mz of that column.
 template <typename T>
-__device__ __forceinline__ bool in_band(const StageArgs<T>& a, int mx, int my, int mz) {
-  if (a.m2max < 0) return false;
-  if (mx > a.bw || my > a.bw || my < -a.bw || mz > a.bw || mz < -a.bw) return false;
-  const int m2 = mx * mx + my * my + mz * mz;
+__device__ __forceinline__ int band_column(const StageArgs<T>& a, int mx, int my) {
+  if (a.m2max < 0 || mx > a.bw || my > a.bw || my < -a.bw) return -1;
+  return mx * mx + my * my;
+}
+template <typename T>
+__device__ __forceinline__ bool in_band(const StageArgs<T>& a, int m2xy, int mz) {
+  if (m2xy < 0 || mz > a.bw || mz < -a.bw) return false;
+  const int m2 = m2xy + mz * mz;
   return m2 >= a.m2min && m2 <= a.m2max;
+}
+
+// 1/x for the projection: the hardware reciprocal (1 ulp) in single
+// precision, a division in double precision
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_rcpf(x);
+  else return (T)1 / x;
 }
 
 // ---------------------------------------------------------------------------
@@ -266,6 +281,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   const int mx = xt * kTile + sub * C::LB + b;
   const int iy = G::j2i(jy), my = G::jmode(jy);
   const bool col = mx < G::H;
+  const int m2xy = band_column(a, mx, my);
   const size_t cstride = (size_t)N * N * NH;
   cx<T> v[3][8];
 #pragma unroll
@@ -277,7 +293,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
     for (int c = 0; c < 3; c++) v[c][e] = kept ? state[c * cstride + o] : cx<T>{0, 0};
     if (kept) {
       const int mz = iz <= N / 2 ? iz : iz - N;
-      if (in_band(a, mx, my, mz)) {
+      if (in_band(a, m2xy, mz)) {
         const int bi = band_index<T>(mx, my, mz, a.bw);
         const int bn = (2 * a.bw + 1) * (2 * a.bw + 1) * (a.bw + 1);
 #pragma unroll
@@ -332,6 +348,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
   const int bn = (2 * a.bw + 1) * (2 * a.bw + 1) * (a.bw + 1);
   const T alpha = a.m2max >= 0 ? a.alpha[0] : (T)0;
   const T kx = a.kb * (T)mx, ky = a.kb * (T)my;
+  const int m2xy = band_column(a, mx, my);
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int iz = t + e * P;
@@ -347,7 +364,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
     const T k2 = kx * kx + ky * ky + kz * kz;
     cx<T> nl[3];
     if (k2 > (T)0) {
-      const T ik2 = (T)1 / k2;
+      const T ik2 = recip(k2);
       const cx<T> kp = cscale(cscale(v[0][e], kx) + cscale(v[1][e], ky) + cscale(v[2][e], kz), ik2);
       nl[0] = v[0][e] - cscale(kp, kx);
       nl[1] = v[1][e] - cscale(kp, ky);
@@ -355,7 +372,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
     } else {
       nl[0] = nl[1] = nl[2] = {0, 0};
     }
-    const bool band = in_band(a, mx, my, mz);
+    const bool band = in_band(a, m2xy, mz);
     const int bi = band ? band_index<T>(mx, my, mz, a.bw) : 0;
     if (band) {
 #pragma unroll
