@@ -26,6 +26,11 @@ Pins (tests/test_oracle_*.py, all CPU):
   forcing_alpha3d        injected power equals the prescribed power
   diag2d / diag3d        closed-form Taylor-Green energy, enstrophy and shell,
                          sum of the spectrum equals the energy
+  transfer2d / 3d        per-shell dE/dt at nu = 0 from centred differences of
+                         the shell spectrum under the exact-in-time step
+                         (fourth-order scheme); total 0 without forcing (and
+                         2D enstrophy rate 0 when alias free), total = power
+                         with forcing
   cutoff3d / grad3d      tr A = 0 for solenoidal fields, closed-form gradient
                          of Taylor-Green, cutoff idempotent and exact on kept
   sgs_tau3d              zero for band-limited fields, symmetric, traceless,
@@ -92,6 +97,8 @@ def lib():
         L.or_adam.argtypes = [vp, vp, vp, vp, i, i, d, d, d, d]
         L.or_tendency3d_les.argtypes = [i, d, vp, vp, vp]
         L.or_lawson_scalar.restype = d
+        L.or_transfer3d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
+        L.or_transfer2d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
         L.or_round_bf16.argtypes = [d]
         L.or_round_bf16.restype = d
         L.or_round_bf16_array.argtypes = [vp, C.c_int64]
@@ -198,6 +205,23 @@ def diag2d(wh, nbins, L=2 * np.pi):
     e, z = C.c_double(), C.c_double()
     lib().or_diag2d(w.shape[0], float(L), _p(w), int(nbins), _p(spec), C.byref(e), C.byref(z))
     return spec, e.value, z.value
+
+
+def transfer3d(uh, nh, nbins, L=2 * np.pi):
+    """(T[nbins], dE/dt, dZ/dt): shell sums of w Re(conj(u) . N)."""
+    u, a = _c128(uh), _c128(nh)
+    T = np.zeros(nbins)
+    e, z = C.c_double(), C.c_double()
+    lib().or_transfer3d(u.shape[1], float(L), _p(u), _p(a), int(nbins), _p(T), C.byref(e), C.byref(z))
+    return T, e.value, z.value
+
+
+def transfer2d(wh, nh, nbins, L=2 * np.pi):
+    w, a = _c128(wh), _c128(nh)
+    T = np.zeros(nbins)
+    e, z = C.c_double(), C.c_double()
+    lib().or_transfer2d(w.shape[0], float(L), _p(w), _p(a), int(nbins), _p(T), C.byref(e), C.byref(z))
+    return T, e.value, z.value
 
 
 def kept(m: int, n: int) -> bool:

@@ -534,6 +534,69 @@ void or_diag2d(int n, double L, const cplx *wh, int nbins, double *spec, double 
   *Z = z;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Spectral energy budget: with E = 1/2 sum w |u_hat|^2 and du_hat/dt = N_hat  */
+/* (no viscosity), dE/dt = sum w Re(conj(u_hat) . N_hat); its shell sums are   */
+/* the transfer T(s), s = floor(|m| + 1/2) (bins >= nbins dropped from T       */
+/* only).  *Et = the total; *Zt = the enstrophy rate sum w Re(conj(w) . (i k x */
+/* N)) in 3D.  2D: state and N are the vorticity and its tendency,             */
+/* T = w Re(conj(w_hat) N_hat) / |k|^2 and *Zt = sum w Re(conj(w_hat) N_hat).  */
+/* ------------------------------------------------------------------------ */
+void or_transfer3d(int n, double L, const cplx *uh, const cplx *nh, int nbins, double *T,
+                   double *Et, double *Zt) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
+  const double kb = 2.0 * M_PI / L;
+  double e = 0, z = 0;
+  for (int b = 0; b < nbins; b++) T[b] = 0.0;
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int mz = mode_full(iz, n), my = mode_full(iy, n), mx = ix;
+    if (!(keep1(mx, n) && keep1(my, n) && keep1(mz, n))) continue;
+    double w = mx == 0 ? 1.0 : 2.0;
+    double k[3] = {kb * mx, kb * my, kb * mz};
+    const cplx u[3] = {uh[i], uh[ns + i], uh[2 * ns + i]};
+    const cplx a[3] = {nh[i], nh[ns + i], nh[2 * ns + i]};
+    double te = 0;
+    for (int c = 0; c < 3; c++) te += w * creal(conj(u[c]) * a[c]);
+    cplx wu[3], wa[3];
+    for (int c = 0; c < 3; c++) {
+      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      wu[c] = I * (k[c1] * u[c2] - k[c2] * u[c1]);
+      wa[c] = I * (k[c1] * a[c2] - k[c2] * a[c1]);
+    }
+    double tz = 0;
+    for (int c = 0; c < 3; c++) tz += w * creal(conj(wu[c]) * wa[c]);
+    e += te;
+    z += tz;
+    int s = (int)floor(sqrt((double)mx * mx + (double)my * my + (double)mz * mz) + 0.5);
+    if (s < nbins) T[s] += te;
+  }
+  *Et = e;
+  *Zt = z;
+}
+
+void or_transfer2d(int n, double L, const cplx *wh, const cplx *nh, int nbins, double *T,
+                   double *Et, double *Zt) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * h;
+  const double kb = 2.0 * M_PI / L;
+  double e = 0, z = 0;
+  for (int b = 0; b < nbins; b++) T[b] = 0.0;
+  for (int64_t i = 0; i < ns; i++) {
+    int my = mode_full((int)(i / h), n), mx = (int)(i % h);
+    if (!(keep1(mx, n) && keep1(my, n))) continue;
+    if (mx == 0 && my == 0) continue;
+    double w = mx == 0 ? 1.0 : 2.0;
+    double k2 = kb * kb * ((double)mx * mx + (double)my * my);
+    double tz = w * creal(conj(wh[i]) * nh[i]);
+    e += tz / k2;
+    z += tz;
+    int s = (int)floor(sqrt((double)mx * mx + (double)my * my) + 0.5);
+    if (s < nbins) T[s] += tz / k2;
+  }
+  *Et = e;
+  *Zt = z;
+}
+
 /* ======================================================================== */
 /* Learned-closure building blocks (filtered DNS -> coarse LES).              */
 /* A coarse grid nc keeps |m_a| <= Kc = floor((nc-1)/3): exactly its own      */
