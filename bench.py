@@ -130,20 +130,31 @@ def closure_les_speed(fs, torch, plan, state, nc, steps, dns_ms_per_step):
     return out
 
 
-def bench_ensemble(args) -> int:
-    """256 independent 2D runs (128 at 128^2, 96 at 256^2, 32 at 512^2), FP32,
-    nu = 1e-4, dt = 5e-4, 200 RK4 steps in one graph launch."""
-    import numpy as np
-    import torch
-    from paper_1807_01769_amd import fs, inputs as I
+ENS_NU, ENS_DT = 1e-4, 5e-4
 
+
+def ensemble_alg_bytes(sizes) -> float:
+    """Bytes one 2D RK4 step of the ensemble must move if only kept modes
+    travel: per stage the x pass reads 3 fields and writes 2 (N x H each), the
+    y pass reads those 2, the state and accumulator (M x H) and writes 3
+    fields and the accumulator; the state is written once per step."""
+    tot = 0.0
+    for n in sizes:
+        K = (n - 1) // 3
+        M, H = 2 * K + 1, K + 1
+        un, us = n * H * 8.0, M * H * 8.0
+        tot += 4 * (3 * un + 2 * un + 2 * un + 3 * un + 3 * us) + us
+    return tot
+
+
+def time_ensemble(fs, torch, I, np, steps):
+    """256 independent 2D runs (128 at 128^2, 96 at 256^2, 32 at 512^2), FP32,
+    nu = 1e-4, dt = 5e-4, `steps` RK4 steps in one graph launch."""
     sizes = I.ensemble_sizes()
-    nu, dt = 1e-4, 5e-4
-    steps = args.ens_steps
     fields = [I.ensemble_vorticity(r, n).astype(np.complex64) for r, n in enumerate(sizes)]
     log("ensemble inputs ready")
     t0 = time.perf_counter()
-    ens = fs.Ensemble(sizes, nu=nu, dt=dt)
+    ens = fs.Ensemble(sizes, nu=ENS_NU, dt=ENS_DT)
     log(f"ensemble created and tuned in {time.perf_counter() - t0:.2f} s: {ens.schedule()}")
     st = ens.pack(fields)
     ens.step(st, steps)  # warm-up: captures and runs the graph once
@@ -155,8 +166,24 @@ def bench_ensemble(args) -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     pts = sum(n * n for n in sizes)
-    rate = pts * steps / (t1 - t0)
-    finite = bool(torch.isfinite(torch.view_as_real(st)).all())
+    alg = ensemble_alg_bytes(sizes) * steps
+    res = {"gridpoint_steps_per_s": pts * steps / (t1 - t0), "ms_total": (t1 - t0) * 1e3,
+           "steps": steps, "gridpoints": pts,
+           "alg_bytes_per_step": alg / steps, "alg_GBps": alg / (t1 - t0) / 1e9,
+           "finite": bool(torch.isfinite(torch.view_as_real(st)).all()),
+           "schedule": ens.schedule()}
+    ens.close()
+    return res, sizes, fields
+
+
+def bench_ensemble(args) -> int:
+    import numpy as np
+    import torch
+    from paper_1807_01769_amd import fs, inputs as I
+
+    nu, dt, steps = ENS_NU, ENS_DT, args.ens_steps
+    res, sizes, fields = time_ensemble(fs, torch, I, np, steps)
+    rate, pts, finite = res["gridpoint_steps_per_s"], res["gridpoints"], res["finite"]
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -170,15 +197,68 @@ def bench_ensemble(args) -> int:
         cpu = {"value": 128 * 128 * k / el, "unit": "gridpoint-steps/s", "cores": oracle.get_threads(),
                "kind": "oracle", "sample": f"{k} FP64 RK4 steps of ensemble run 0 (128^2) in {el:.1f} s"}
     out = {"metric": "2D ensemble throughput (256 uneven runs, one graph launch)", "value": rate,
-           "unit": "gridpoint-steps/s", "n_gpus": 1, "steps": steps, "ms_total": (t1 - t0) * 1e3,
+           "unit": "gridpoint-steps/s", "n_gpus": 1, "steps": steps, "ms_total": res["ms_total"],
            "higher_is_better": True, "dtype": "f32", "data": "synthetic", "finite": finite,
            "config": {"workload": "2D NS ensemble: 128 runs at 128^2, 96 at 256^2, 32 at 512^2, "
                                   "FP32, nu=1e-4, dt=5e-4, E(k)~k exp(-(k/6)^2), seeds 1000+r",
                       "gridpoints": pts},
-           "schedule": ens.schedule(), "cpu_baseline": cpu}
+           "alg_GBps": res["alg_GBps"], "schedule": res["schedule"], "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
-    ens.close()
     return 0
+
+
+MLP_FLOP_PER_POINT = 2 * (9 * 64 + 64 * 64 + 64 * 6)  # forward multiply-adds x 2
+
+
+def time_mlp(fs, torch, points=64 ** 3, batch=8192, reps=20):
+    """Forward TFLOP/s of the closure network over one 64^3 field of features
+    and the rate of full Adam training steps (forward, backward, reduction,
+    update) on minibatches; random inputs, BF16 matrix cores."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    x = torch.randn((points, 16), generator=g, device="cuda").to(torch.bfloat16)
+    x[:, 9:] = 0
+    t = torch.randn((points, 6), generator=g, device="cuda")
+    net = fs.Mlp(seed=7)
+    net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / reps
+    xb, tb = x[:batch].contiguous(), t[:batch].contiguous()
+    net.train_step(xb, tb, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps * 5):
+        net.train_step(xb, tb, 1e-4)
+    torch.cuda.synchronize()
+    trn = (time.perf_counter() - t0) / (reps * 5)
+    net.close()
+    return {"forward_points": points, "forward_us": fwd * 1e6,
+            "forward_TFLOPs": MLP_FLOP_PER_POINT * points / fwd / 1e12,
+            "train_batch": batch, "train_step_us": trn * 1e6,
+            "train_TFLOPs": 3 * MLP_FLOP_PER_POINT * batch / trn / 1e12,
+            "peak_TFLOPs_bf16": 2500.0,
+            "note": "flop = 2 x multiply-adds of the three layers (GELU and biases not counted); "
+                    "training counted as 3 x forward"}
+
+
+def copy_ceiling(torch, gib=2.0, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written per second)."""
+    nb = int(gib * 2 ** 30) // 4
+    a = torch.ones(nb, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    del a, b
+    return {"GBps": 2 * nb * 4 / el / 1e9, "bytes_per_copy": nb * 4, "kind": "torch copy_"}
 
 
 def main() -> int:
@@ -196,6 +276,8 @@ def main() -> int:
     ap.add_argument("--les-n", type=int, default=64,
                     help="LES grid of the closure speedup measurement (0 = skip)")
     ap.add_argument("--les-steps", type=int, default=200)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the copy ceiling, network and ensemble measurements")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -254,6 +336,7 @@ def main() -> int:
         return 1
 
     kernels, roofline = {}, None
+    tr = read_traffic()
     if not args.graphs:
         prof = plan.profile_read()
         alg = algorithmic_bytes(n, args.steps)
@@ -266,7 +349,6 @@ def main() -> int:
             kernels[name] = rec
         dom = max((k for k in kernels if "alg_GBps" in kernels[k]), key=lambda k: kernels[k]["ms_total"])
         traffic = None
-        tr = read_traffic()
         if tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
             traffic = tr.get("bytes_per_launch", {}).get(dom)
         ach = kernels[dom]["alg_GBps"]
@@ -277,9 +359,30 @@ def main() -> int:
         step_alg = sum(v[0] for k, v in alg.items() if k != "p1") / args.steps
         roofline["step_alg_GBps"] = round(step_alg / (ms_per_step * 1e-3) / 1e9, 1)
 
+    if roofline is not None and tr and tr.get("source_hash") == kernel_source_hash() \
+            and tr.get("n") == n:
+        bpl = tr.get("bytes_per_launch", {})
+        names = [k for k in ("z_stage", "x_c2r_product_r2c", "y_inverse", "y_forward")
+                 if k in bpl and k in kernels]
+        step_bytes = sum(bpl[k] * kernels[k]["launches"] for k in names) / args.steps
+        roofline["step_measured_GBps"] = round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1)
+        roofline["step_measured_frac"] = round(roofline["step_measured_GBps"] / HBM_PEAK_GBS, 4)
+
     les = None
     if args.les_n > 0 and args.les_n < n:
         les = closure_les_speed(fs, torch, plan, state, args.les_n, args.les_steps, ms_per_step)
+    extras = {}
+    if not args.no_extras:
+        plan.close()
+        del state
+        torch.cuda.empty_cache()
+        extras["copy_ceiling"] = copy_ceiling(torch)
+        log(f"copy ceiling {extras['copy_ceiling']['GBps']:.0f} GB/s")
+        extras["mlp"] = time_mlp(fs, torch)
+        log(f"closure network: forward {extras['mlp']['forward_TFLOPs']:.1f} TFLOP/s")
+        ens, _, _ = time_ensemble(fs, torch, I, np, args.ens_steps)
+        extras["ensemble"] = ens
+        log(f"ensemble: {ens['gridpoint_steps_per_s']:.3e} gridpoint-steps/s")
 
     cpu = None
     if not args.no_cpu:
@@ -307,12 +410,14 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "closure_les": les,
+        **extras,
         "kernels": kernels,
         "energy_after": energy,
         "enstrophy_after": enstrophy,
     }
     print(json.dumps(out), flush=True)
-    plan.close()
+    if args.no_extras:
+        plan.close()
     return 0
 
 

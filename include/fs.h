@@ -168,6 +168,25 @@ fs_status fs_energy_spectrum(fs_plan *plan, const void *state, double *spectrum,
                              double *energy, double *enstrophy);
 
 /*
+ * Spectral energy budget of a tendency (the spectra of energy transfer the
+ * paper's output object provides, section "Implementation and
+ * architecture"): with tend = d state / dt (e.g. from fs_tendency; viscosity
+ * excluded, forcing included when the plan forces),
+ *   transfer[s] = sum over modes of shell s of w Re(conj(u_hat) . tend)
+ *                 (2D: w Re(conj(w_hat) tend) / |k|^2),
+ *   energy_rate = the sum over every kept mode (dE/dt of the tendency),
+ *   enstrophy_rate = sum w Re(conj(w_hat) . i k x tend) (2D: sum w
+ *                 Re(conj(w_hat) tend)).
+ *   flux[s] = -sum_{s' <= s} transfer[s'], the energy flux through shell s
+ *                 (nullable; summed in shell order).
+ * Same weights, shells, determinism and pointer rules as fs_energy_spectrum;
+ * state and tend are not modified.
+ */
+fs_status fs_energy_transfer(fs_plan *plan, const void *state, const void *tend,
+                             double *transfer, double *flux, int nbins, double *energy_rate,
+                             double *enstrophy_rate);
+
+/*
  * With FS_PROFILE: accumulate the elapsed time of every kernel launched since
  * the previous call (waits for them) into ms[kid] and launch counts into
  * counts[kid] for kid < nk; names[kid] receives a static kernel name.  Kernel

@@ -1,5 +1,6 @@
-// diag.hip -- FP64 diagnostics (energy, enstrophy, shell spectrum), the
-// constant-power forcing coefficient and a fill kernel.
+// diag.hip -- FP64 diagnostics (energy, enstrophy, shell spectrum; the
+// spectral energy transfer of a tendency), the constant-power forcing
+// coefficient and a fill kernel.
 //
 // All reductions are deterministic: every partial sum is formed in a fixed
 // order (per-lane accumulators, fixed shuffle trees, wave-private LDS bins,
@@ -22,10 +23,14 @@ __device__ __forceinline__ int j2i_rt(int j, int K, int n) { return j <= K ? j :
 // run along kx, where the shell index is non-decreasing, so the spectrum
 // contributions of a 64-mode chunk form contiguous segments that a segmented
 // scan sums before one lane per segment adds into the wave's own bins.
-template <typename T>
+// TR (transfer): with tend = dstate/dt the per-mode values become the rates
+// w Re(conj(u) . N) (binned) and w Re(conj(w) . curl N) (3D; 2D: the state
+// is the vorticity, energy rate w Re(conj(w) N) / |k|^2, enstrophy rate
+// w Re(conj(w) N)).
+template <typename T, bool TR>
 __global__ void __launch_bounds__(kDiagThreads)
-    k_diag1(const cx<T>* __restrict__ state, int ndim, int n, int K, double kb, int nbins,
-            double* __restrict__ partial) {
+    k_diag1(const cx<T>* __restrict__ state, const cx<T>* __restrict__ tend, int ndim, int n,
+            int K, double kb, int nbins, double* __restrict__ partial) {
   __shared__ double bins[kWaves][kDiagMaxBins];
   __shared__ double red[2][kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -60,16 +65,33 @@ __global__ void __launch_bounds__(kDiagThreads)
           const cx<T> a = state[rowoff + mx], b = state[cstride + rowoff + mx],
                       c = state[2 * cstride + rowoff + mx];
           const double ar = a.re, ai = a.im, br = b.re, bi = b.im, cr = c.re, ci = c.im;
-          eu = 0.5 * w * (ar * ar + ai * ai + br * br + bi * bi + cr * cr + ci * ci);
-          // |k x u|^2, real and imaginary parts separately
+          // k x u, real and imaginary parts separately
           const double x0r = ky * cr - kz * br, x0i = ky * ci - kz * bi;
           const double x1r = kz * ar - kx * cr, x1i = kz * ai - kx * ci;
           const double x2r = kx * br - ky * ar, x2i = kx * bi - ky * ai;
-          ez = 0.5 * w * (x0r * x0r + x0i * x0i + x1r * x1r + x1i * x1i + x2r * x2r + x2i * x2i);
+          if constexpr (TR) {
+            const cx<T> p = tend[rowoff + mx], q = tend[cstride + rowoff + mx],
+                        r = tend[2 * cstride + rowoff + mx];
+            const double pr = p.re, pi = p.im, qr = q.re, qi = q.im, rr = r.re, ri = r.im;
+            eu = w * (ar * pr + ai * pi + br * qr + bi * qi + cr * rr + ci * ri);
+            const double y0r = ky * rr - kz * qr, y0i = ky * ri - kz * qi;
+            const double y1r = kz * pr - kx * rr, y1i = kz * pi - kx * ri;
+            const double y2r = kx * qr - ky * pr, y2i = kx * qi - ky * pi;
+            ez = w * (x0r * y0r + x0i * y0i + x1r * y1r + x1i * y1i + x2r * y2r + x2i * y2i);
+          } else {
+            eu = 0.5 * w * (ar * ar + ai * ai + br * br + bi * bi + cr * cr + ci * ci);
+            ez = 0.5 * w * (x0r * x0r + x0i * x0i + x1r * x1r + x1i * x1i + x2r * x2r + x2i * x2i);
+          }
           s = (int)floor(sqrt((double)m2) + 0.5);
         } else if (m2 > 0) {
           const cx<T> a = state[rowoff + mx];
-          const double a2 = (double)a.re * a.re + (double)a.im * a.im;
+          double a2;
+          if constexpr (TR) {
+            const cx<T> p = tend[rowoff + mx];
+            a2 = 2.0 * ((double)a.re * p.re + (double)a.im * p.im);
+          } else {
+            a2 = (double)a.re * a.re + (double)a.im * a.im;
+          }
           const double k2 = kx * kx + ky * ky;
           eu = 0.5 * w * a2 / k2;
           ez = 0.5 * w * a2;
@@ -137,6 +159,15 @@ __global__ void __launch_bounds__(kDiagThreads)
   }
 }
 
+// flux[s] = -(transfer[0] + ... + transfer[s]), summed in shell order
+__global__ void k_flux(const double* __restrict__ transfer, int nbins, double* __restrict__ flux) {
+  double c = 0.0;
+  for (int s = 0; s < nbins; s++) {
+    c += transfer[s];
+    flux[s] = -c;
+  }
+}
+
 // Forcing coefficient alpha = power / sum_band w |u_hat|^2 (0 if the band is
 // empty), one block, fixed-order tree.
 template <typename T>
@@ -188,12 +219,36 @@ void launch_diag(Plan* p, const void* state, double* spectrum, int nbins, double
   int blocks = (rows + kWaves - 1) / kWaves;
   if (blocks > p->dpart_blocks) blocks = p->dpart_blocks;
   p->begin(KID_DIAG);
-  hipLaunchKernelGGL((k_diag1<T>), dim3(blocks), dim3(kDiagThreads), 0, p->launch,
-                     (const cx<T>*)state, p->ndim, p->n, K, 2.0 * M_PI / p->L, nbins, p->dpart);
+  hipLaunchKernelGGL((k_diag1<T, false>), dim3(blocks), dim3(kDiagThreads), 0, p->launch,
+                     (const cx<T>*)state, (const cx<T>*)nullptr, p->ndim, p->n, K,
+                     2.0 * M_PI / p->L, nbins, p->dpart);
   launched(p, "k_diag1");
   hipLaunchKernelGGL(k_diag2, dim3(1), dim3(kDiagThreads), 0, p->launch, (const double*)p->dpart,
                      blocks, nbins, spectrum, energy, enstrophy);
   launched(p, "k_diag2");
+  p->end(KID_DIAG);
+}
+
+template <typename T>
+void launch_transfer(Plan* p, const void* state, const void* tend, double* transfer,
+                     double* flux, int nbins, double* energy_rate, double* enstrophy_rate) {
+  const int K = (p->n - 1) / 3, M = 2 * K + 1;
+  const int rows = p->ndim == 3 ? M * M : M;
+  int blocks = (rows + kWaves - 1) / kWaves;
+  if (blocks > p->dpart_blocks) blocks = p->dpart_blocks;
+  p->begin(KID_DIAG);
+  hipLaunchKernelGGL((k_diag1<T, true>), dim3(blocks), dim3(kDiagThreads), 0, p->launch,
+                     (const cx<T>*)state, (const cx<T>*)tend, p->ndim, p->n, K,
+                     2.0 * M_PI / p->L, nbins, p->dpart);
+  launched(p, "k_diag1 transfer");
+  hipLaunchKernelGGL(k_diag2, dim3(1), dim3(kDiagThreads), 0, p->launch, (const double*)p->dpart,
+                     blocks, nbins, transfer, energy_rate, enstrophy_rate);
+  launched(p, "k_diag2");
+  if (flux) {
+    hipLaunchKernelGGL(k_flux, dim3(1), dim3(1), 0, p->launch, (const double*)transfer, nbins,
+                       flux);
+    launched(p, "k_flux");
+  }
   p->end(KID_DIAG);
 }
 
@@ -220,6 +275,10 @@ void launch_fill(Plan* p, void* ptr, size_t n_complex) {
 
 template void launch_diag<float>(Plan*, const void*, double*, int, double*, double*);
 template void launch_diag<double>(Plan*, const void*, double*, int, double*, double*);
+template void launch_transfer<float>(Plan*, const void*, const void*, double*, double*, int,
+                                     double*, double*);
+template void launch_transfer<double>(Plan*, const void*, const void*, double*, double*, int,
+                                      double*, double*);
 template void launch_alpha<float>(Plan*, const void*);
 template void launch_alpha<double>(Plan*, const void*);
 template void launch_fill<float>(Plan*, void*, size_t);

@@ -391,6 +391,18 @@ fs_status fs_energy_spectrum(fs_plan* plan, const void* state, double* spectrum,
   return device_status(&plan->p);
 }
 
+fs_status fs_energy_transfer(fs_plan* plan, const void* state, const void* tend, double* transfer,
+                             double* flux, int nbins, double* energy_rate,
+                             double* enstrophy_rate) {
+  if (fs_status s = usable(plan)) return s;
+  if (!state || !tend || !transfer) return fail(FS_E_INVALID, "NULL array");
+  if (nbins < 1 || nbins > fs::kDiagMaxBins)
+    return fail(FS_E_INVALID, "nbins = %d must be in 1..%d", nbins, fs::kDiagMaxBins);
+  plan->p.ops.transfer(&plan->p, state, tend, transfer, flux, nbins, energy_rate,
+                       enstrophy_rate);
+  return device_status(&plan->p);
+}
+
 fs_status fs_profile_read(fs_plan* plan, double* ms, long* counts, const char** names, int nk) {
   if (fs_status s = usable(plan)) return s;
   Plan* p = &plan->p;

@@ -48,6 +48,9 @@ struct Ops {
   // diagnostics
   void (*diag)(Plan*, const void* state, double* spectrum, int nbins, double* energy,
                double* enstrophy);
+  // spectral energy transfer of a tendency
+  void (*transfer)(Plan*, const void* state, const void* tend, double* transfer, double* flux,
+                   int nbins, double* energy_rate, double* enstrophy_rate);
   // workspace element counts (complex elements of the plan's precision)
   size_t elems_a, elems_b, elems_acc;
   size_t elems_full;  // one undealiased field in the transform workspace layout
@@ -105,6 +108,9 @@ Ops make_ops2(int n);
 template <typename T>
 void launch_diag(Plan* p, const void* state, double* spectrum, int nbins, double* energy,
                  double* enstrophy);
+template <typename T>
+void launch_transfer(Plan* p, const void* state, const void* tend, double* transfer,
+                     double* flux, int nbins, double* energy_rate, double* enstrophy_rate);
 template <typename T>
 void launch_alpha(Plan* p, const void* state);
 template <typename T>

@@ -111,6 +111,7 @@ struct L2 {
     o.fft_inv = fft_inv;
     o.alpha = nullptr;
     o.diag = launch_diag<T>;
+    o.transfer = launch_transfer<T>;
     const size_t wn3 = (size_t)3 * G::XT * N * kTile;
     const size_t wn2 = (size_t)2 * G::XT * N * kTile;
     const size_t wfull = (size_t)GF::XT * N * kTile;

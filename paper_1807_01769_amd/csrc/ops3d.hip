@@ -151,6 +151,7 @@ struct L3 {
     o.fft_inv_n = fft_inv_n;
     o.alpha = launch_alpha<T>;
     o.diag = launch_diag<T>;
+    o.transfer = launch_transfer<T>;
     const size_t wm6 = (size_t)6 * N * G::XT * G::M * kTile;
     const size_t wn6 = (size_t)6 * N * G::XT * N * kTile;
     const size_t wfull = (size_t)N * GF::XT * N * kTile;

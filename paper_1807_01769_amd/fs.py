@@ -52,6 +52,7 @@ lib.fs_fft_inverse.argtypes = [_vp, _vp, _vp]
 lib.fs_tendency.argtypes = [_vp, _vp, _vp]
 lib.fs_step_rk4.argtypes = [_vp, _vp, _i]
 lib.fs_energy_spectrum.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
+lib.fs_energy_transfer.argtypes = [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp]
 lib.fs_profile_read.argtypes = [_vp, C.POINTER(_d), C.POINTER(C.c_long), C.POINTER(C.c_char_p), _i]
 lib.fs_status_str.argtypes = [_i]
 lib.fs_status_str.restype = C.c_char_p
@@ -59,7 +60,8 @@ lib.fs_last_error.argtypes = []
 lib.fs_last_error.restype = C.c_char_p
 for _f in ("fs_plan_create", "fs_plan_destroy", "fs_plan_set_stream", "fs_state_elems",
            "fs_workspace_bytes", "fs_spectrum_bins", "fs_fft_forward", "fs_fft_inverse",
-           "fs_tendency", "fs_step_rk4", "fs_energy_spectrum", "fs_profile_read"):
+           "fs_tendency", "fs_step_rk4", "fs_energy_spectrum", "fs_energy_transfer",
+           "fs_profile_read"):
     getattr(lib, _f).restype = _i
 
 
@@ -187,6 +189,24 @@ class Plan:
                                       spec.data_ptr(), nbins, ez.data_ptr(), ez.data_ptr() + 8),
                "fs_energy_spectrum")
         return spec, ez[0:1], ez[1:2]
+
+    def energy_transfer(self, state: torch.Tensor, tend: torch.Tensor | None = None,
+                        nbins: int | None = None):
+        """Device float64 tensors (transfer[nbins], flux[nbins], energy_rate[1],
+        enstrophy_rate[1]) of the tendency `tend` (default: fs_tendency of
+        `state`); flux[s] = -sum_{s' <= s} transfer[s'] is the energy flux
+        through shell s."""
+        nbins = self.spectrum_bins() if nbins is None else int(nbins)
+        if tend is None:
+            tend = self.tendency(state)
+        tr = torch.empty(nbins, dtype=torch.float64, device=state.device)
+        fl = torch.empty(nbins, dtype=torch.float64, device=state.device)
+        ez = torch.empty(2, dtype=torch.float64, device=state.device)
+        _check(lib.fs_energy_transfer(
+            self._h, self._arg(state, self.state_shape, self.complex_dtype, "state"),
+            self._arg(tend, self.state_shape, self.complex_dtype, "tend"), tr.data_ptr(),
+            fl.data_ptr(), nbins, ez.data_ptr(), ez.data_ptr() + 8), "fs_energy_transfer")
+        return tr, fl, ez[0:1], ez[1:2]
 
     def profile_read(self) -> dict:
         """Per-kernel (total ms, launches) since the previous read (profile=True plans)."""

@@ -84,6 +84,7 @@ def test_null_arguments(lib):
     assert lib.fs_plan_create(None, 64, 6.28, 0.1, 0.01, None) == -1
     for fn, nargs in [("fs_step_rk4", 3), ("fs_tendency", 3), ("fs_fft_forward", 3),
                       ("fs_fft_inverse", 3), ("fs_energy_spectrum", 6), ("fs_plan_set_stream", 2),
+                      ("fs_energy_transfer", 8),
                       ("fs_profile_read", 5)]:
         f = getattr(lib, fn)
         f.argtypes = [C.c_void_p] * nargs

@@ -1,0 +1,65 @@
+"""GPU parity of the spectral energy budget (fs_energy_transfer) against the
+FP64 oracle: the reduction alone on identical inputs (FP64 accumulation of
+the same values: 1e-12), and the whole chain state -> GPU tendency ->
+transfer (the tendency's FP32 tolerance, 1e-5 of the largest shell)."""
+import numpy as np
+import pytest
+
+from paper_1807_01769_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fs():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1807_01769_amd import fs as _fs
+    return _fs
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("power", [0.0, 0.3])
+def test_transfer3d(fs, oracle_mod, prec, power):
+    print(f"case transfer3d n=32 {prec} power={power}", flush=True)
+    n, nbins = 32, 24
+    cd = np.complex64 if prec == "f32" else np.complex128
+    u = I.random_solenoidal_3d(n, seed=41, dtype=cd)
+    plan = fs.Plan(n, nu=1e-3, dt=1e-3, precision=prec, forcing_power=power)
+    ud = torch.from_numpy(u).cuda()
+    nd = plan.tendency(ud)
+    T, F, er, zr = plan.energy_transfer(ud, nd, nbins)
+    u64 = u.astype(np.complex128)
+    # the reduction alone, on the GPU's own tendency
+    n64 = nd.cpu().numpy().astype(np.complex128)
+    rT, re_, rz = oracle_mod.transfer3d(u64, n64, nbins)
+    T, F = T.cpu().numpy(), F.cpu().numpy()
+    sc = np.abs(rT).max()
+    assert np.abs(T - rT).max() <= 1e-12 * sc
+    assert np.abs(F + np.cumsum(rT)).max() <= 1e-12 * sc * nbins
+    assert abs(float(zr.item()) - rz) <= 1e-12 * abs(rz)
+    # the whole chain against the oracle's tendency
+    alpha = oracle_mod.forcing_alpha3d(u64, power) if power else 0.0
+    oT, oe, oz = oracle_mod.transfer3d(u64, oracle_mod.tendency3d(u64, alpha=alpha), nbins)
+    tol = 1e-5 if prec == "f32" else 1e-11
+    err = np.abs(T - oT).max() / np.abs(oT).max()
+    print(f"shell transfer max err {err:.2e}; dE/dt {float(er.item()):.6e} vs {oe:.6e}", flush=True)
+    assert err <= tol
+    assert abs(float(er.item()) - oe) <= tol * np.abs(oT).max() * nbins
+    if power:
+        assert abs(float(er.item()) - power) <= tol * 10 * power
+    plan.close()
+
+
+def test_transfer2d_fp64(fs, oracle_mod):
+    n, nbins = 64, 32
+    w = I.random_vorticity_2d(n, 42, lambda k: k * np.exp(-(k / 6.0) ** 2))
+    plan = fs.Plan(n, nu=1e-3, dt=1e-3, ndim=2, precision="f64")
+    wd = torch.from_numpy(w).cuda()
+    T, F, er, zr = plan.energy_transfer(wd, None, nbins)
+    oT, oe, oz = oracle_mod.transfer2d(w, oracle_mod.tendency2d(w), nbins)
+    T = T.cpu().numpy()
+    assert np.abs(T - oT).max() <= 1e-11 * np.abs(oT).max()
+    assert abs(float(zr.item()) - oz) <= 1e-11 * np.abs(oT).max() * nbins
+    plan.close()
