@@ -160,21 +160,6 @@ __global__ void __launch_bounds__(kThr)
   }
 }
 
-// network output [np][6] (standardised) -> physical stress [6][np]:
-// tau_s = clip(y_s) * scale_s (no clipping when clip <= 0)
-__global__ void __launch_bounds__(kThr)
-    k_tau_from_y(const float* __restrict__ y, int64_t np, Six scale, float clip,
-                 float* __restrict__ tau) {
-  const int64_t q = (int64_t)blockIdx.x * kThr + threadIdx.x;
-  if (q >= np) return;
-#pragma unroll
-  for (int s = 0; s < 6; s++) {
-    float v = y[q * 6 + s];
-    if (clip > 0.f) v = fminf(fmaxf(v, -clip), clip);
-    tau[s * np + q] = v * scale.v[s];
-  }
-}
-
 // tend += P[-i k_j tau_ij^] on the kept set, k != 0 (P v = v - k (k.v)/|k|^2)
 __global__ void __launch_bounds__(kThr)
     k_sgs(cf* __restrict__ tend, const cf* __restrict__ th, int n, float kb) {
@@ -441,8 +426,8 @@ struct fs_les {
   fs::Six scale{};
   void* base = nullptr;
   cf *acc = nullptr, *v = nullptr, *k = nullptr, *grad = nullptr, *th = nullptr;
-  float *A = nullptr, *tau = nullptr, *y = nullptr;
-  void *x = nullptr, *wa = nullptr, *wb = nullptr;
+  float *A = nullptr, *tau = nullptr;
+  void *wa = nullptr, *wb = nullptr;
   hipGraphExec_t graph = nullptr;
   void* gstate = nullptr;
 };
@@ -461,15 +446,12 @@ void les_tendency(fs_les* les, const void* state, cf* tend, bool fresh_alpha) {
                      (const cf*)state, les->grad, n, kb);
   fs::plan_ok(p, "k_grad");
   p->ops.fft_inv_n(p, les->grad, les->A, 9, les->wa, les->wb);
-  hipLaunchKernelGGL(fs::k_features, dim3(fs::blocks_for(np)), dim3(fs::kThr), 0, p->launch,
-                     (const float*)les->A, np, les->inv_a, (uint4*)les->x, (const float*)nullptr,
-                     fs::Six{}, (float*)nullptr);
-  fs::plan_ok(p, "k_features");
-  fs::mlp_forward_launch(fs::mlp_of(les->net), les->x, les->y, np, nullptr, p->launch);
-  fs::plan_ok(p, "k_mlp_forward");
-  hipLaunchKernelGGL(fs::k_tau_from_y, dim3(fs::blocks_for(np)), dim3(fs::kThr), 0, p->launch,
-                     (const float*)les->y, np, les->scale, les->clip, les->tau);
-  fs::plan_ok(p, "k_tau_from_y");
+  fs::StressMap sm;
+  for (int c = 0; c < 6; c++) sm.scale[c] = les->scale.v[c];
+  sm.clip = les->clip;
+  fs::mlp_forward_planar_launch(fs::mlp_of(les->net), les->A, np, les->inv_a, les->tau, sm,
+                                p->launch);
+  fs::plan_ok(p, "k_mlp_forward_planar");
   p->ops.fft_fwd_n(p, les->tau, les->th, 6, les->wa, les->wb);
   hipLaunchKernelGGL(fs::k_sgs, dim3(fs::blocks_for(ns)), dim3(fs::kThr), 0, p->launch, tend,
                      (const cf*)les->th, n, kb);
@@ -566,8 +548,7 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
     const size_t o_acc = cv.take(sizeof(cf) * 3 * ns), o_v = cv.take(sizeof(cf) * 3 * ns),
                  o_k = cv.take(sizeof(cf) * 3 * ns), o_grad = cv.take(sizeof(cf) * 9 * ns),
                  o_th = cv.take(sizeof(cf) * 6 * ns), o_A = cv.take(sizeof(float) * 9 * np),
-                 o_tau = cv.take(sizeof(float) * 6 * np), o_y = cv.take(sizeof(float) * 6 * np),
-                 o_x = cv.take(sizeof(short) * 16 * np),
+                 o_tau = cv.take(sizeof(float) * 6 * np),
                  o_wa = cv.take(sizeof(cf) * 9 * coarse->p.ops.elems_full),
                  o_wb = cv.take(sizeof(cf) * 9 * coarse->p.ops.elems_full);
     if (hipMalloc(&les->base, cv.total) != hipSuccess) {
@@ -583,8 +564,6 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
     les->th = (cf*)(b + o_th);
     les->A = (float*)(b + o_A);
     les->tau = (float*)(b + o_tau);
-    les->y = (float*)(b + o_y);
-    les->x = b + o_x;
     les->wa = b + o_wa;
     les->wb = b + o_wb;
   }

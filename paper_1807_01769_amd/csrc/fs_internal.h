@@ -120,6 +120,14 @@ void launch_fill(Plan* p, void* ptr, size_t n_complex);
 struct Mlp;
 void mlp_forward_launch(Mlp* net, const void* x, float* y, int64_t P, const float* out_scale,
                         hipStream_t s);
+// network output o -> stress: clip(y_o) * scale[o] (clip <= 0: none)
+struct StressMap {
+  float scale[6];
+  float clip;
+};
+// tau[6][P] = StressMap(net(BF16(A[9][P] * inv_a)))
+void mlp_forward_planar_launch(Mlp* net, const float* A, int64_t P, float inv_a, float* tau,
+                               StressMap sm, hipStream_t s);
 int mlp_nparams();
 
 constexpr int kDiagThreads = 256;

@@ -314,13 +314,25 @@ __global__ void __launch_bounds__(kThreads)
   if (l == 0) out[NPARAM] = loss / ((float)P * kOut);
 }
 
-// grad[i] = sum over waves (wave order) of partial[w][i]; loss (FP64) likewise
-__global__ void k_mlp_reduce(const float* __restrict__ partial, int nw, float* __restrict__ grad,
-                             double* __restrict__ loss) {
+// Deterministic two-level sum of the wave partials: group g of kGroup waves
+// (wave order) -> part2[g][i] in FP64, then the groups in order -> grad[i]
+// (and the loss, slot NPARAM).  Grid of the first level: (params, groups).
+constexpr int kGroup = 32, kMaxGroups = 1024 / kGroup;
+__global__ void k_mlp_reduce1(const float* __restrict__ partial, int nw,
+                              double* __restrict__ part2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > NPARAM) return;
+  const int w0 = blockIdx.y * kGroup, w1 = w0 + kGroup < nw ? w0 + kGroup : nw;
+  double s = 0.0;
+  for (int w = w0; w < w1; w++) s += partial[(size_t)w * (NPARAM + 1) + i];
+  part2[(size_t)blockIdx.y * (NPARAM + 1) + i] = s;
+}
+__global__ void k_mlp_reduce2(const double* __restrict__ part2, int ng, float* __restrict__ grad,
+                              double* __restrict__ loss) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > NPARAM) return;
   double s = 0.0;
-  for (int w = 0; w < nw; w++) s += partial[(size_t)w * (NPARAM + 1) + i];
+  for (int g = 0; g < ng; g++) s += part2[(size_t)g * (NPARAM + 1) + i];
   if (i < NPARAM) {
     if (grad) grad[i] = (float)s;
   } else if (loss) {
@@ -353,6 +365,7 @@ struct Mlp {
   hipStream_t stream = nullptr;
   void* base = nullptr;
   float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *partial = nullptr;
+  double* part2 = nullptr;
   s4* packed = nullptr;
   int nwaves = 0, step = 0;
   bool failed = false;
@@ -370,6 +383,53 @@ struct Mlp {
 };
 
 // used by the closure/LES code
+// The LES form: features read planar from the gradients A[9][P] and
+// standardised and rounded exactly as k_features stores them; outputs
+// clipped, scaled and written planar as the stress tau[6][P].
+__global__ void __launch_bounds__(kThreads)
+    k_mlp_forward_planar(const float* __restrict__ A, int64_t P, float inv_a,
+                         float* __restrict__ tau, StressMap sm, const s4* __restrict__ pk,
+                         const float* __restrict__ w) {
+  const int l = threadIdx.x % 64;
+  const int64_t wave = (int64_t)blockIdx.x * kWaves + threadIdx.x / 64;
+  const int64_t nw = (int64_t)gridDim.x * kWaves;
+  Net n;
+  load_net(n, pk, w, l);
+  const int r0 = 4 * (l / 16);
+  const int64_t ntiles = (P + 15) / 16;
+  for (int64_t tile = wave; tile < ntiles; tile += nw) {
+    const int64_t p = tile * 16 + (l % 16);
+    s4 xin = {0, 0, 0, 0};
+    if (p < P) {
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (r0 + j < kIn) xin[j] = to_bf16(A[(r0 + j) * P + p] * inv_a);
+    }
+    f4 z1[4], z2[4];
+    s4 h1[4], h2[4];
+    const f4 out = forward_tile(n, xin, z1, h1, z2, h2);
+    if (p < P) {
+#pragma unroll
+      for (int j = 0; j < 4; j++)
+        if (r0 + j < kOut) {
+          float v = out[j];
+          if (sm.clip > 0.f) v = fminf(fmaxf(v, -sm.clip), sm.clip);
+          tau[(r0 + j) * P + p] = v * sm.scale[r0 + j];
+        }
+    }
+  }
+}
+
+void mlp_forward_planar_launch(Mlp* net, const float* A, int64_t P, float inv_a, float* tau,
+                               StressMap sm, hipStream_t s) {
+  const int64_t tiles = (P + 15) / 16;
+  int64_t blocks = (tiles + kWaves - 1) / kWaves;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_mlp_forward_planar, dim3((unsigned)blocks), dim3(kThreads), 0, s, A, P,
+                     inv_a, tau, sm, net->packed, net->w);
+}
+
 void mlp_forward_launch(Mlp* net, const void* x, float* y, int64_t P, const float* out_scale,
                         hipStream_t s) {
   const int64_t tiles = (P + 15) / 16;
@@ -407,7 +467,8 @@ fs_status fs_mlp_create(fs_mlp** out, uint64_t seed, void* stream) {
   n->nwaves = 1024;
   const size_t np = fs::NPARAM;
   const size_t bytes = 4 * (4 * np + 64) + sizeof(fs::s4) * fs::NBLK * 64 +
-                       4 * (size_t)n->nwaves * (np + 1) + 1024;
+                       4 * (size_t)n->nwaves * (np + 1) + 8 * (size_t)fs::kMaxGroups * (np + 1) +
+                       2048;
   if (hipMalloc(&n->base, bytes) != hipSuccess) {
     hipGetLastError();
     delete h;
@@ -426,6 +487,7 @@ fs_status fs_mlp_create(fs_mlp** out, uint64_t seed, void* stream) {
   n->g = (float*)take(4 * np);
   n->packed = (fs::s4*)take(sizeof(fs::s4) * fs::NBLK * 64);
   n->partial = (float*)take(4 * (size_t)n->nwaves * (np + 1));
+  n->part2 = (double*)take(8 * (size_t)fs::kMaxGroups * (np + 1));
   // Xavier-uniform initial weights from a counter-based hash of (seed, index);
   // biases zero
   std::vector<float> hw(np, 0.f);
@@ -515,14 +577,25 @@ fs_status fs_mlp_forward(fs_mlp* net, const void* x_bf16, float* y, int64_t npts
   return n->launched("k_mlp_forward") ? FS_OK : FS_E_DEVICE;
 }
 
+// The gradient kernel runs one wave per 16-point tile up to n->nwaves waves
+// (then waves loop over tiles); the partials are summed in two fixed-order
+// levels, so the result is deterministic for a given npts.
 static fs_status mlp_grad_impl(fs::Mlp* n, const void* x, const float* t, int64_t P, float* grad,
                                double* loss) {
-  hipLaunchKernelGGL(fs::k_mlp_grad, dim3(n->nwaves / fs::kWaves), dim3(fs::kThreads), 0,
-                     n->stream, (const short*)x, t, P, n->packed, (const float*)n->w, n->partial);
+  const int64_t tiles = (P + 15) / 16;
+  int nw = (int)(tiles < n->nwaves ? tiles : n->nwaves);
+  nw = (nw + fs::kWaves - 1) / fs::kWaves * fs::kWaves;
+  hipLaunchKernelGGL(fs::k_mlp_grad, dim3(nw / fs::kWaves), dim3(fs::kThreads), 0, n->stream,
+                     (const short*)x, t, P, n->packed, (const float*)n->w, n->partial);
   if (!n->launched("k_mlp_grad")) return FS_E_DEVICE;
-  hipLaunchKernelGGL(fs::k_mlp_reduce, dim3((fs::NPARAM + 1 + 255) / 256), dim3(256), 0,
-                     n->stream, (const float*)n->partial, n->nwaves, grad, loss);
-  return n->launched("k_mlp_reduce") ? FS_OK : FS_E_DEVICE;
+  const int ng = (nw + fs::kGroup - 1) / fs::kGroup;
+  const unsigned pb = (fs::NPARAM + 1 + 255) / 256;
+  hipLaunchKernelGGL(fs::k_mlp_reduce1, dim3(pb, ng), dim3(256), 0, n->stream,
+                     (const float*)n->partial, nw, n->part2);
+  if (!n->launched("k_mlp_reduce1")) return FS_E_DEVICE;
+  hipLaunchKernelGGL(fs::k_mlp_reduce2, dim3(pb), dim3(256), 0, n->stream,
+                     (const double*)n->part2, ng, grad, loss);
+  return n->launched("k_mlp_reduce2") ? FS_OK : FS_E_DEVICE;
 }
 
 fs_status fs_mlp_grad(fs_mlp* net, const void* x_bf16, const float* y_target, int64_t npts,
