@@ -26,6 +26,9 @@ Pins (tests/test_oracle_*.py, all CPU):
   forcing_alpha3d        injected power equals the prescribed power
   diag2d / diag3d        closed-form Taylor-Green energy, enstrophy and shell,
                          sum of the spectrum equals the energy
+  spectra1d2d / 3d       single Fourier modes land in their bins with the
+                         closed-form energy; every axis sums to the component
+                         energy measured in physical space
   transfer2d / 3d        per-shell dE/dt at nu = 0 from centred differences of
                          the shell spectrum under the exact-in-time step
                          (fourth-order scheme); total 0 without forcing (and
@@ -97,6 +100,8 @@ def lib():
         L.or_adam.argtypes = [vp, vp, vp, vp, i, i, d, d, d, d]
         L.or_tendency3d_les.argtypes = [i, d, vp, vp, vp]
         L.or_lawson_scalar.restype = d
+        L.or_spectra1d3d.argtypes = [i, vp, vp]
+        L.or_spectra1d2d.argtypes = [i, d, vp, vp]
         L.or_transfer3d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
         L.or_transfer2d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
         L.or_round_bf16.argtypes = [d]
@@ -205,6 +210,24 @@ def diag2d(wh, nbins, L=2 * np.pi):
     e, z = C.c_double(), C.c_double()
     lib().or_diag2d(w.shape[0], float(L), _p(w), int(nbins), _p(spec), C.byref(e), C.byref(z))
     return spec, e.value, z.value
+
+
+def spectra1d3d(uh):
+    """[axis x,y,z][component][k = 0..K] energies binned by |m_axis|."""
+    u = _c128(uh)
+    n = u.shape[1]
+    out = np.zeros((3, 3, (n - 1) // 3 + 1))
+    lib().or_spectra1d3d(n, _p(u), _p(out))
+    return out
+
+
+def spectra1d2d(wh, L=2 * np.pi):
+    """[axis x,y][velocity component u,v][k = 0..K]."""
+    w = _c128(wh)
+    n = w.shape[0]
+    out = np.zeros((2, 2, (n - 1) // 3 + 1))
+    lib().or_spectra1d2d(n, float(L), _p(w), _p(out))
+    return out
 
 
 def transfer3d(uh, nh, nbins, L=2 * np.pi):

@@ -535,6 +535,48 @@ void or_diag2d(int n, double L, const cplx *wh, int nbins, double *spec, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* 1D spectra: energy of each velocity component binned by the modulus of   */
+/* one wavenumber component, out[a][c][k] = 1/2 sum over kept modes with     */
+/* |m_a| = k of w |u_c_hat|^2, k = 0..K (a = x, y, z; 2D: a = x, y and the   */
+/* velocity u_hat = i ky w_hat/|k|^2, v_hat = -i kx w_hat/|k|^2).            */
+/* ------------------------------------------------------------------------ */
+void or_spectra1d3d(int n, const cplx *uh, double *out) {
+  const int K = (n - 1) / 3, nb = K + 1;
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
+  for (int i = 0; i < 9 * nb; i++) out[i] = 0.0;
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int m[3] = {ix, mode_full(iy, n), mode_full(iz, n)};
+    if (!(keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n))) continue;
+    double w = ix == 0 ? 1.0 : 2.0;
+    for (int c = 0; c < 3; c++) {
+      const cplx u = uh[c * ns + i];
+      const double e = 0.5 * w * creal(u * conj(u));
+      for (int a = 0; a < 3; a++) out[(a * 3 + c) * nb + abs(m[a])] += e;
+    }
+  }
+}
+
+void or_spectra1d2d(int n, double L, const cplx *wh, double *out) {
+  const int K = (n - 1) / 3, nb = K + 1;
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * h;
+  const double kb = 2.0 * M_PI / L;
+  for (int i = 0; i < 4 * nb; i++) out[i] = 0.0;
+  for (int64_t i = 0; i < ns; i++) {
+    int m[2] = {(int)(i % h), mode_full((int)(i / h), n)};
+    if (!(keep1(m[0], n) && keep1(m[1], n))) continue;
+    if (m[0] == 0 && m[1] == 0) continue;
+    double w = m[0] == 0 ? 1.0 : 2.0;
+    double kx = kb * m[0], ky = kb * m[1], k2 = kx * kx + ky * ky;
+    const cplx vel[2] = {I * ky * wh[i] / k2, -I * kx * wh[i] / k2};
+    for (int c = 0; c < 2; c++) {
+      const double e = 0.5 * w * creal(vel[c] * conj(vel[c]));
+      for (int a = 0; a < 2; a++) out[(a * 2 + c) * nb + abs(m[a])] += e;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Spectral energy budget: with E = 1/2 sum w |u_hat|^2 and du_hat/dt = N_hat  */
 /* (no viscosity), dE/dt = sum w Re(conj(u_hat) . N_hat); its shell sums are   */
 /* the transfer T(s), s = floor(|m| + 1/2) (bins >= nbins dropped from T       */
