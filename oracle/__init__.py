@@ -23,6 +23,10 @@ Pins (tests/test_oracle_*.py, all CPU):
   step2d / step3d        exact decaying Taylor-Green / ABC solutions, a scalar
                          ODE with closed form (order-4 convergence of the
                          Lawson scheme), energy budget dE/dt = -2 nu Z
+  step*_ex (RK2, CFL)    order 2 of the Lawson midpoint rule on the scalar ODE,
+                         exact decays, the CFL step from the physical velocity
+                         maximum (checked against numpy's inverse FFT), the
+                         fixed step when the CFL bound exceeds it
   forcing_alpha3d        injected power equals the prescribed power
   diag2d / diag3d        closed-form Taylor-Green energy, enstrophy and shell,
                          sum of the spectrum equals the energy
@@ -100,6 +104,12 @@ def lib():
         L.or_adam.argtypes = [vp, vp, vp, vp, i, i, d, d, d, d]
         L.or_tendency3d_les.argtypes = [i, d, vp, vp, vp]
         L.or_lawson_scalar.restype = d
+        L.or_lawson_scalar2.argtypes = [d, d, d, i]
+        L.or_lawson_scalar2.restype = d
+        L.or_step3d_ex.argtypes = [i, d, d, d, d, d, d, i, d, vp, i, vp]
+        L.or_step2d_ex.argtypes = [i, d, d, d, i, d, vp, i, vp]
+        L.or_umax.argtypes = [i, i, d, vp]
+        L.or_umax.restype = d
         L.or_spectra1d3d.argtypes = [i, vp, vp]
         L.or_spectra1d2d.argtypes = [i, d, vp, vp]
         L.or_transfer3d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
@@ -194,6 +204,35 @@ def step2d(wh, nu, dt, nsteps, L=2 * np.pi):
     w = _c128(wh).copy()
     lib().or_step2d(w.shape[0], float(L), float(nu), float(dt), _p(w), int(nsteps))
     return w
+
+
+def step3d_ex(uh, nu, dt_max, nsteps, scheme=4, cfl=0.0, L=2 * np.pi, power=0.0, kf_min=2.0,
+              kf_max=3.0):
+    """(state after nsteps, elapsed time) with scheme 4 / 2 and optional CFL steps."""
+    u = _c128(uh).copy()
+    t = C.c_double(0.0)
+    lib().or_step3d_ex(u.shape[1], float(L), float(nu), float(dt_max), float(power),
+                       float(kf_min), float(kf_max), int(scheme), float(cfl), _p(u), int(nsteps),
+                       C.byref(t))
+    return u, t.value
+
+
+def step2d_ex(wh, nu, dt_max, nsteps, scheme=4, cfl=0.0, L=2 * np.pi):
+    w = _c128(wh).copy()
+    t = C.c_double(0.0)
+    lib().or_step2d_ex(w.shape[0], float(L), float(nu), float(dt_max), int(scheme), float(cfl),
+                       _p(w), int(nsteps), C.byref(t))
+    return w, t.value
+
+
+def umax(state, ndim, L=2 * np.pi):
+    s = _c128(state)
+    n = s.shape[1] if ndim == 3 else s.shape[0]
+    return float(lib().or_umax(int(ndim), n, float(L), _p(s)))
+
+
+def lawson_scalar2(lam, y0, dt, nsteps):
+    return float(lib().or_lawson_scalar2(float(lam), float(y0), float(dt), int(nsteps)))
 
 
 def diag3d(uh, nbins, L=2 * np.pi):

@@ -404,6 +404,25 @@ static void lawson_rk4(int64_t nf, int ncomp, const double *E, const double *Eh,
   free(v);
 }
 
+/* Lawson integrating-factor RK2 (the exponential midpoint rule):
+ * v = Eh (u + dt/2 N(u)),  u <- E u + dt Eh N(v). */
+static void lawson_rk2(int64_t nf, int ncomp, const double *E, const double *Eh, double dt,
+                       cplx *u, int nsteps, tend_fn f, hook_fn pre, void *ctx) {
+  const int64_t tot = nf * ncomp;
+  cplx *k1 = malloc(sizeof(cplx) * tot), *k2 = malloc(sizeof(cplx) * tot);
+  cplx *v = malloc(sizeof(cplx) * tot);
+  for (int s = 0; s < nsteps; s++) {
+    if (pre) pre(u, ctx);
+    f(u, k1, ctx);
+    for (int64_t i = 0; i < tot; i++) v[i] = Eh[i % nf] * (u[i] + 0.5 * dt * k1[i]);
+    f(v, k2, ctx);
+    for (int64_t i = 0; i < tot; i++) u[i] = E[i % nf] * u[i] + dt * Eh[i % nf] * k2[i];
+  }
+  free(k1);
+  free(k2);
+  free(v);
+}
+
 /* factor exp(-nu |k|^2 t) of element i of one field; 0 outside kept set */
 static double decay(int ndim, int n, double L, double nu, double t, int64_t i) {
   const int64_t h = n / 2 + 1;
@@ -468,6 +487,91 @@ void or_step2d(int n, double L, double nu, double dt, cplx *wh, int nsteps) {
   grid_steps(2, n, L, nu, dt, wh, nsteps, &c);
 }
 
+/* Largest |u_c| over the grid points and velocity components of a kept-set
+ * state (3D velocity; 2D velocity from the vorticity). */
+static double umax_state(int ndim, int n, double L, const cplx *s) {
+  const int64_t h = n / 2 + 1, ns = ndim == 3 ? (int64_t)n * n * h : (int64_t)n * h;
+  const int64_t np = ndim == 3 ? (int64_t)n * n * n : (int64_t)n * n;
+  const double kb = 2.0 * M_PI / L;
+  cplx *g = malloc(sizeof(cplx) * ns);
+  double *phys = malloc(sizeof(double) * np);
+  double m = 0.0;
+  for (int c = 0; c < ndim; c++) {
+    for (int64_t i = 0; i < ns; i++) {
+      int mx = (int)(i % h), my, mz = 0;
+      if (ndim == 3) {
+        my = mode_full((int)((i / h) % n), n);
+        mz = mode_full((int)(i / (n * h)), n);
+      } else {
+        my = mode_full((int)(i / h), n);
+      }
+      if (!(keep1(mx, n) && keep1(my, n) && keep1(mz, n))) {
+        g[i] = 0;
+        continue;
+      }
+      if (ndim == 3) {
+        g[i] = s[c * ns + i];
+      } else {
+        const double kx = kb * mx, ky = kb * my, k2 = kx * kx + ky * ky;
+        g[i] = k2 == 0 ? 0 : (c == 0 ? I * ky * s[i] / k2 : -I * kx * s[i] / k2);
+      }
+    }
+    or_irfftn(ndim, n, g, phys);
+    for (int64_t q = 0; q < np; q++) m = fmax(m, fabs(phys[q]));
+  }
+  free(g);
+  free(phys);
+  return m;
+}
+
+/* General stepping: scheme 4 (Lawson RK4) or 2 (Lawson RK2); with cfl > 0 the
+ * step of step n is dt_n = min(dt_max, cfl (L/n) / umax(u_n)) (dt_max when
+ * the velocity vanishes), else dt_max.  *t_out (nullable) += the steps. */
+static void steps_ex(int ndim, int n, double L, double nu, double dt_max, int scheme, double cfl,
+                     cplx *u, int nsteps, struct grid_ctx *c, double *t_out) {
+  const int64_t h = n / 2 + 1, nf = ndim == 2 ? (int64_t)n * h : (int64_t)n * n * h;
+  double *E = malloc(sizeof(double) * nf), *Eh = malloc(sizeof(double) * nf);
+  double t = 0.0, last = -1.0;
+  for (int s = 0; s < nsteps; s++) {
+    double dt = dt_max;
+    if (cfl > 0) {
+      const double um = umax_state(ndim, n, L, u);
+      if (um > 0) dt = fmin(dt_max, cfl * (L / n) / um);
+    }
+    if (dt != last) {
+      for (int64_t i = 0; i < nf; i++) {
+        E[i] = decay(ndim, n, L, nu, dt, i);
+        Eh[i] = decay(ndim, n, L, nu, 0.5 * dt, i);
+      }
+      last = dt;
+    }
+    tend_fn f = ndim == 3 ? tend3 : tend2;
+    hook_fn pre = ndim == 3 ? alpha3 : NULL;
+    if (scheme == 2)
+      lawson_rk2(nf, ndim == 3 ? 3 : 1, E, Eh, dt, u, 1, f, pre, c);
+    else
+      lawson_rk4(nf, ndim == 3 ? 3 : 1, E, Eh, dt, u, 1, f, pre, c);
+    t += dt;
+  }
+  if (t_out) *t_out += t;
+  free(E);
+  free(Eh);
+}
+
+void or_step3d_ex(int n, double L, double nu, double dt_max, double power, double kf_min,
+                  double kf_max, int scheme, double cfl, cplx *uh, int nsteps, double *t_out) {
+  struct grid_ctx c = {n, L, 0.0, power, kf_min, kf_max};
+  steps_ex(3, n, L, nu, dt_max, scheme, cfl, uh, nsteps, &c, t_out);
+}
+
+void or_step2d_ex(int n, double L, double nu, double dt_max, int scheme, double cfl, cplx *wh,
+                  int nsteps, double *t_out) {
+  struct grid_ctx c = {n, L, 0.0, 0.0, 0.0, 0.0};
+  steps_ex(2, n, L, nu, dt_max, scheme, cfl, wh, nsteps, &c, t_out);
+}
+
+double or_umax(int ndim, int n, double L, const cplx *s) { return umax_state(ndim, n, L, s); }
+
 /* The same Lawson combination on the scalar ODE y' = -lam y + y^2 (linear
  * part exact, quadratic part by RK4); used only to pin the scheme. */
 static void tend_sq(const cplx *u, cplx *out, void *ctx) {
@@ -479,6 +583,13 @@ double or_lawson_scalar(double lam, double y0, double dt, int nsteps) {
   double E = exp(-lam * dt), Eh = exp(-0.5 * lam * dt);
   cplx y = y0;
   lawson_rk4(1, 1, &E, &Eh, dt, &y, nsteps, tend_sq, NULL, NULL);
+  return creal(y);
+}
+
+double or_lawson_scalar2(double lam, double y0, double dt, int nsteps) {
+  double E = exp(-lam * dt), Eh = exp(-0.5 * lam * dt);
+  cplx y = y0;
+  lawson_rk2(1, 1, &E, &Eh, dt, &y, nsteps, tend_sq, NULL, NULL);
   return creal(y);
 }
 
