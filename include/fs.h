@@ -61,6 +61,10 @@ typedef enum {
 } fs_status;
 
 enum { FS_F32 = 0, FS_F64 = 1 };
+/* time schemes (the time-stepping object of the paper advances with RK2 or
+ * RK4): Lawson integrating-factor RK4, or the Lawson midpoint rule (RK2)
+ *   v = Eh (u + dt/2 N(u)),  u <- E u + dt Eh N(v) */
+enum { FS_SCHEME_RK4 = 0, FS_SCHEME_RK2 = 1 };
 
 /* flags */
 #define FS_NO_GRAPH 0x1u /* launch kernels one by one instead of a captured graph */
@@ -77,6 +81,11 @@ typedef struct {
   double forcing_kmin;  /* forcing band kmin <= |k| <= kmax (default 2, 3) */
   double forcing_kmax;
   unsigned flags;       /* FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE */
+  int scheme;           /* FS_SCHEME_RK4 (default) or FS_SCHEME_RK2 */
+  double cfl;           /* > 0: adaptive steps, dt_n = min(dt, cfl (L/n) / umax_n) with
+                           umax_n the largest |u_c| of the physical velocity of u_n
+                           (2D: from the vorticity), measured on the GPU during the
+                           step's first stage; 0 (default): the fixed step dt */
 } fs_plan_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -93,6 +102,10 @@ void fs_plan_opts_default(fs_plan_opts *opts);
  */
 fs_status fs_plan_create(fs_plan **out, int n, double L, double nu, double dt,
                          const fs_plan_opts *opts);
+
+/* Elapsed simulated time of the plan's steps since creation and the step size
+ * of the last step (device doubles, each nullable); enqueued like the steps. */
+fs_status fs_plan_time(fs_plan *plan, double *time, double *last_dt);
 
 /* Release a plan and its workspace (waits for its stream).  NULL is a no-op. */
 fs_status fs_plan_destroy(fs_plan *plan);
@@ -166,6 +179,18 @@ fs_status fs_step_rk4(fs_plan *plan, void *state, int nsteps);
  */
 fs_status fs_energy_spectrum(fs_plan *plan, const void *state, double *spectrum, int nbins,
                              double *energy, double *enstrophy);
+
+/*
+ * 1D spectra ("spectra as functions of ... a component of the wavenumber",
+ * section "Implementation and architecture"): the energy of each velocity
+ * component binned by the modulus of one wavenumber component,
+ *   out[a][c][k] = 1/2 sum over kept modes with |m_a| = k of w |u_c_hat|^2,
+ * a, c over the d axes / components (2D: velocity from the vorticity), k = 0..K
+ * with K = floor((n-1)/3): out holds d*d*(K+1) device doubles.  Each axis
+ * sums to the component's energy.  Deterministic; uses the plan's transform
+ * workspace as scratch (no other call may run on the plan concurrently).
+ */
+fs_status fs_energy_spectra_1d(fs_plan *plan, const void *state, double *out);
 
 /*
  * Spectral energy budget of a tendency (the spectra of energy transfer the
@@ -303,6 +328,7 @@ fs_status fs_closure_features(fs_closure *c, const float *A, const float *tau, f
  * fs_tendency / fs_step_rk4 of the plan.  The LES reads the network's
  * parameters when its work runs; it borrows plan and model (both must
  * outlive it) and owns ~40 coarse fields of scratch when a model is given.
+ * With a model the plan must use fixed steps and RK4 (else FS_E_UNSUPPORTED).
  */
 typedef struct fs_les fs_les;
 fs_status fs_les_create(fs_les **out, fs_plan *coarse, fs_mlp *model, float a_scale,

@@ -159,6 +159,121 @@ __global__ void __launch_bounds__(kDiagThreads)
   }
 }
 
+// 1D spectra, pass 1.  Waves take rows of kept modes ((kz, ky) in 3D, ky in
+// 2D) in a fixed order; lanes run along kx.  Per row the wave sums each
+// velocity component's energy over kx (fixed shuffle tree) into
+// rowsum[row][c]; per lane it accumulates the energy of its kx values over the
+// rows it visits into xpart[wave][c][kx].  NC = velocity components (2 or 3).
+template <typename T, int NC>
+__global__ void __launch_bounds__(kDiagThreads)
+    k_spec1d_rows(const cx<T>* __restrict__ state, int n, int K, double kb,
+                  double* __restrict__ rowsum, double* __restrict__ xpart) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int W = gridDim.x * kWaves;
+  const int M = 2 * K + 1, H = K + 1, NH = n / 2 + 1;
+  const int rows = NC == 3 ? M * M : M;
+  const size_t cstride = (size_t)n * n * NH;
+  constexpr int kMaxChunks = 6;  // H <= 342 (n <= 1024)
+  double xacc[kMaxChunks][NC];
+#pragma unroll
+  for (int q = 0; q < kMaxChunks; q++)
+#pragma unroll
+    for (int c = 0; c < NC; c++) xacc[q][c] = 0.0;
+  for (int r = wave; r < rows; r += W) {
+    int iz = 0, iy;
+    if (NC == 3) {
+      iz = j2i_rt(r / M, K, n);
+      iy = j2i_rt(r % M, K, n);
+    } else {
+      iy = j2i_rt(r, K, n);
+    }
+    const int my = dmode(iy, n);
+    const size_t rowoff = ((size_t)iz * n + iy) * NH;
+    double rs[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) rs[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kMaxChunks; q++) {
+      const int mx = q * 64 + lane;
+      if (q * 64 >= H) break;
+      double e[NC];
+#pragma unroll
+      for (int c = 0; c < NC; c++) e[c] = 0.0;
+      if (mx < H) {
+        const double w = mx == 0 ? 1.0 : 2.0;
+        if constexpr (NC == 3) {
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            const cx<T> u = state[c * cstride + rowoff + mx];
+            e[c] = 0.5 * w * ((double)u.re * u.re + (double)u.im * u.im);
+          }
+        } else {
+          const int m2 = mx * mx + my * my;
+          if (m2 > 0) {
+            const cx<T> a = state[rowoff + mx];
+            const double kx = kb * mx, ky = kb * my, k2 = kx * kx + ky * ky;
+            const double a2 = (double)a.re * a.re + (double)a.im * a.im;
+            e[0] = 0.5 * w * a2 * ky * ky / (k2 * k2);
+            e[1] = 0.5 * w * a2 * kx * kx / (k2 * k2);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        xacc[q][c] += e[c];
+        rs[c] += e[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      double v = rs[c];
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+      if (lane == 0) rowsum[(size_t)r * NC + c] = v;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kMaxChunks; q++) {
+    const int mx = q * 64 + lane;
+    if (mx < H) {
+#pragma unroll
+      for (int c = 0; c < NC; c++) xpart[((size_t)wave * NC + c) * H + mx] = xacc[q][c];
+    }
+  }
+}
+
+// 1D spectra, pass 2: out[a][c][k] with one thread per output in a fixed
+// summation order (x: waves in order; y, z: rows with |m_a| = k in row order).
+template <int NC>
+__global__ void __launch_bounds__(kDiagThreads)
+    k_spec1d_bins(const double* __restrict__ rowsum, const double* __restrict__ xpart, int W,
+                  int n, int K, double* __restrict__ out) {
+  const int H = K + 1, M = 2 * K + 1;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= NC * NC * H) return;
+  const int k = id % H, c = (id / H) % NC, a = id / (H * NC);
+  double s = 0.0;
+  if (a == 0) {
+    for (int w = 0; w < W; w++) s += xpart[((size_t)w * NC + c) * H + k];
+  } else {
+    // compact indices j with |mode| = k: j = k and (k > 0) j = M - k
+    const int jn = k > 0 ? 2 : 1;
+    if (NC == 2) {
+      for (int q = 0; q < jn; q++) s += rowsum[(size_t)(q == 0 ? k : M - k) * NC + c];
+    } else if (a == 1) {  // ky: rows r = jz * M + jy
+      for (int jz = 0; jz < M; jz++)
+        for (int q = 0; q < jn; q++)
+          s += rowsum[((size_t)jz * M + (q == 0 ? k : M - k)) * NC + c];
+    } else {  // kz
+      for (int q = 0; q < jn; q++)
+        for (int jy = 0; jy < M; jy++)
+          s += rowsum[((size_t)(q == 0 ? k : M - k) * M + jy) * NC + c];
+    }
+  }
+  out[id] = s;
+}
+
 // flux[s] = -(transfer[0] + ... + transfer[s]), summed in shell order
 __global__ void k_flux(const double* __restrict__ transfer, int nbins, double* __restrict__ flux) {
   double c = 0.0;
@@ -200,6 +315,42 @@ __global__ void __launch_bounds__(kDiagThreads)
     __syncthreads();
   }
   if (threadIdx.x == 0) alpha[0] = (T)(red[0] > 0.0 ? power / red[0] : 0.0);
+}
+
+// Adaptive step of a step: dt = min(dt_max, cfl (L/n) / umax) (dt_max when
+// the velocity vanishes), the per-axis decay tables exp(-nu k^2 dt) and
+// exp(-nu k^2 dt/2) computed in FP64 and rounded once, the elapsed time; the
+// velocity maximum is cleared for the next step.  One block.
+template <typename T>
+__global__ void __launch_bounds__(kDiagThreads)
+    k_dtstep(unsigned long long* __restrict__ umax, int n, double L, double nu, double dt_max,
+             double cfl, T* __restrict__ dtdev, double* __restrict__ tdev, T* __restrict__ e1,
+             T* __restrict__ eh1) {
+  __shared__ double dts;
+  if (threadIdx.x == 0) {
+    const double um = __longlong_as_double((long long)*umax);
+    dts = um > 0.0 ? fmin(dt_max, cfl * (L / n) / um) : dt_max;
+  }
+  __syncthreads();
+  const double dt = dts, kb = 2.0 * M_PI / L;
+  for (int m = threadIdx.x; m < n; m += kDiagThreads) {
+    const double mm = m <= n / 2 ? m : m - n;
+    const double k2 = kb * kb * mm * mm;
+    e1[m] = (T)exp(-nu * dt * k2);
+    eh1[m] = (T)exp(-0.5 * nu * dt * k2);
+  }
+  if (threadIdx.x == 0) {
+    *dtdev = (T)dt;
+    *tdev += dt;
+    *umax = 0ull;
+  }
+}
+
+template <typename T>
+__global__ void k_time(const double* __restrict__ tdev, double t_fixed, const T* __restrict__ dtdev,
+                       double* t, double* dt) {
+  if (t) *t = t_fixed + *tdev;
+  if (dt) *dt = (double)*dtdev;
 }
 
 template <typename T>
@@ -252,6 +403,43 @@ void launch_transfer(Plan* p, const void* state, const void* tend, double* trans
   p->end(KID_DIAG);
 }
 
+// Uses the plan's first transform workspace as scratch (free between calls).
+template <typename T>
+void launch_spectra1d(Plan* p, const void* state, double* out) {
+  const int K = (p->n - 1) / 3, M = 2 * K + 1, H = K + 1;
+  const int nc = p->ndim;
+  const int rows = nc == 3 ? M * M : M;
+  int blocks = (rows + kWaves - 1) / kWaves;
+  if (blocks > 256) blocks = 256;
+  const int W = blocks * kWaves;
+  double* rowsum = (double*)p->bufA;
+  double* xpart = rowsum + (size_t)rows * nc;
+  const size_t need = ((size_t)rows * nc + (size_t)W * nc * H) * sizeof(double);
+  if (need > p->ops.elems_a * sizeof(cx<T>)) {
+    set_error("1D spectra scratch of %zu bytes exceeds the plan workspace", need);
+    p->failed = true;
+    return;
+  }
+  const double kb = 2.0 * M_PI / p->L;
+  const unsigned ob = (unsigned)((nc * nc * H + kDiagThreads - 1) / kDiagThreads);
+  p->begin(KID_DIAG);
+  if (nc == 3) {
+    hipLaunchKernelGGL((k_spec1d_rows<T, 3>), dim3(blocks), dim3(kDiagThreads), 0, p->launch,
+                       (const cx<T>*)state, p->n, K, kb, rowsum, xpart);
+    launched(p, "k_spec1d_rows");
+    hipLaunchKernelGGL((k_spec1d_bins<3>), dim3(ob), dim3(kDiagThreads), 0, p->launch,
+                       (const double*)rowsum, (const double*)xpart, W, p->n, K, out);
+  } else {
+    hipLaunchKernelGGL((k_spec1d_rows<T, 2>), dim3(blocks), dim3(kDiagThreads), 0, p->launch,
+                       (const cx<T>*)state, p->n, K, kb, rowsum, xpart);
+    launched(p, "k_spec1d_rows");
+    hipLaunchKernelGGL((k_spec1d_bins<2>), dim3(ob), dim3(kDiagThreads), 0, p->launch,
+                       (const double*)rowsum, (const double*)xpart, W, p->n, K, out);
+  }
+  launched(p, "k_spec1d_bins");
+  p->end(KID_DIAG);
+}
+
 template <typename T>
 void launch_alpha(Plan* p, const void* state) {
   p->begin(KID_ALPHA);
@@ -259,6 +447,25 @@ void launch_alpha(Plan* p, const void* state) {
                      p->n, p->bw, p->m2min, p->m2max, p->fpow, (T*)p->alpha);
   launched(p, "k_alpha");
   p->end(KID_ALPHA);
+}
+
+template <typename T>
+void launch_dtstep(Plan* p) {
+  p->begin(KID_ALPHA);
+  hipLaunchKernelGGL((k_dtstep<T>), dim3(1), dim3(kDiagThreads), 0, p->launch, p->umaxdev, p->n,
+                     p->L, p->nu, p->dt, p->cfl, (T*)p->dtdev, p->tdev, (T*)p->e1, (T*)p->eh1);
+  launched(p, "k_dtstep");
+  p->end(KID_ALPHA);
+}
+
+void launch_time(Plan* p, double* t, double* dt) {
+  if (p->prec == FS_F32)
+    hipLaunchKernelGGL((k_time<float>), dim3(1), dim3(1), 0, p->launch, (const double*)p->tdev,
+                       p->t_fixed, (const float*)p->dtdev, t, dt);
+  else
+    hipLaunchKernelGGL((k_time<double>), dim3(1), dim3(1), 0, p->launch, (const double*)p->tdev,
+                       p->t_fixed, (const double*)p->dtdev, t, dt);
+  launched(p, "k_time");
 }
 
 template <typename T>
@@ -279,8 +486,12 @@ template void launch_transfer<float>(Plan*, const void*, const void*, double*, d
                                      double*, double*);
 template void launch_transfer<double>(Plan*, const void*, const void*, double*, double*, int,
                                       double*, double*);
+template void launch_spectra1d<float>(Plan*, const void*, double*);
+template void launch_spectra1d<double>(Plan*, const void*, double*);
 template void launch_alpha<float>(Plan*, const void*);
 template void launch_alpha<double>(Plan*, const void*);
+template void launch_dtstep<float>(Plan*);
+template void launch_dtstep<double>(Plan*);
 template void launch_fill<float>(Plan*, void*, size_t);
 template void launch_fill<double>(Plan*, void*, size_t);
 

@@ -124,7 +124,7 @@ void launch_x(const Ensemble* e, const EnsClass& c, hipStream_t s) {
   Batch bt{nullptr, c.w1s, c.w2s, 0, bpr};
   hipLaunchKernelGGL((k2_x<float, N, RP>), dim3(bpr * c.nruns), dim3(RP * N / 8), 0, s,
                      (const cx<float>*)c.w1, (cx<float>*)c.w2, (const cx<float>*)c.tw,
-                     (float)(1.0 / ((double)N * N)), bt);
+                     (float)(1.0 / ((double)N * N)), bt, (unsigned long long*)nullptr);
 }
 
 template <int N>

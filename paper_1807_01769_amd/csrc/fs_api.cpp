@@ -11,8 +11,8 @@
 #include <vector>
 
 #include "fs.h"
-#include "fft_core.h"
 #include "fs_internal.h"
+#include "ns_common.h"
 
 namespace fs {
 
@@ -105,7 +105,13 @@ void release(Plan* p) {
 // One RK4 step (forcing coefficient, four stages) on p->launch.
 void enqueue_step(Plan* p, void* state, int do_p1) {
   if (p->ops.alpha && p->m2max >= 0) p->ops.alpha(p, state);
-  for (int mode = 1; mode <= 4; mode++) p->ops.stage(p, state, mode, mode == 4 ? do_p1 : 1);
+  if (p->scheme == FS_SCHEME_RK2) {
+    p->ops.stage(p, state, fs::kRk2a, 1);
+    p->ops.stage(p, state, fs::kRk2b, do_p1);
+  } else {
+    for (int mode = fs::kStage1; mode <= fs::kStage4; mode++)
+      p->ops.stage(p, state, mode, mode == fs::kStage4 ? do_p1 : 1);
+  }
 }
 
 bool capture(Plan* p, void* state, int do_p1, hipGraphExec_t* out) {
@@ -142,6 +148,8 @@ void fs_plan_opts_default(fs_plan_opts* o) {
   o->forcing_kmin = 2.0;
   o->forcing_kmax = 3.0;
   o->flags = 0;
+  o->scheme = FS_SCHEME_RK4;
+  o->cfl = 0.0;
 }
 
 fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
@@ -163,6 +171,9 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE)) return fail(FS_E_INVALID, "unknown flags");
   if (!(isfin(o.forcing_power) && o.forcing_power >= 0))
     return fail(FS_E_INVALID, "forcing_power must be finite and >= 0");
+  if (o.scheme != FS_SCHEME_RK4 && o.scheme != FS_SCHEME_RK2)
+    return fail(FS_E_INVALID, "scheme = %d must be FS_SCHEME_RK4 or FS_SCHEME_RK2", o.scheme);
+  if (!(isfin(o.cfl) && o.cfl >= 0)) return fail(FS_E_INVALID, "cfl must be finite and >= 0");
   const double kb = 2.0 * M_PI / L;
   const int K = K_of(n);
   int bw = 0, m2min = 0, m2max = -1;
@@ -205,6 +216,8 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   p->m2min = m2min;
   p->m2max = m2max;
   p->flags = o.flags;
+  p->scheme = o.scheme;
+  p->cfl = o.cfl;
   p->stream = (hipStream_t)o.stream;
   p->launch = p->stream;
   if (o.ndim == 3)
@@ -222,18 +235,20 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   const size_t rs = o.precision == FS_F32 ? 4 : 8, cs = 2 * rs;
   const int band_elems = 3 * (2 * bw + 1) * (2 * bw + 1) * (bw + 1);
   const size_t dpart = (size_t)fs::kDiagMaxBlocks * (fs::kDiagMaxBins + 2) * sizeof(double);
-  size_t off[9];
-  size_t sz[9] = {cs * n,
-                  rs * n,
-                  rs * n,
-                  cs * p->ops.elems_a,
-                  cs * p->ops.elems_b,
-                  cs * p->ops.elems_acc,
-                  cs * (size_t)(band_elems > 0 ? band_elems : 1),
-                  rs * 2,
-                  dpart};
+  constexpr int kPieces = 10;
+  size_t off[kPieces];
+  size_t sz[kPieces] = {cs * n,
+                        rs * n,
+                        rs * n,
+                        cs * p->ops.elems_a,
+                        cs * p->ops.elems_b,
+                        cs * p->ops.elems_acc,
+                        cs * (size_t)(band_elems > 0 ? band_elems : 1),
+                        rs * 2,
+                        dpart,
+                        64};  // step, elapsed time, velocity maximum
   size_t total = 0;
-  for (int i = 0; i < 9; i++) {
+  for (int i = 0; i < kPieces; i++) {
     off[i] = total;
     total += align256(sz[i]);
   }
@@ -253,8 +268,12 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   p->vband = b + off[6];
   p->alpha = b + off[7];
   p->dpart = (double*)(b + off[8]);
+  p->tdev = (double*)(b + off[9]);
+  p->umaxdev = (unsigned long long*)(b + off[9] + 8);
+  p->dtdev = b + off[9] + 16;
   p->dpart_blocks = fs::kDiagMaxBlocks;
 
+  const float dt32 = (float)dt;
   // FP64 tables, rounded once
   std::vector<char> host(sz[0] + sz[1] + sz[2]);
   for (int m = 0; m < n; m++) {
@@ -284,6 +303,9 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
                   "copy tables") &&
             p->ok(hipMemset(p->vband, 0, sz[6]), "clear band") &&
             p->ok(hipMemset(p->alpha, 0, sz[7]), "clear alpha") &&
+            p->ok(hipMemset(b + off[9], 0, sz[9]), "clear step scalars") &&
+            (rs == 4 ? p->ok(hipMemcpy(p->dtdev, &dt32, 4, hipMemcpyHostToDevice), "dt")
+                     : p->ok(hipMemcpy(p->dtdev, &dt, 8, hipMemcpyHostToDevice), "dt")) &&
             p->ok(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking), "capture stream");
   if (!ok) {
     std::string msg = fs::g_err;
@@ -378,7 +400,14 @@ fs_status fs_step_rk4(fs_plan* plan, void* state, int nsteps) {
   } else {
     for (int s = 0; s < nsteps; s++) enqueue_step(p, state, s + 1 < nsteps);
   }
+  if (p->cfl <= 0) p->t_fixed += nsteps * p->dt;
   return device_status(p);
+}
+
+fs_status fs_plan_time(fs_plan* plan, double* time, double* last_dt) {
+  if (fs_status s = usable(plan)) return s;
+  fs::launch_time(&plan->p, time, last_dt);
+  return device_status(&plan->p);
 }
 
 fs_status fs_energy_spectrum(fs_plan* plan, const void* state, double* spectrum, int nbins,
@@ -388,6 +417,13 @@ fs_status fs_energy_spectrum(fs_plan* plan, const void* state, double* spectrum,
   if (nbins < 1 || nbins > fs::kDiagMaxBins)
     return fail(FS_E_INVALID, "nbins = %d must be in 1..%d", nbins, fs::kDiagMaxBins);
   plan->p.ops.diag(&plan->p, state, spectrum, nbins, energy, enstrophy);
+  return device_status(&plan->p);
+}
+
+fs_status fs_energy_spectra_1d(fs_plan* plan, const void* state, double* out) {
+  if (fs_status s = usable(plan)) return s;
+  if (!state || !out) return fail(FS_E_INVALID, "NULL array");
+  plan->p.ops.spectra1d(&plan->p, state, out);
   return device_status(&plan->p);
 }
 

@@ -45,9 +45,14 @@ struct Ops {
   void (*fft_inv_n)(Plan*, const void* spec, void* phys, int nf, void* wa, void* wb);
   // forcing coefficient from the state (3D only; may be null)
   void (*alpha)(Plan*, const void* state);
+  // adaptive step: dt from the velocity maximum of the step, decay tables,
+  // elapsed time
+  void (*dtstep)(Plan*);
   // diagnostics
   void (*diag)(Plan*, const void* state, double* spectrum, int nbins, double* energy,
                double* enstrophy);
+  // 1D spectra of the velocity components
+  void (*spectra1d)(Plan*, const void* state, double* out);
   // spectral energy transfer of a tendency
   void (*transfer)(Plan*, const void* state, const void* tend, double* transfer, double* flux,
                    int nbins, double* energy_rate, double* enstrophy_rate);
@@ -62,6 +67,9 @@ struct Plan {
   double fpow = 0, fkmin = 2, fkmax = 3;
   int bw = 0, m2min = 0, m2max = -1;  // forcing band in integer |m|^2
   unsigned flags = 0;
+  int scheme = FS_SCHEME_RK4;
+  double cfl = 0;           // > 0: dt_n = min(dt, cfl (L/n) / max|u_c|) every step
+  double t_fixed = 0;       // elapsed time of fixed-dt steps (host)
   int device = 0;
   hipStream_t stream = nullptr;  // caller's stream
   hipStream_t launch = nullptr;  // stream kernels go to right now
@@ -73,6 +81,9 @@ struct Plan {
   void *tw = nullptr, *e1 = nullptr, *eh1 = nullptr;
   void *bufA = nullptr, *bufB = nullptr, *acc = nullptr, *vband = nullptr, *alpha = nullptr;
   double* dpart = nullptr;  // diagnostics partial sums
+  void* dtdev = nullptr;    // step of the current step (working precision)
+  double* tdev = nullptr;   // elapsed time of adaptive steps
+  unsigned long long* umaxdev = nullptr;  // velocity maximum of the step (double bits)
   int dpart_blocks = 0;
   // captured step graphs for one state pointer
   hipGraphExec_t gmid = nullptr, glast = nullptr;
@@ -109,10 +120,15 @@ template <typename T>
 void launch_diag(Plan* p, const void* state, double* spectrum, int nbins, double* energy,
                  double* enstrophy);
 template <typename T>
+void launch_spectra1d(Plan* p, const void* state, double* out);
+template <typename T>
 void launch_transfer(Plan* p, const void* state, const void* tend, double* transfer,
                      double* flux, int nbins, double* energy_rate, double* enstrophy_rate);
 template <typename T>
 void launch_alpha(Plan* p, const void* state);
+template <typename T>
+void launch_dtstep(Plan* p);
+void launch_time(Plan* p, double* t, double* dt);
 template <typename T>
 void launch_fill(Plan* p, void* ptr, size_t n_complex);
 

@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(LB * N / 8)
 template <typename T, int N, int RP>
 __global__ void __launch_bounds__(RP * N / 8)
     k2_x(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
-         T scale, Batch bt) {
+         T scale, Batch bt, unsigned long long* __restrict__ umax) {
   using G = Geo<N, false>;
   using R = RowPairs<N>;
   constexpr int P = G::P;
@@ -120,6 +120,14 @@ __global__ void __launch_bounds__(RP * N / 8)
                                        [&](int m) { return at(2, y0 + 1, m); });
   }
   fft_lines<T, N, +1, 3>(v, t, my_lds, lidx, twr);
+  if (umax) {
+    double um = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; e++)
+      um = fmax(um, (double)fmax(fmax(fabs(v[0][e].re), fabs(v[0][e].im)),
+                                 fmax(fabs(v[1][e].re), fabs(v[1][e].im))));
+    umax_wave(umax, um);
+  }
   cx<T> q[2][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
@@ -145,7 +153,7 @@ __global__ void __launch_bounds__(RP * N / 8)
   }
 }
 
-// Y pass: forward y transforms of (u w, v w), tendency, RK4 combine and the
+// Y pass: forward y transforms of (u w, v w), tendency, Lawson combine and the
 // next stage's inverse transforms.  acc: [XT][M][16] per run.
 // Grid: runs * bpr, bpr = 16 XT / LB.
 template <typename T, int N, int LB, int MODE>
@@ -175,6 +183,7 @@ __global__ void __launch_bounds__(LB * N / 8)
   fft_lines<T, N, -1, 1>(f2, t, lds, lidx, twr);
 
   const T kx = a.kb * (T)mx;
+  const T dt = stage_dt(a);
   cx<T> w[8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
@@ -196,13 +205,11 @@ __global__ void __launch_bounds__(LB * N / 8)
       const T Eh = a.eh1[mx] * a.eh1[iy];
       const size_t ao = run * bt.acc_stride + ((size_t)(mx >> 4) * G::M + jy) * kTile + (mx & 15);
       cx<T> acc = {0, 0}, u = {0, 0};
-      if constexpr (MODE != kStage4) u = a.state[so];
-      if constexpr (MODE != kStage1) acc = a.acc[ao];
-      const cx<T> nxt = rk4_combine<MODE>(u, acc, nl, E, Eh, a.dt);
-      if constexpr (MODE == kStage4)
-        a.state[so] = nxt;
-      else
-        a.acc[ao] = acc;
+      if constexpr (mode_reads_state(MODE)) u = a.state[so];
+      if constexpr (mode_reads_acc(MODE)) acc = a.acc[ao];
+      const cx<T> nxt = rk4_combine<MODE>(u, acc, nl, E, Eh, dt);
+      if constexpr (mode_writes_state(MODE)) a.state[so] = nxt;
+      if constexpr (mode_writes_acc(MODE)) a.acc[ao] = acc;
       w[e] = nxt;
     }
   }

@@ -25,14 +25,15 @@ namespace fs {
 // transform (px + i py) of each row and (pz(y0) + i pz(y1)), store kept kx.
 // One transform line is in flight at a time and the cross product is built
 // as its factors arrive (u kept, partial products accumulated), so a row
-// pair needs one LDS line and about 100 VGPRs.
+// pair needs one LDS line and about 100 VGPRs.  With umax, the largest
+// |u_c| of the physical velocity is max-reduced into *umax.
 // in : Wn[6][N][XT][N][16]   out: Wn[3][N][XT][N][16]
 // Grid: (N/2/RP, N).
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 __global__ void __launch_bounds__((RowPairs<N>::THREADS))
     k3_x(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
-         T scale) {
+         T scale, unsigned long long* __restrict__ umax) {
   using G = Geo<N, false>;
   using R = RowPairs<N>;
   constexpr int P = G::P;
@@ -122,6 +123,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   // factors arrive; (px + i py) is transformed at once, pz of the first row
   // waits to be paired with pz of the second.
   T pz0[8];
+  double um = 0.0;  // largest |u_c| seen (only when umax is requested)
 #pragma unroll
   for (int r = 0; r < 2; r++) {
     T ux[8], uy[8], uz[8], qy[8], qz[8];
@@ -136,6 +138,8 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       uz[e] = v[0][e].re;
+      if (umax)
+        um = fmax(um, (double)fmax(fmax(fabs(ux[e]), fabs(uy[e])), fabs(uz[e])));
       const T wx = v[0][e].im;
       qy[e] = uz[e] * wx;   // py = uz wx - ux wz
       qz[e] = -uy[e] * wx;  // pz = ux wy - uy wx
@@ -156,6 +160,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
       forward_store(v, 2, y0, 2, y0 + 1);
     }
   }
+  if (umax) umax_wave(umax, um);
 }
 
 // The fused z passes keep three components plus a transform line in registers
@@ -347,6 +352,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
   const size_t acstride = (size_t)G::XT * G::M * G::M * kTile;
   const int bn = (2 * a.bw + 1) * (2 * a.bw + 1) * (a.bw + 1);
   const T alpha = a.m2max >= 0 ? a.alpha[0] : (T)0;
+  const T dt = stage_dt(a);
   const T kx = a.kb * (T)mx, ky = a.kb * (T)my;
   const int m2xy = band_column(a, mx, my);
 #pragma unroll
@@ -390,14 +396,11 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
       for (int c = 0; c < 3; c++) {
         cx<T> acc = {0, 0};
         cx<T> u = {0, 0};
-        if constexpr (MODE != kStage4) u = a.state[c * cstride + so];
-        if constexpr (MODE != kStage1) acc = a.acc[c * acstride + ao];
-        const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, a.dt);
-        if constexpr (MODE == kStage4) {
-          a.state[c * cstride + so] = nxt;
-        } else {
-          a.acc[c * acstride + ao] = acc;
-        }
+        if constexpr (mode_reads_state(MODE)) u = a.state[c * cstride + so];
+        if constexpr (mode_reads_acc(MODE)) acc = a.acc[c * acstride + ao];
+        const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, dt);
+        if constexpr (mode_writes_state(MODE)) a.state[c * cstride + so] = nxt;
+        if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc;
         v[c][e] = nxt;
       }
       if (band && do_p1) {

@@ -95,20 +95,48 @@ struct StageArgs {
   const T* eh1;        // exp(-nu dt k^2 / 2) per FFT index
   const cx<T>* tw;     // twiddle table of the transform size
   T kb;                // 2 pi / L
-  T dt;
+  T dt;                // step (used when dtp is null)
+  const T* dtp;        // device step of the current step (adaptive steps), or null
   int bw;              // half width of the forcing-band cube (modes)
   int m2min, m2max;    // band: m2min <= |m|^2 <= m2max; m2max < 0 => off
 };
 
-enum StageMode : int { kModeTend = 0, kStage1 = 1, kStage2 = 2, kStage3 = 3, kStage4 = 4 };
+template <typename T>
+__device__ __forceinline__ T stage_dt(const StageArgs<T>& a) {
+  return a.dtp ? *a.dtp : a.dt;
+}
 
-// Lawson IF-RK4 stage combination at one mode.  `u` is u_n, `a` the
+// kStage1..4: the four stages of Lawson RK4; kRk2a, kRk2b: the two of the
+// Lawson midpoint rule (RK2); kModeTend: tendency only.
+enum StageMode : int {
+  kModeTend = 0,
+  kStage1 = 1,
+  kStage2 = 2,
+  kStage3 = 3,
+  kStage4 = 4,
+  kRk2a = 5,
+  kRk2b = 6
+};
+// what a stage epilogue touches besides the tendency
+__host__ __device__ constexpr bool mode_reads_state(int m) {
+  return m != kModeTend && m != kStage4;
+}
+__host__ __device__ constexpr bool mode_reads_acc(int m) {
+  return m == kStage2 || m == kStage3 || m == kStage4;
+}
+__host__ __device__ constexpr bool mode_writes_acc(int m) {
+  return m == kStage1 || m == kStage2 || m == kStage3;
+}
+__host__ __device__ constexpr bool mode_writes_state(int m) { return m == kStage4 || m == kRk2b; }
+
+// Lawson stage combination at one mode.  `u` is u_n, `a` the RK4
 // accumulator, `nl` the tendency of this stage; returns the next stage input
-// (stage 4: u_{n+1}).  E = exp(-nu k^2 dt), Eh = exp(-nu k^2 dt/2).
-//   stage1: a = E u + dt/6 E k1          next = Eh (u + dt/2 k1)
-//   stage2: a += dt/3 Eh k2              next = Eh u + dt/2 k2
-//   stage3: a += dt/3 Eh k3              next = E u + dt Eh k3
-//   stage4: u_{n+1} = a + dt/6 k4
+// (last stage: u_{n+1}).  E = exp(-nu k^2 dt), Eh = exp(-nu k^2 dt/2).
+//   RK4 stage1: a = E u + dt/6 E k1          next = Eh (u + dt/2 k1)
+//       stage2: a += dt/3 Eh k2              next = Eh u + dt/2 k2
+//       stage3: a += dt/3 Eh k3              next = E u + dt Eh k3
+//       stage4: u_{n+1} = a + dt/6 k4
+//   RK2 stage a: next = Eh (u + dt/2 k1);  stage b: u_{n+1} = E u + dt Eh k2
 template <int MODE, typename T>
 __device__ __forceinline__ cx<T> rk4_combine(cx<T> u, cx<T>& a, cx<T> nl, T E, T Eh, T dt) {
   const T d2 = dt * (T)0.5, d3 = dt / (T)3, d6 = dt / (T)6;
@@ -121,9 +149,21 @@ __device__ __forceinline__ cx<T> rk4_combine(cx<T> u, cx<T>& a, cx<T> nl, T E, T
   } else if constexpr (MODE == kStage3) {
     a = a + cscale(nl, d3 * Eh);
     return cscale(u, E) + cscale(nl, dt * Eh);
-  } else {
+  } else if constexpr (MODE == kStage4) {
     return a + cscale(nl, d6);
+  } else if constexpr (MODE == kRk2a) {
+    return cscale(u + cscale(nl, d2), Eh);
+  } else {
+    return cscale(u, E) + cscale(nl, dt * Eh);
   }
+}
+
+// Largest |value| of a velocity sample into a device maximum (non-negative
+// doubles order like their bit patterns): wave maximum, then one atomic.
+__device__ __forceinline__ void umax_wave(unsigned long long* umax, double m) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmax(m, __shfl_xor(m, d, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(umax, (unsigned long long)__double_as_longlong(m));
 }
 
 // ---------------------------------------------------------------------------

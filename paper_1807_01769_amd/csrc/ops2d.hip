@@ -21,6 +21,7 @@ StageArgs<T> stage_args2(Plan* p, void* state, void* tend) {
   a.tw = (const cx<T>*)p->tw;
   a.kb = (T)(2.0 * M_PI / p->L);
   a.dt = (T)p->dt;
+  a.dtp = (const T*)p->dtdev;
   a.bw = 0;
   a.m2min = 0;
   a.m2max = -1;
@@ -47,10 +48,11 @@ struct L2 {
     launched(p, "k2_p1");
     p->end(KID_P1);
   }
-  static void x(Plan* p) {
+  static void x(Plan* p, bool umax = false) {
     p->begin(KID_X);
     hipLaunchKernelGGL((k2_x<T, N, RP>), dim3(N / 2 / RP), dim3(RP * N / 8), 0, p->launch,
-                       (const cx<T>*)A(p), B(p), TW(p), (T)(1.0 / ((double)N * N)), one(N / 2 / RP));
+                       (const cx<T>*)A(p), B(p), TW(p), (T)(1.0 / ((double)N * N)), one(N / 2 / RP),
+                       umax ? p->umaxdev : nullptr);
     launched(p, "k2_x");
     p->end(KID_X);
   }
@@ -64,11 +66,15 @@ struct L2 {
     p->end(KID_Z);
   }
   static void stage(Plan* p, void* state, int mode, int do_p1) {
-    x(p);
+    const bool adapt = p->cfl > 0 && (mode == kStage1 || mode == kRk2a);
+    x(p, adapt);
+    if (adapt) launch_dtstep<T>(p);
     switch (mode) {
-      case 1: yk<kStage1>(p, state, nullptr, 1); break;
-      case 2: yk<kStage2>(p, state, nullptr, 1); break;
-      case 3: yk<kStage3>(p, state, nullptr, 1); break;
+      case kStage1: yk<kStage1>(p, state, nullptr, 1); break;
+      case kStage2: yk<kStage2>(p, state, nullptr, 1); break;
+      case kStage3: yk<kStage3>(p, state, nullptr, 1); break;
+      case kRk2a: yk<kRk2a>(p, state, nullptr, 1); break;
+      case kRk2b: yk<kRk2b>(p, state, nullptr, do_p1); break;
       default: yk<kStage4>(p, state, nullptr, do_p1); break;
     }
   }
@@ -111,7 +117,9 @@ struct L2 {
     o.fft_inv = fft_inv;
     o.alpha = nullptr;
     o.diag = launch_diag<T>;
+    o.dtstep = launch_dtstep<T>;
     o.transfer = launch_transfer<T>;
+    o.spectra1d = launch_spectra1d<T>;
     const size_t wn3 = (size_t)3 * G::XT * N * kTile;
     const size_t wn2 = (size_t)2 * G::XT * N * kTile;
     const size_t wfull = (size_t)GF::XT * N * kTile;

@@ -20,6 +20,7 @@ StageArgs<T> stage_args(Plan* p, void* state, void* tend) {
   a.tw = (const cx<T>*)p->tw;
   a.kb = (T)(2.0 * M_PI / p->L);
   a.dt = (T)p->dt;
+  a.dtp = (const T*)p->dtdev;
   a.bw = p->bw;
   a.m2min = p->m2min;
   a.m2max = p->m2max;
@@ -53,10 +54,11 @@ struct L3 {
     launched(p, "k_y_inv");
     p->end(KID_YINV);
   }
-  static void x(Plan* p) {
+  static void x(Plan* p, bool umax = false) {
     p->begin(KID_X);
     hipLaunchKernelGGL((k3_x<T, N>), dim3(N / 2 / R::RP, N), dim3(R::THREADS), 0, p->launch,
-                       (const cx<T>*)B(p), A(p), TW(p), (T)(1.0 / ((double)N * N * N)));
+                       (const cx<T>*)B(p), A(p), TW(p), (T)(1.0 / ((double)N * N * N)),
+                       umax ? p->umaxdev : nullptr);
     launched(p, "k3_x");
     p->end(KID_X);
   }
@@ -77,13 +79,17 @@ struct L3 {
     p->end(KID_Z);
   }
   static void stage(Plan* p, void* state, int mode, int do_p1) {
+    const bool adapt = p->cfl > 0 && (mode == kStage1 || mode == kRk2a);
     yinv(p);
-    x(p);
+    x(p, adapt);
+    if (adapt) launch_dtstep<T>(p);
     yfwd(p);
     switch (mode) {
-      case 1: zk<kStage1>(p, state, nullptr, 1); break;
-      case 2: zk<kStage2>(p, state, nullptr, 1); break;
-      case 3: zk<kStage3>(p, state, nullptr, 1); break;
+      case kStage1: zk<kStage1>(p, state, nullptr, 1); break;
+      case kStage2: zk<kStage2>(p, state, nullptr, 1); break;
+      case kStage3: zk<kStage3>(p, state, nullptr, 1); break;
+      case kRk2a: zk<kRk2a>(p, state, nullptr, 1); break;
+      case kRk2b: zk<kRk2b>(p, state, nullptr, do_p1); break;
       default: zk<kStage4>(p, state, nullptr, do_p1); break;
     }
   }
@@ -150,8 +156,10 @@ struct L3 {
     o.fft_fwd_n = fft_fwd_n;
     o.fft_inv_n = fft_inv_n;
     o.alpha = launch_alpha<T>;
+    o.dtstep = launch_dtstep<T>;
     o.diag = launch_diag<T>;
     o.transfer = launch_transfer<T>;
+    o.spectra1d = launch_spectra1d<T>;
     const size_t wm6 = (size_t)6 * N * G::XT * G::M * kTile;
     const size_t wn6 = (size_t)6 * N * G::XT * N * kTile;
     const size_t wfull = (size_t)N * GF::XT * N * kTile;

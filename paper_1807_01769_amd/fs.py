@@ -21,6 +21,7 @@ lib = C.CDLL(LIB_PATH)
 
 FS_OK, FS_E_INVALID, FS_E_UNSUPPORTED, FS_E_NOMEM, FS_E_DEVICE, FS_E_NONFINITE = 0, -1, -2, -3, -4, -5
 FS_F32, FS_F64 = 0, 1
+FS_SCHEME_RK4, FS_SCHEME_RK2 = 0, 1
 FS_NO_GRAPH, FS_PROFILE = 0x1, 0x2
 KERNEL_NAMES = ["p1", "y_inverse", "x_c2r_product_r2c", "y_forward", "z_stage",
                 "forcing_alpha", "fill", "fft_only", "diagnostics"]
@@ -35,6 +36,8 @@ class Opts(C.Structure):
         ("forcing_kmin", C.c_double),
         ("forcing_kmax", C.c_double),
         ("flags", C.c_uint),
+        ("scheme", C.c_int),
+        ("cfl", C.c_double),
     ]
 
 
@@ -53,6 +56,8 @@ lib.fs_tendency.argtypes = [_vp, _vp, _vp]
 lib.fs_step_rk4.argtypes = [_vp, _vp, _i]
 lib.fs_energy_spectrum.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
 lib.fs_energy_transfer.argtypes = [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp]
+lib.fs_energy_spectra_1d.argtypes = [_vp, _vp, _vp]
+lib.fs_plan_time.argtypes = [_vp, _vp, _vp]
 lib.fs_profile_read.argtypes = [_vp, C.POINTER(_d), C.POINTER(C.c_long), C.POINTER(C.c_char_p), _i]
 lib.fs_status_str.argtypes = [_i]
 lib.fs_status_str.restype = C.c_char_p
@@ -61,7 +66,7 @@ lib.fs_last_error.restype = C.c_char_p
 for _f in ("fs_plan_create", "fs_plan_destroy", "fs_plan_set_stream", "fs_state_elems",
            "fs_workspace_bytes", "fs_spectrum_bins", "fs_fft_forward", "fs_fft_inverse",
            "fs_tendency", "fs_step_rk4", "fs_energy_spectrum", "fs_energy_transfer",
-           "fs_profile_read"):
+           "fs_energy_spectra_1d", "fs_plan_time", "fs_profile_read"):
     getattr(lib, _f).restype = _i
 
 
@@ -89,7 +94,7 @@ class Plan:
     def __init__(self, n: int, L: float = 2 * math.pi, nu: float = 0.0, dt: float = 1e-3,
                  ndim: int = 3, precision: str = "f32", stream=None, forcing_power: float = 0.0,
                  forcing_kmin: float = 2.0, forcing_kmax: float = 3.0, graphs: bool = True,
-                 profile: bool = False):
+                 profile: bool = False, scheme: str = "rk4", cfl: float = 0.0):
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1807_01769_amd.fs needs a HIP device")
         self.n, self.L, self.nu, self.dt, self.ndim = int(n), float(L), float(nu), float(dt), int(ndim)
@@ -106,6 +111,8 @@ class Plan:
         o.forcing_kmin = float(forcing_kmin)
         o.forcing_kmax = float(forcing_kmax)
         o.flags = (0 if graphs else FS_NO_GRAPH) | (FS_PROFILE if profile else 0)
+        o.scheme = {"rk4": FS_SCHEME_RK4, "rk2": FS_SCHEME_RK2}[scheme]
+        o.cfl = float(cfl)
         h = _vp()
         _check(lib.fs_plan_create(C.byref(h), self.n, self.L, self.nu, self.dt, C.byref(o)),
                "fs_plan_create")
@@ -189,6 +196,21 @@ class Plan:
                                       spec.data_ptr(), nbins, ez.data_ptr(), ez.data_ptr() + 8),
                "fs_energy_spectrum")
         return spec, ez[0:1], ez[1:2]
+
+    def time(self):
+        """Device float64 tensors (elapsed time, last step size)."""
+        out = torch.empty(2, dtype=torch.float64, device="cuda")
+        _check(lib.fs_plan_time(self._h, out.data_ptr(), out.data_ptr() + 8), "fs_plan_time")
+        return out[0:1], out[1:2]
+
+    def energy_spectra_1d(self, state: torch.Tensor) -> torch.Tensor:
+        """Device float64 [axis][component][k = 0..K] energies binned by |m_axis|."""
+        d, K = self.ndim, (self.n - 1) // 3
+        out = torch.empty((d, d, K + 1), dtype=torch.float64, device=state.device)
+        _check(lib.fs_energy_spectra_1d(
+            self._h, self._arg(state, self.state_shape, self.complex_dtype, "state"),
+            out.data_ptr()), "fs_energy_spectra_1d")
+        return out
 
     def energy_transfer(self, state: torch.Tensor, tend: torch.Tensor | None = None,
                         nbins: int | None = None):

@@ -35,7 +35,8 @@ def test_exports_every_declared_symbol(lib):
 class Opts(C.Structure):
     _fields_ = [("ndim", C.c_int), ("precision", C.c_int), ("stream", C.c_void_p),
                 ("forcing_power", C.c_double), ("forcing_kmin", C.c_double),
-                ("forcing_kmax", C.c_double), ("flags", C.c_uint)]
+                ("forcing_kmax", C.c_double), ("flags", C.c_uint), ("scheme", C.c_int),
+                ("cfl", C.c_double)]
 
 
 def _create(lib, n, L, nu, dt, **kw):
@@ -70,6 +71,10 @@ def _create(lib, n, L, nu, dt, **kw):
     ((64, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 3.0, "forcing_kmax": 2.0}, -1),
     ((16, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 2.0, "forcing_kmax": 9.0}, -1),
     ((64, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 1.1, "forcing_kmax": 1.2}, -1),
+    ((64, 6.28, 0.1, 0.01), {"scheme": 2}, -1),
+    ((64, 6.28, 0.1, 0.01), {"scheme": -1}, -1),
+    ((64, 6.28, 0.1, 0.01), {"cfl": -0.5}, -1),
+    ((64, 6.28, 0.1, 0.01), {"cfl": float("nan")}, -1),
 ])
 def test_create_validates_before_device(lib, args, kw, expect):
     st, h = _create(lib, *args, **kw)
@@ -84,7 +89,7 @@ def test_null_arguments(lib):
     assert lib.fs_plan_create(None, 64, 6.28, 0.1, 0.01, None) == -1
     for fn, nargs in [("fs_step_rk4", 3), ("fs_tendency", 3), ("fs_fft_forward", 3),
                       ("fs_fft_inverse", 3), ("fs_energy_spectrum", 6), ("fs_plan_set_stream", 2),
-                      ("fs_energy_transfer", 8),
+                      ("fs_energy_transfer", 8), ("fs_energy_spectra_1d", 3), ("fs_plan_time", 3),
                       ("fs_profile_read", 5)]:
         f = getattr(lib, fn)
         f.argtypes = [C.c_void_p] * nargs
@@ -155,3 +160,12 @@ def test_closure_and_les_null_arguments(lib):
         fn = getattr(lib, name)
         fn.argtypes = [vp]
         assert fn(None) == 0, name
+
+
+def test_opts_defaults(lib):
+    lib.fs_plan_opts_default.argtypes = [C.POINTER(Opts)]
+    o = Opts()
+    o.scheme, o.cfl = 7, 3.0
+    lib.fs_plan_opts_default(C.byref(o))
+    assert (o.ndim, o.precision, o.flags, o.scheme, o.cfl) == (3, 0, 0, 0, 0.0)
+    assert (o.forcing_power, o.forcing_kmin, o.forcing_kmax) == (0.0, 2.0, 3.0)

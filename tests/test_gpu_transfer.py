@@ -1,4 +1,5 @@
-"""GPU parity of the spectral energy budget (fs_energy_transfer) against the
+"""GPU parity of the spectral energy budget (fs_energy_transfer) and the 1D
+spectra (fs_energy_spectra_1d) against the
 FP64 oracle: the reduction alone on identical inputs (FP64 accumulation of
 the same values: 1e-12), and the whole chain state -> GPU tendency ->
 transfer (the tendency's FP32 tolerance, 1e-5 of the largest shell)."""
@@ -62,4 +63,25 @@ def test_transfer2d_fp64(fs, oracle_mod):
     T = T.cpu().numpy()
     assert np.abs(T - oT).max() <= 1e-11 * np.abs(oT).max()
     assert abs(float(zr.item()) - oz) <= 1e-11 * np.abs(oT).max() * nbins
+    plan.close()
+
+
+@pytest.mark.parametrize("ndim,n,prec", [(3, 32, "f32"), (3, 64, "f64"), (2, 64, "f64"),
+                                         (2, 128, "f32")])
+def test_spectra_1d(fs, oracle_mod, ndim, n, prec):
+    """1D spectra: FP64 sums of the same state values as the oracle's (1e-12)."""
+    print(f"case spectra1d {ndim}d n={n} {prec}", flush=True)
+    cd = np.complex64 if prec == "f32" else np.complex128
+    if ndim == 3:
+        s = I.random_solenoidal_3d(n, seed=43, dtype=cd)
+    else:
+        s = I.random_vorticity_2d(n, 44, lambda k: k * np.exp(-(k / 6.0) ** 2)).astype(cd)
+    plan = fs.Plan(n, nu=1e-3, dt=1e-3, ndim=ndim, precision=prec)
+    got = plan.energy_spectra_1d(torch.from_numpy(s).cuda()).cpu().numpy()
+    s64 = s.astype(np.complex128)
+    ref = oracle_mod.spectra1d3d(s64) if ndim == 3 else oracle_mod.spectra1d2d(s64)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    got2 = plan.energy_spectra_1d(torch.from_numpy(s).cuda()).cpu().numpy()
+    assert np.array_equal(got, got2)  # deterministic
     plan.close()
