@@ -30,6 +30,12 @@ Pins (tests/test_oracle_*.py, all CPU):
   forcing_alpha3d        injected power equals the prescribed power
   diag2d / diag3d        closed-form Taylor-Green energy, enstrophy and shell,
                          sum of the spectrum equals the energy
+  tendency2d_strat /     single plane waves are exact nonlinear solutions
+  step2d_strat           (internal gravity waves: closed-form oscillation at
+                         N |kx| / |k| with viscous decay, fourth-order
+                         convergence of the step to it); kinetic plus
+                         potential energy conserved by the inviscid tendency;
+                         N2 = 0, b = 0 reduces to the 2D solver
   spectra1d2d / 3d       single Fourier modes land in their bins with the
                          closed-form energy; every axis sums to the component
                          energy measured in physical space
@@ -111,6 +117,8 @@ def lib():
         L.or_umax.argtypes = [i, i, d, vp]
         L.or_umax.restype = d
         L.or_spectra1d3d.argtypes = [i, vp, vp]
+        L.or_tendency2d_strat.argtypes = [i, d, d, vp, vp]
+        L.or_step2d_strat.argtypes = [i, d, d, d, d, vp, i]
         L.or_spectra1d2d.argtypes = [i, d, vp, vp]
         L.or_transfer3d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
         L.or_transfer2d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
@@ -249,6 +257,20 @@ def diag2d(wh, nbins, L=2 * np.pi):
     e, z = C.c_double(), C.c_double()
     lib().or_diag2d(w.shape[0], float(L), _p(w), int(nbins), _p(spec), C.byref(e), C.byref(z))
     return spec, e.value, z.value
+
+
+def tendency2d_strat(s, N2, L=2 * np.pi):
+    """Tendency of the 2D Boussinesq state [2][n][n/2+1] = (w_hat, b_hat)."""
+    x = _c128(s)
+    out = np.empty_like(x)
+    lib().or_tendency2d_strat(x.shape[1], float(L), float(N2), _p(x), _p(out))
+    return out
+
+
+def step2d_strat(s, nu, dt, N2, nsteps, L=2 * np.pi):
+    x = _c128(s).copy()
+    lib().or_step2d_strat(x.shape[1], float(L), float(nu), float(dt), float(N2), _p(x), int(nsteps))
+    return x
 
 
 def spectra1d3d(uh):

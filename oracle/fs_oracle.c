@@ -365,6 +365,53 @@ void or_tendency2d(int n, double L, const cplx *wh, cplx *nh) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* 2D Boussinesq (stably stratified) flow in the vertical (x, y) plane,     */
+/* gravity along -y, buoyancy b, Brunt-Vaisala frequency N (N2 = N^2):       */
+/*   d w / dt + u . grad w = d b / dx            (+ nu lap w)                 */
+/*   d b / dt + u . grad b = -N2 v               (+ nu lap b, Prandtl 1)      */
+/* with w = dv/dx - du/dy.  State [2][n][n/2+1] (w_hat, b_hat); tendency:    */
+/*   N_w = -i kx (u w)^ - i ky (v w)^ + i kx b_hat                           */
+/*   N_b = -i kx (u b)^ - i ky (v b)^ - N2 v_hat,  v_hat = -i kx w_hat/|k|^2  */
+/* dealiased on the kept set, zero at k = 0.                                  */
+/* ------------------------------------------------------------------------ */
+void or_tendency2d_strat(int n, double L, double N2, const cplx *s, cplx *out) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * h, np = (int64_t)n * n;
+  const double kb = 2.0 * M_PI / L;
+  cplx *g = malloc(sizeof(cplx) * 4 * ns);
+  double *r = malloc(sizeof(double) * 4 * np), *q = malloc(sizeof(double) * 4 * np);
+  cplx *fh = malloc(sizeof(cplx) * 4 * ns);
+  for (int64_t i = 0; i < ns; i++) {
+    int my = mode_full((int)(i / h), n), mx = (int)(i % h);
+    int keep = keep1(mx, n) && keep1(my, n);
+    double kx = kb * mx, ky = kb * my, k2 = kx * kx + ky * ky;
+    cplx w = keep ? s[i] : 0, b = keep ? s[ns + i] : 0;
+    g[i] = k2 > 0 ? I * ky * w / k2 : 0;
+    g[ns + i] = k2 > 0 ? -I * kx * w / k2 : 0;
+    g[2 * ns + i] = w;
+    g[3 * ns + i] = b;
+  }
+  for (int c = 0; c < 4; c++) or_irfftn(2, n, g + c * ns, r + c * np);
+  for (int64_t i = 0; i < np; i++) {
+    q[i] = r[i] * r[2 * np + i];               /* u w */
+    q[np + i] = r[np + i] * r[2 * np + i];     /* v w */
+    q[2 * np + i] = r[i] * r[3 * np + i];      /* u b */
+    q[3 * np + i] = r[np + i] * r[3 * np + i]; /* v b */
+  }
+  for (int c = 0; c < 4; c++) or_rfftn(2, n, q + c * np, fh + c * ns);
+  for (int64_t i = 0; i < ns; i++) {
+    int my = mode_full((int)(i / h), n), mx = (int)(i % h);
+    int keep = keep1(mx, n) && keep1(my, n) && (mx != 0 || my != 0);
+    double kx = kb * mx, ky = kb * my;
+    out[i] = keep ? -I * kx * fh[i] - I * ky * fh[ns + i] + I * kx * g[3 * ns + i] : 0;
+    out[ns + i] = keep ? -I * kx * fh[2 * ns + i] - I * ky * fh[3 * ns + i] - N2 * g[ns + i] : 0;
+  }
+  free(g);
+  free(r);
+  free(q);
+  free(fh);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Lawson integrating-factor RK4 (exact viscous factor E = exp(-nu k^2 dt)): */
 /*   k1 = N(u)            k2 = N(E_h (u + dt/2 k1))                          */
 /*   k3 = N(E_h u + dt/2 k2)            k4 = N(E u + dt E_h k3)              */
@@ -480,6 +527,30 @@ void or_step3d(int n, double L, double nu, double dt, double power, double kf_mi
                double kf_max, cplx *uh, int nsteps) {
   struct grid_ctx c = {n, L, 0.0, power, kf_min, kf_max};
   grid_steps(3, n, L, nu, dt, uh, nsteps, &c);
+}
+
+struct strat_ctx {
+  int n;
+  double L, N2;
+};
+
+static void tend2s(const cplx *u, cplx *out, void *ctx) {
+  struct strat_ctx *c = ctx;
+  or_tendency2d_strat(c->n, c->L, c->N2, u, out);
+}
+
+/* Lawson RK4 of the 2D Boussinesq system (both fields decay with nu). */
+void or_step2d_strat(int n, double L, double nu, double dt, double N2, cplx *s, int nsteps) {
+  struct strat_ctx c = {n, L, N2};
+  const int64_t nf = (int64_t)n * (n / 2 + 1);
+  double *E = malloc(sizeof(double) * nf), *Eh = malloc(sizeof(double) * nf);
+  for (int64_t i = 0; i < nf; i++) {
+    E[i] = decay(2, n, L, nu, dt, i);
+    Eh[i] = decay(2, n, L, nu, 0.5 * dt, i);
+  }
+  lawson_rk4(nf, 2, E, Eh, dt, s, nsteps, tend2s, NULL, &c);
+  free(E);
+  free(Eh);
 }
 
 void or_step2d(int n, double L, double nu, double dt, cplx *wh, int nsteps) {
