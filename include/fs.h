@@ -23,6 +23,7 @@
  * Layouts (C order, interleaved complex, contiguous):
  *   3D state / tendency : complex[3][N][N][N/2+1]   (component, kz, ky, kx)
  *   2D state / tendency : complex[N][N/2+1]         (ky, kx), vorticity
+ *                         (FS_BOUSSINESQ: complex[2][N][N/2+1], + buoyancy)
  *   3D physical field   : real[N][N][N]             (z, y, x)
  *   2D physical field   : real[N][N]                (y, x)
  * ky and kz are in FFT order (0..N/2-1, -N/2..-1).  "complex" is two floats
@@ -70,6 +71,13 @@ enum { FS_SCHEME_RK4 = 0, FS_SCHEME_RK2 = 1 };
 #define FS_NO_GRAPH 0x1u /* launch kernels one by one instead of a captured graph */
 #define FS_PROFILE 0x2u  /* time every kernel with events (see fs_profile_read) */
 #define FS_NO_AUTOTUNE 0x4u /* ensembles: keep the default schedules */
+/* 2D only: Boussinesq flow in the vertical plane (gravity along -y) with a
+ * buoyancy field b (Prandtl number 1, squared buoyancy frequency opts.n2):
+ *   dw/dt + u.grad w = db/dx + nu lap w,  db/dt + u.grad b = -n2 v + nu lap b.
+ * The state is then complex[2][N][N/2+1] (w_hat, b_hat); the coupling terms
+ * are part of the tendency, the diffusion stays exact.  Diagnostics,
+ * transfer and 1D spectra describe the vorticity (kinetic) part. */
+#define FS_BOUSSINESQ 0x8u
 
 typedef struct fs_plan fs_plan;
 
@@ -86,6 +94,7 @@ typedef struct {
                            umax_n the largest |u_c| of the physical velocity of u_n
                            (2D: from the vorticity), measured on the GPU during the
                            step's first stage; 0 (default): the fixed step dt */
+  double n2;            /* FS_BOUSSINESQ: squared buoyancy frequency N^2 >= 0 */
 } fs_plan_opts;
 
 /* Fill *opts with the defaults listed above. */

@@ -150,6 +150,7 @@ void fs_plan_opts_default(fs_plan_opts* o) {
   o->flags = 0;
   o->scheme = FS_SCHEME_RK4;
   o->cfl = 0.0;
+  o->n2 = 0.0;
 }
 
 fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
@@ -168,7 +169,11 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   if (o.ndim != 2 && o.ndim != 3) return fail(FS_E_INVALID, "ndim = %d must be 2 or 3", o.ndim);
   if (o.precision != FS_F32 && o.precision != FS_F64)
     return fail(FS_E_INVALID, "precision = %d must be FS_F32 or FS_F64", o.precision);
-  if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE)) return fail(FS_E_INVALID, "unknown flags");
+  if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE | FS_BOUSSINESQ))
+    return fail(FS_E_INVALID, "unknown flags");
+  if ((o.flags & FS_BOUSSINESQ) && o.ndim != 2)
+    return fail(FS_E_UNSUPPORTED, "FS_BOUSSINESQ is implemented for ndim = 2");
+  if (!(isfin(o.n2) && o.n2 >= 0)) return fail(FS_E_INVALID, "n2 must be finite and >= 0");
   if (!(isfin(o.forcing_power) && o.forcing_power >= 0))
     return fail(FS_E_INVALID, "forcing_power must be finite and >= 0");
   if (o.scheme != FS_SCHEME_RK4 && o.scheme != FS_SCHEME_RK2)
@@ -218,12 +223,15 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   p->flags = o.flags;
   p->scheme = o.scheme;
   p->cfl = o.cfl;
+  p->nfield = (o.flags & FS_BOUSSINESQ) ? 2 : 1;
+  p->n2 = o.n2;
   p->stream = (hipStream_t)o.stream;
   p->launch = p->stream;
   if (o.ndim == 3)
     p->ops = o.precision == FS_F32 ? fs::make_ops3<float>(n) : fs::make_ops3<double>(n);
   else
-    p->ops = o.precision == FS_F32 ? fs::make_ops2<float>(n) : fs::make_ops2<double>(n);
+    p->ops = o.precision == FS_F32 ? fs::make_ops2<float>(n, p->nfield)
+                                   : fs::make_ops2<double>(n, p->nfield);
   if (!p->ops.stage) {
     delete h;
     return fail(FS_E_UNSUPPORTED, "no kernels for n = %d", n);
@@ -235,7 +243,7 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   const size_t rs = o.precision == FS_F32 ? 4 : 8, cs = 2 * rs;
   const int band_elems = 3 * (2 * bw + 1) * (2 * bw + 1) * (bw + 1);
   const size_t dpart = (size_t)fs::kDiagMaxBlocks * (fs::kDiagMaxBins + 2) * sizeof(double);
-  constexpr int kPieces = 10;
+  constexpr int kPieces = 11;
   size_t off[kPieces];
   size_t sz[kPieces] = {cs * n,
                         rs * n,
@@ -246,7 +254,8 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
                         cs * (size_t)(band_elems > 0 ? band_elems : 1),
                         rs * 2,
                         dpart,
-                        64};  // step, elapsed time, velocity maximum
+                        64,  // step, elapsed time, velocity maximum
+                        cs * (p->ops.elems_sin ? p->ops.elems_sin : 1)};
   size_t total = 0;
   for (int i = 0; i < kPieces; i++) {
     off[i] = total;
@@ -271,6 +280,7 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   p->tdev = (double*)(b + off[9]);
   p->umaxdev = (unsigned long long*)(b + off[9] + 8);
   p->dtdev = b + off[9] + 16;
+  p->sin = p->ops.elems_sin ? b + off[10] : nullptr;
   p->dpart_blocks = fs::kDiagMaxBlocks;
 
   const float dt32 = (float)dt;
@@ -337,7 +347,7 @@ fs_status fs_plan_set_stream(fs_plan* plan, void* stream) {
 fs_status fs_state_elems(const fs_plan* plan, size_t* n_complex) {
   if (!plan || !n_complex) return fail(FS_E_INVALID, "NULL argument");
   const size_t n = plan->p.n;
-  *n_complex = plan->p.ndim == 3 ? 3 * n * n * (n / 2 + 1) : n * (n / 2 + 1);
+  *n_complex = plan->p.ndim == 3 ? 3 * n * n * (n / 2 + 1) : plan->p.nfield * n * (n / 2 + 1);
   return FS_OK;
 }
 

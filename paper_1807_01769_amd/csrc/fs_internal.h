@@ -59,6 +59,7 @@ struct Ops {
   // workspace element counts (complex elements of the plan's precision)
   size_t elems_a, elems_b, elems_acc;
   size_t elems_full;  // one undealiased field in the transform workspace layout
+  size_t elems_sin;   // 2D Boussinesq stage-input buffer (0 otherwise)
 };
 
 struct Plan {
@@ -69,6 +70,8 @@ struct Plan {
   unsigned flags = 0;
   int scheme = FS_SCHEME_RK4;
   double cfl = 0;           // > 0: dt_n = min(dt, cfl (L/n) / max|u_c|) every step
+  int nfield = 1;           // 2D state fields: 1 (vorticity) or 2 (+ buoyancy)
+  double n2 = 0;            // 2D Boussinesq: squared buoyancy frequency
   double t_fixed = 0;       // elapsed time of fixed-dt steps (host)
   int device = 0;
   hipStream_t stream = nullptr;  // caller's stream
@@ -82,6 +85,7 @@ struct Plan {
   void *bufA = nullptr, *bufB = nullptr, *acc = nullptr, *vband = nullptr, *alpha = nullptr;
   double* dpart = nullptr;  // diagnostics partial sums
   void* dtdev = nullptr;    // step of the current step (working precision)
+  void* sin = nullptr;      // 2D Boussinesq stage input
   double* tdev = nullptr;   // elapsed time of adaptive steps
   unsigned long long* umaxdev = nullptr;  // velocity maximum of the step (double bits)
   int dpart_blocks = 0;
@@ -113,7 +117,7 @@ bool launched(Plan* p, const char* what);
 template <typename T>
 Ops make_ops3(int n);
 template <typename T>
-Ops make_ops2(int n);
+Ops make_ops2(int n, int nfield);
 
 // diagnostics launchers (diag.hip)
 template <typename T>

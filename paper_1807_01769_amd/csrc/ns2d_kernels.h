@@ -10,6 +10,11 @@
 //                  combine -> next stage input -> (u, v, w) -> three inverse
 //                  y transforms                               [k2_y]
 //   X (c2r / r2c)  three C2R, products, two R2C               [k2_x]
+// With NF = 2 the state also holds the buoyancy b_hat (Boussinesq flow in
+// the vertical plane, gravity along -y, N2 the squared Brunt-Vaisala
+// frequency):  N_w += -div(u w) + i kx b_hat,  N_b = -div(u b) - N2 v_hat;
+// the passes then carry (u, v, w, b) and (u w, v w, u b, v b), and the y pass
+// keeps every stage input in `a.sin` for the linear coupling terms.
 //
 // Every kernel works on a batch of equal-size runs: block b handles part
 // b % bpr of local run b / bpr; the run's state sits at state_off[run] in
@@ -30,12 +35,13 @@ struct Batch {
   int bpr;                     // blocks per run
 };
 
-// three inverse y transforms of (u, v, w) derived from w_hat held as w[e]
-// at y-position t + e*P of line b (kx = mx); writes Wn[3][XT][N][16]
-template <typename T, int N, int LB, class TW>
-__device__ __forceinline__ void y_inverse_three(cx<T> (&w)[8], int t, int b, int mx, T kb,
-                                                cx<T>* __restrict__ w1, cx<T>* lds,
-                                                const TW& tw) {
+// inverse y transforms of (u, v, w[, b]) derived from the stage input held
+// as w[0][e] (and b = w[1][e]) at y-position t + e*P of line b (kx = mx);
+// writes Wn[3 or 4][XT][N][16]
+template <typename T, int N, int LB, int NF, class TW>
+__device__ __forceinline__ void y_inverse_fields(cx<T> (&w)[NF][8], int t, int b, int mx, T kb,
+                                                 cx<T>* __restrict__ w1, cx<T>* lds,
+                                                 const TW& tw) {
   using G = Geo<N, false>;
   constexpr int P = G::P;
   const size_t fstride = (size_t)G::XT * N * kTile;
@@ -43,7 +49,7 @@ __device__ __forceinline__ void y_inverse_three(cx<T> (&w)[8], int t, int b, int
   auto lidx = [=](int, int pos) { return pos * LB + b; };
   const T kx = kb * (T)mx;
 #pragma unroll
-  for (int f = 0; f < 3; f++) {
+  for (int f = 0; f < 2 + NF; f++) {
     cx<T> v[1][8];
 #pragma unroll
     for (int e = 0; e < 8; e++) {
@@ -51,9 +57,9 @@ __device__ __forceinline__ void y_inverse_three(cx<T> (&w)[8], int t, int b, int
       const T ky = kb * (T)(iy <= N / 2 ? iy : iy - N);
       const T k2 = kx * kx + ky * ky;
       const T ik2 = k2 > (T)0 ? (T)1 / k2 : (T)0;
-      if (f == 0) v[0][e] = mul_i(cscale(w[e], ky * ik2));
-      else if (f == 1) v[0][e] = mul_i(cscale(w[e], -kx * ik2));
-      else v[0][e] = w[e];
+      if (f == 0) v[0][e] = mul_i(cscale(w[0][e], ky * ik2));
+      else if (f == 1) v[0][e] = mul_i(cscale(w[0][e], -kx * ik2));
+      else v[0][e] = w[f - 2][e];
     }
     fft_lines<T, N, +1, 1>(v, t, lds, lidx, tw);
     cx<T>* dst = dst0 + f * fstride;
@@ -64,7 +70,7 @@ __device__ __forceinline__ void y_inverse_three(cx<T> (&w)[8], int t, int b, int
 
 // First pass of a stage from the state: W1 = inverse y transforms of
 // (u, v, w).  Grid: runs * bpr, bpr = 16 XT / LB.
-template <typename T, int N, int LB>
+template <typename T, int N, int LB, int NF = 1>
 __global__ void __launch_bounds__(LB * N / 8)
     k2_p1(const cx<T>* __restrict__ state, cx<T>* __restrict__ w1, StageArgs<T> a, Batch bt) {
   using G = Geo<N, false>;
@@ -76,39 +82,49 @@ __global__ void __launch_bounds__(LB * N / 8)
   state += bt.state_off ? bt.state_off[run] : 0;
   w1 += run * bt.out_stride;
   const int mx = part * LB + b;
-  cx<T> w[8];
+  cx<T> w[NF][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int iy = t + e * P;
-    const bool kept = mx < G::H && G::i2j(iy) >= 0;
-    w[e] = kept ? state[(size_t)iy * NH + mx] : cx<T>{0, 0};
+    const int jy = G::i2j(iy);
+    const bool kept = mx < G::H && jy >= 0;
+#pragma unroll
+    for (int f = 0; f < NF; f++) {
+      w[f][e] = kept ? state[(size_t)f * N * NH + (size_t)iy * NH + mx] : cx<T>{0, 0};
+      if (NF > 1 && kept)
+        a.sin[((size_t)f * G::XT * G::M + (size_t)(mx >> 4) * G::M + jy) * kTile + (mx & 15)] =
+            w[f][e];
+    }
   }
-  y_inverse_three<T, N, LB>(w, t, b, mx, a.kb, w1, lds, twr);
+  y_inverse_fields<T, N, LB, NF>(w, t, b, mx, a.kb, w1, lds, twr);
 }
 
-// X pass: rows (y0, y0+1); in Wn[3][XT][N][16] (u, v, w), out Wn[2][XT][N][16]
-// ((u w), (v w)) scaled by `scale`.  Grid: runs * bpr, bpr = N/2/RP.
-template <typename T, int N, int RP>
+// X pass: rows (y0, y0+1); in Wn[3 or 4][XT][N][16] (u, v, w[, b]), out
+// Wn[2 or 4][XT][N][16] ((u w), (v w)[, (u b), (v b)]) scaled by `scale`.
+// With umax, the largest |u|, |v| is max-reduced into *umax.
+// Grid: runs * bpr, bpr = N/2/RP.
+template <typename T, int N, int RP, int NF = 1>
 __global__ void __launch_bounds__(RP * N / 8)
     k2_x(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
          T scale, Batch bt, unsigned long long* __restrict__ umax) {
   using G = Geo<N, false>;
   using R = RowPairs<N>;
   constexpr int P = G::P;
-  __shared__ cx<T> lds[RP * 3 * R::NPAD];
+  constexpr int NL = 2 + NF;  // inverse lines: (u, v) of each row, (w[, b]) of both rows
+  __shared__ cx<T> lds[RP * NL * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
   const Twiddles<T, N> twr(tw, t);
   const int run = blockIdx.x / bt.bpr, part = blockIdx.x % bt.bpr;
   in += run * bt.in_stride;
   out += run * bt.out_stride;
   const int y0 = 2 * (part * RP + rp);
-  cx<T>* my_lds = lds + rp * 3 * R::NPAD;
+  cx<T>* my_lds = lds + rp * NL * R::NPAD;
   auto lidx = [=](int f, int pos) { return f * R::NPAD + R::pad(pos); };
   const size_t fstride = (size_t)G::XT * N * kTile;
   auto at = [=](int f, int y, int m) -> cx<T> {
     return in[f * fstride + ((size_t)(m >> 4) * N + y) * kTile + (m & 15)];
   };
-  cx<T> v[3][8];
+  cx<T> v[NL][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int k = t + e * P;
@@ -116,10 +132,12 @@ __global__ void __launch_bounds__(RP * N / 8)
                                        [&](int m) { return at(1, y0, m); });
     v[1][e] = c2r_pair_at<T, N, false>(k, [&](int m) { return at(0, y0 + 1, m); },
                                        [&](int m) { return at(1, y0 + 1, m); });
-    v[2][e] = c2r_pair_at<T, N, false>(k, [&](int m) { return at(2, y0, m); },
-                                       [&](int m) { return at(2, y0 + 1, m); });
+#pragma unroll
+    for (int f = 0; f < NF; f++)
+      v[2 + f][e] = c2r_pair_at<T, N, false>(k, [&](int m) { return at(2 + f, y0, m); },
+                                             [&](int m) { return at(2 + f, y0 + 1, m); });
   }
-  fft_lines<T, N, +1, 3>(v, t, my_lds, lidx, twr);
+  fft_lines<T, N, +1, NL>(v, t, my_lds, lidx, twr);
   if (umax) {
     double um = 0.0;
 #pragma unroll
@@ -128,40 +146,47 @@ __global__ void __launch_bounds__(RP * N / 8)
                                  fmax(fabs(v[1][e].re), fabs(v[1][e].im))));
     umax_wave(umax, um);
   }
-  cx<T> q[2][8];
+  // product lines: (u s, v s) of row y0 and of row y1 for s = w[, b]
+  cx<T> q[2 * NF][8];
 #pragma unroll
-  for (int e = 0; e < 8; e++) {
-    const T w0 = v[2][e].re * scale, w1 = v[2][e].im * scale;
-    q[0][e] = {v[0][e].re * w0, v[0][e].im * w0};
-    q[1][e] = {v[1][e].re * w1, v[1][e].im * w1};
-  }
-  fft_lines<T, N, -1, 2>(q, t, my_lds, lidx, twr);
+  for (int f = 0; f < NF; f++)
 #pragma unroll
-  for (int f = 0; f < 2; f++)
+    for (int e = 0; e < 8; e++) {
+      const T s0 = v[2 + f][e].re * scale, s1 = v[2 + f][e].im * scale;
+      q[2 * f][e] = {v[0][e].re * s0, v[0][e].im * s0};
+      q[2 * f + 1][e] = {v[1][e].re * s1, v[1][e].im * s1};
+    }
+  fft_lines<T, N, -1, 2 * NF>(q, t, my_lds, lidx, twr);
+#pragma unroll
+  for (int f = 0; f < 2 * NF; f++)
 #pragma unroll
     for (int e = 0; e < 8; e++) my_lds[lidx(f, t + e * P)] = q[f][e];
   __syncthreads();
   for (int m = t; m < G::XT * kTile; m += P) {
     const size_t o = ((size_t)(m >> 4) * N) * kTile + (m & 15);
 #pragma unroll
-    for (int r = 0; r < 2; r++) {
+    for (int l = 0; l < 2 * NF; l++) {
+      const int r = l & 1, fo = 2 * (l >> 1);  // row, first output field of the line
       cx<T> A = {0, 0}, B = {0, 0};
-      if (m < G::H) r2c_untangle(my_lds[lidx(r, m)], my_lds[lidx(r, (N - m) & (N - 1))], A, B);
-      out[o + (size_t)(y0 + r) * kTile] = A;
-      out[fstride + o + (size_t)(y0 + r) * kTile] = B;
+      if (m < G::H) r2c_untangle(my_lds[lidx(l, m)], my_lds[lidx(l, (N - m) & (N - 1))], A, B);
+      out[fo * fstride + o + (size_t)(y0 + r) * kTile] = A;
+      out[(fo + 1) * fstride + o + (size_t)(y0 + r) * kTile] = B;
     }
   }
 }
 
-// Y pass: forward y transforms of (u w, v w), tendency, Lawson combine and the
-// next stage's inverse transforms.  acc: [XT][M][16] per run.
+// Y pass: forward y transforms of the products, tendency, Lawson combine and
+// the next stage's inverse transforms.  acc: [NF][XT][M][16] per run; with
+// NF = 2, a.sin [2][XT][M][16] holds the stage input (read for the coupling
+// terms, then replaced by the next stage input).
 // Grid: runs * bpr, bpr = 16 XT / LB.
-template <typename T, int N, int LB, int MODE>
+template <typename T, int N, int LB, int MODE, int NF = 1>
 __global__ void __launch_bounds__(LB * N / 8)
     k2_y(const cx<T>* __restrict__ w2, cx<T>* __restrict__ w1, StageArgs<T> a, Batch bt,
          int do_p1) {
   using G = Geo<N, false>;
   constexpr int P = G::P, NH = N / 2 + 1;
+  constexpr size_t kField = (size_t)G::XT * G::M * kTile;  // one compact field
   __shared__ cx<T> lds[LB * N];
   const int b = threadIdx.x % LB, t = threadIdx.x / LB;
   const Twiddles<T, N> twr(a.tw, t);
@@ -173,48 +198,66 @@ __global__ void __launch_bounds__(LB * N / 8)
   auto lidx = [=](int, int pos) { return pos * LB + b; };
   const size_t fstride = (size_t)G::XT * N * kTile;
   const cx<T>* src = w2 + (size_t)(mx >> 4) * N * kTile + (mx & 15);
-  cx<T> f1[1][8], f2[1][8];
+  cx<T> f[2 * NF][1][8];
 #pragma unroll
-  for (int e = 0; e < 8; e++) {
-    f1[0][e] = src[(size_t)(t + e * P) * kTile];
-    f2[0][e] = src[fstride + (size_t)(t + e * P) * kTile];
-  }
-  fft_lines<T, N, -1, 1>(f1, t, lds, lidx, twr);
-  fft_lines<T, N, -1, 1>(f2, t, lds, lidx, twr);
+  for (int c = 0; c < 2 * NF; c++)
+#pragma unroll
+    for (int e = 0; e < 8; e++) f[c][0][e] = src[c * fstride + (size_t)(t + e * P) * kTile];
+#pragma unroll
+  for (int c = 0; c < 2 * NF; c++) fft_lines<T, N, -1, 1>(f[c], t, lds, lidx, twr);
 
   const T kx = a.kb * (T)mx;
   const T dt = stage_dt(a);
-  cx<T> w[8];
+  cx<T> w[NF][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int iy = t + e * P;
     const int jy = G::i2j(iy);
     if (!(mx < G::H && jy >= 0)) {
-      w[e] = {0, 0};
+#pragma unroll
+      for (int c = 0; c < NF; c++) w[c][e] = {0, 0};
       continue;
     }
     const int my = iy <= N / 2 ? iy : iy - N;
     const T ky = a.kb * (T)my;
-    cx<T> nl = {0, 0};
-    if (mx != 0 || my != 0) nl = mul_i(cscale(f1[0][e], -kx) - cscale(f2[0][e], ky));
+    const size_t ci = ((size_t)(mx >> 4) * G::M + jy) * kTile + (mx & 15);
+    cx<T> nl[NF];
+#pragma unroll
+    for (int c = 0; c < NF; c++) nl[c] = {0, 0};
+    if (mx != 0 || my != 0) {
+#pragma unroll
+      for (int c = 0; c < NF; c++)
+        nl[c] = mul_i(cscale(f[2 * c][0][e], -kx) - cscale(f[2 * c + 1][0][e], ky));
+      if constexpr (NF == 2) {
+        const cx<T> ws = a.sin[ci], bs = a.sin[kField + ci];
+        const T k2 = kx * kx + ky * ky;
+        nl[0] = nl[0] + mul_i(cscale(bs, kx));                // + d b / dx
+        nl[1] = nl[1] + mul_i(cscale(ws, a.n2 * kx / k2));    // - N2 v
+      }
+    }
     const size_t so = soff + (size_t)iy * NH + mx;
     if constexpr (MODE == kModeTend) {
-      a.tend[so] = nl;
+#pragma unroll
+      for (int c = 0; c < NF; c++) a.tend[(size_t)c * N * NH + so] = nl[c];
     } else {
       const T E = a.e1[mx] * a.e1[iy];
       const T Eh = a.eh1[mx] * a.eh1[iy];
-      const size_t ao = run * bt.acc_stride + ((size_t)(mx >> 4) * G::M + jy) * kTile + (mx & 15);
-      cx<T> acc = {0, 0}, u = {0, 0};
-      if constexpr (mode_reads_state(MODE)) u = a.state[so];
-      if constexpr (mode_reads_acc(MODE)) acc = a.acc[ao];
-      const cx<T> nxt = rk4_combine<MODE>(u, acc, nl, E, Eh, dt);
-      if constexpr (mode_writes_state(MODE)) a.state[so] = nxt;
-      if constexpr (mode_writes_acc(MODE)) a.acc[ao] = acc;
-      w[e] = nxt;
+      const size_t ao = run * bt.acc_stride + ci;
+#pragma unroll
+      for (int c = 0; c < NF; c++) {
+        cx<T> acc = {0, 0}, u = {0, 0};
+        if constexpr (mode_reads_state(MODE)) u = a.state[(size_t)c * N * NH + so];
+        if constexpr (mode_reads_acc(MODE)) acc = a.acc[c * kField + ao];
+        const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, dt);
+        if constexpr (mode_writes_state(MODE)) a.state[(size_t)c * N * NH + so] = nxt;
+        if constexpr (mode_writes_acc(MODE)) a.acc[c * kField + ao] = acc;
+        if constexpr (NF == 2) a.sin[c * kField + ci] = nxt;
+        w[c][e] = nxt;
+      }
     }
   }
   if constexpr (MODE != kModeTend) {
-    if (do_p1) y_inverse_three<T, N, LB>(w, t, b, mx, a.kb, w1, lds, twr);
+    if (do_p1) y_inverse_fields<T, N, LB, NF>(w, t, b, mx, a.kb, w1, lds, twr);
   }
 }
 

@@ -97,6 +97,8 @@ struct StageArgs {
   T kb;                // 2 pi / L
   T dt;                // step (used when dtp is null)
   const T* dtp;        // device step of the current step (adaptive steps), or null
+  cx<T>* sin;          // 2D Boussinesq: stage input [2][XT][M][16] (else null)
+  T n2;                // 2D Boussinesq: squared buoyancy frequency
   int bw;              // half width of the forcing-band cube (modes)
   int m2min, m2max;    // band: m2min <= |m|^2 <= m2max; m2max < 0 => off
 };

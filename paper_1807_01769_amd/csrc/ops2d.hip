@@ -22,13 +22,15 @@ StageArgs<T> stage_args2(Plan* p, void* state, void* tend) {
   a.kb = (T)(2.0 * M_PI / p->L);
   a.dt = (T)p->dt;
   a.dtp = (const T*)p->dtdev;
+  a.sin = (cx<T>*)p->sin;
+  a.n2 = (T)p->n2;
   a.bw = 0;
   a.m2min = 0;
   a.m2max = -1;
   return a;
 }
 
-template <typename T, int N>
+template <typename T, int N, int NF>
 struct L2 {
   using G = Geo<N, false>;
   using GF = Geo<N, true>;
@@ -42,7 +44,7 @@ struct L2 {
 
   static void p1(Plan* p, const void* state) {
     p->begin(KID_P1);
-    hipLaunchKernelGGL((k2_p1<T, N, LB>), dim3(G::XT * kTile / LB), dim3(LB * N / 8), 0,
+    hipLaunchKernelGGL((k2_p1<T, N, LB, NF>), dim3(G::XT * kTile / LB), dim3(LB * N / 8), 0,
                        p->launch, (const cx<T>*)state, A(p),
                        stage_args2<T>(p, (void*)state, nullptr), one(G::XT * kTile / LB));
     launched(p, "k2_p1");
@@ -50,7 +52,7 @@ struct L2 {
   }
   static void x(Plan* p, bool umax = false) {
     p->begin(KID_X);
-    hipLaunchKernelGGL((k2_x<T, N, RP>), dim3(N / 2 / RP), dim3(RP * N / 8), 0, p->launch,
+    hipLaunchKernelGGL((k2_x<T, N, RP, NF>), dim3(N / 2 / RP), dim3(RP * N / 8), 0, p->launch,
                        (const cx<T>*)A(p), B(p), TW(p), (T)(1.0 / ((double)N * N)), one(N / 2 / RP),
                        umax ? p->umaxdev : nullptr);
     launched(p, "k2_x");
@@ -59,7 +61,7 @@ struct L2 {
   template <int MODE>
   static void yk(Plan* p, void* state, void* tend, int do_p1) {
     p->begin(KID_Z);
-    hipLaunchKernelGGL((k2_y<T, N, LB, MODE>), dim3(G::XT * kTile / LB), dim3(LB * N / 8), 0,
+    hipLaunchKernelGGL((k2_y<T, N, LB, MODE, NF>), dim3(G::XT * kTile / LB), dim3(LB * N / 8), 0,
                        p->launch, (const cx<T>*)B(p), A(p), stage_args2<T>(p, state, tend),
                        one(G::XT * kTile / LB), do_p1);
     launched(p, "k2_y");
@@ -79,7 +81,7 @@ struct L2 {
     }
   }
   static void tendency(Plan* p, const void* state, void* out, bool) {
-    launch_fill<T>(p, out, (size_t)N * (N / 2 + 1));
+    launch_fill<T>(p, out, (size_t)NF * N * (N / 2 + 1));
     p1(p, state);
     x(p);
     yk<kModeTend>(p, (void*)state, out, 0);
@@ -120,33 +122,39 @@ struct L2 {
     o.dtstep = launch_dtstep<T>;
     o.transfer = launch_transfer<T>;
     o.spectra1d = launch_spectra1d<T>;
-    const size_t wn3 = (size_t)3 * G::XT * N * kTile;
-    const size_t wn2 = (size_t)2 * G::XT * N * kTile;
+    const size_t wn3 = (size_t)(2 + NF) * G::XT * N * kTile;  // (u, v, w[, b])
+    const size_t wn2 = (size_t)2 * NF * G::XT * N * kTile;    // products
     const size_t wfull = (size_t)GF::XT * N * kTile;
     o.elems_a = wn3 > wfull ? wn3 : wfull;
     o.elems_b = wn2 > wfull ? wn2 : wfull;
-    o.elems_acc = (size_t)G::XT * G::M * kTile;
+    o.elems_acc = (size_t)NF * G::XT * G::M * kTile;
+    o.elems_sin = NF > 1 ? (size_t)NF * G::XT * G::M * kTile : 0;
     return o;
   }
 };
 
 }  // namespace
 
-template <typename T>
-Ops make_ops2(int n) {
+template <typename T, int NF>
+Ops ops2_of(int n) {
   switch (n) {
-    case 16: return L2<T, 16>::ops();
-    case 32: return L2<T, 32>::ops();
-    case 64: return L2<T, 64>::ops();
-    case 128: return L2<T, 128>::ops();
-    case 256: return L2<T, 256>::ops();
-    case 512: return L2<T, 512>::ops();
-    case 1024: return L2<T, 1024>::ops();
+    case 16: return L2<T, 16, NF>::ops();
+    case 32: return L2<T, 32, NF>::ops();
+    case 64: return L2<T, 64, NF>::ops();
+    case 128: return L2<T, 128, NF>::ops();
+    case 256: return L2<T, 256, NF>::ops();
+    case 512: return L2<T, 512, NF>::ops();
+    case 1024: return L2<T, 1024, NF>::ops();
     default: return Ops{};
   }
 }
 
-template Ops make_ops2<float>(int);
-template Ops make_ops2<double>(int);
+template <typename T>
+Ops make_ops2(int n, int nfield) {
+  return nfield == 2 ? ops2_of<T, 2>(n) : ops2_of<T, 1>(n);
+}
+
+template Ops make_ops2<float>(int, int);
+template Ops make_ops2<double>(int, int);
 
 }  // namespace fs

@@ -22,7 +22,7 @@ lib = C.CDLL(LIB_PATH)
 FS_OK, FS_E_INVALID, FS_E_UNSUPPORTED, FS_E_NOMEM, FS_E_DEVICE, FS_E_NONFINITE = 0, -1, -2, -3, -4, -5
 FS_F32, FS_F64 = 0, 1
 FS_SCHEME_RK4, FS_SCHEME_RK2 = 0, 1
-FS_NO_GRAPH, FS_PROFILE = 0x1, 0x2
+FS_NO_GRAPH, FS_PROFILE, FS_BOUSSINESQ = 0x1, 0x2, 0x8
 KERNEL_NAMES = ["p1", "y_inverse", "x_c2r_product_r2c", "y_forward", "z_stage",
                 "forcing_alpha", "fill", "fft_only", "diagnostics"]
 
@@ -38,6 +38,7 @@ class Opts(C.Structure):
         ("flags", C.c_uint),
         ("scheme", C.c_int),
         ("cfl", C.c_double),
+        ("n2", C.c_double),
     ]
 
 
@@ -94,7 +95,8 @@ class Plan:
     def __init__(self, n: int, L: float = 2 * math.pi, nu: float = 0.0, dt: float = 1e-3,
                  ndim: int = 3, precision: str = "f32", stream=None, forcing_power: float = 0.0,
                  forcing_kmin: float = 2.0, forcing_kmax: float = 3.0, graphs: bool = True,
-                 profile: bool = False, scheme: str = "rk4", cfl: float = 0.0):
+                 profile: bool = False, scheme: str = "rk4", cfl: float = 0.0,
+                 boussinesq: bool = False, n2: float = 0.0):
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1807_01769_amd.fs needs a HIP device")
         self.n, self.L, self.nu, self.dt, self.ndim = int(n), float(L), float(nu), float(dt), int(ndim)
@@ -110,7 +112,10 @@ class Plan:
         o.forcing_power = float(forcing_power)
         o.forcing_kmin = float(forcing_kmin)
         o.forcing_kmax = float(forcing_kmax)
-        o.flags = (0 if graphs else FS_NO_GRAPH) | (FS_PROFILE if profile else 0)
+        o.flags = ((0 if graphs else FS_NO_GRAPH) | (FS_PROFILE if profile else 0) |
+                   (FS_BOUSSINESQ if boussinesq else 0))
+        o.n2 = float(n2)
+        self.nfield = 2 if boussinesq else 1
         o.scheme = {"rk4": FS_SCHEME_RK4, "rk2": FS_SCHEME_RK2}[scheme]
         o.cfl = float(cfl)
         h = _vp()
@@ -121,6 +126,14 @@ class Plan:
     # -- shapes ------------------------------------------------------------
     @property
     def state_shape(self):
+        n = self.n
+        if self.ndim == 3:
+            return (3, n, n, n // 2 + 1)
+        return (2, n, n // 2 + 1) if self.nfield == 2 else (n, n // 2 + 1)
+
+    @property
+    def field_shape(self):
+        """Shape of one scalar spectral field (diagnostics act on the first)."""
         n = self.n
         return (3, n, n, n // 2 + 1) if self.ndim == 3 else (n, n // 2 + 1)
 
