@@ -78,7 +78,20 @@ def algorithmic_bytes(n: int, steps: int, elem: int = 8) -> dict:
     return {k: (total[k], launches[k]) for k in total}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(seconds: float, n: int = 128) -> dict:
+    """The oracle's RK4 steps of the forced recipe on all host threads for
+    about `seconds`, then one step on a single thread."""
     import numpy as np
     import oracle
     from paper_1807_01769_amd import inputs as I
@@ -92,9 +105,16 @@ def cpu_baseline(seconds: float, n: int = 128) -> dict:
         t += time.perf_counter() - t0
         steps += 1
     ns = t / steps / n ** 3 * 1e9
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.step3d(u, NU, DT, 1, power=POWER, kf_min=KMIN, kf_max=KMAX)
+    t1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
     return {"value": ns, "unit": "ns/gridpoint/step", "cores": cores, "kind": "oracle",
+            "cpu": cpu_model(), "single_thread_value": t1 / n ** 3 * 1e9,
             "sample": f"{steps} FP64 RK4 step(s) of the same forced-turbulence recipe at {n}^3 "
-                      f"({t:.1f} s); per-point FFT work at {n}^3 is log2({n})/9 of 512^3's"}
+                      f"on {cores} threads ({t:.1f} s), then 1 step on one thread ({t1:.1f} s); "
+                      f"per-point FFT work at {n}^3 is log2({n})/9 of 512^3's"}
 
 
 LES_DT_FACTOR = 8  # LES step = 8 DNS steps (grid ratio 512 / 64)
