@@ -36,6 +36,10 @@ Pins (tests/test_oracle_*.py, all CPU):
                          convergence of the step to it); kinetic plus
                          potential energy conserved by the inviscid tendency;
                          N2 = 0, b = 0 reduces to the 2D solver
+  step3d_rot             a single helical mode is an exact inertial wave
+                         (frequency f kz / |k|, viscous decay) reproduced to
+                         rounding; f = 0 reduces to step3d; the propagator is
+                         orthogonal (energy kept at nu = 0, N = 0)
   spectra1d2d / 3d       single Fourier modes land in their bins with the
                          closed-form energy; every axis sums to the component
                          energy measured in physical space
@@ -118,6 +122,7 @@ def lib():
         L.or_umax.restype = d
         L.or_spectra1d3d.argtypes = [i, vp, vp]
         L.or_tendency2d_strat.argtypes = [i, d, d, vp, vp]
+        L.or_step3d_rot.argtypes = [i, d, d, d, d, d, d, d, vp, i]
         L.or_step2d_strat.argtypes = [i, d, d, d, d, vp, i]
         L.or_spectra1d2d.argtypes = [i, d, vp, vp]
         L.or_transfer3d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
@@ -257,6 +262,14 @@ def diag2d(wh, nbins, L=2 * np.pi):
     e, z = C.c_double(), C.c_double()
     lib().or_diag2d(w.shape[0], float(L), _p(w), int(nbins), _p(spec), C.byref(e), C.byref(z))
     return spec, e.value, z.value
+
+
+def step3d_rot(uh, nu, dt, f, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0):
+    """Lawson RK4 in a frame rotating about z (Coriolis -f z x u)."""
+    u = _c128(uh).copy()
+    lib().or_step3d_rot(u.shape[1], float(L), float(nu), float(dt), float(f), float(power),
+                        float(kf_min), float(kf_max), _p(u), int(nsteps))
+    return u
 
 
 def tendency2d_strat(s, N2, L=2 * np.pi):
