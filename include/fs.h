@@ -95,6 +95,12 @@ typedef struct {
                            (2D: from the vorticity), measured on the GPU during the
                            step's first stage; 0 (default): the fixed step dt */
   double n2;            /* FS_BOUSSINESQ: squared buoyancy frequency N^2 >= 0 */
+  double rotation;      /* 3D: Coriolis parameter f of a frame rotating about z
+                           (acceleration -f z x u); 0 (default): none.  Folded into
+                           the exact linear propagator: for solenoidal fields
+                           E(t) u = exp(-nu k^2 t)(cos(s t) u - sin(s t) khat x u),
+                           s = f kz / |k|; fs_tendency excludes it; fixed steps
+                           only (cfl = 0) */
 } fs_plan_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -337,7 +343,8 @@ fs_status fs_closure_features(fs_closure *c, const float *A, const float *tau, f
  * fs_tendency / fs_step_rk4 of the plan.  The LES reads the network's
  * parameters when its work runs; it borrows plan and model (both must
  * outlive it) and owns ~40 coarse fields of scratch when a model is given.
- * With a model the plan must use fixed steps and RK4 (else FS_E_UNSUPPORTED).
+ * With a model the plan must use fixed steps, RK4 and no rotation (else
+ * FS_E_UNSUPPORTED).
  */
 typedef struct fs_les fs_les;
 fs_status fs_les_create(fs_les **out, fs_plan *coarse, fs_mlp *model, float a_scale,

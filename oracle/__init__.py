@@ -122,7 +122,7 @@ def lib():
         L.or_umax.restype = d
         L.or_spectra1d3d.argtypes = [i, vp, vp]
         L.or_tendency2d_strat.argtypes = [i, d, d, vp, vp]
-        L.or_step3d_rot.argtypes = [i, d, d, d, d, d, d, d, vp, i]
+        L.or_step3d_rot.argtypes = [i, d, d, d, d, d, d, d, i, vp, i]
         L.or_step2d_strat.argtypes = [i, d, d, d, d, vp, i]
         L.or_spectra1d2d.argtypes = [i, d, vp, vp]
         L.or_transfer3d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
@@ -264,11 +264,11 @@ def diag2d(wh, nbins, L=2 * np.pi):
     return spec, e.value, z.value
 
 
-def step3d_rot(uh, nu, dt, f, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0):
-    """Lawson RK4 in a frame rotating about z (Coriolis -f z x u)."""
+def step3d_rot(uh, nu, dt, f, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0, scheme=4):
+    """Lawson RK4 (or RK2) in a frame rotating about z (Coriolis -f z x u)."""
     u = _c128(uh).copy()
     lib().or_step3d_rot(u.shape[1], float(L), float(nu), float(dt), float(f), float(power),
-                        float(kf_min), float(kf_max), _p(u), int(nsteps))
+                        float(kf_min), float(kf_max), int(scheme), _p(u), int(nsteps))
     return u
 
 

@@ -593,9 +593,10 @@ struct rot_ctx {
   double nu, f;
 };
 
-/* Lawson RK4 with the operator propagator (E = E(dt), Eh = E(dt/2)). */
+/* Lawson RK4 (scheme 4) or RK2 (scheme 2) with the operator propagator
+ * (E = E(dt), Eh = E(dt/2)). */
 void or_step3d_rot(int n, double L, double nu, double dt, double f, double power, double kf_min,
-                   double kf_max, cplx *uh, int nsteps) {
+                   double kf_max, int scheme, cplx *uh, int nsteps) {
   struct grid_ctx c = {n, L, 0.0, power, kf_min, kf_max};
   const int64_t tot = 3 * (int64_t)n * n * (n / 2 + 1);
   cplx *k1 = malloc(sizeof(cplx) * tot), *k2 = malloc(sizeof(cplx) * tot);
@@ -609,6 +610,12 @@ void or_step3d_rot(int n, double L, double nu, double dt, double f, double power
     for (int64_t i = 0; i < tot; i++) w[i] = uh[i] + 0.5 * dt * k1[i];
     rot_apply(n, L, nu, f, 0.5 * dt, w, v);
     tend3(v, k2, &c);
+    if (scheme == 2) { /* midpoint rule: u' = E u + dt Eh k2 */
+      rot_apply(n, L, nu, f, 0.5 * dt, k2, w);
+      rot_apply(n, L, nu, f, dt, uh, v);
+      for (int64_t i = 0; i < tot; i++) uh[i] = v[i] + dt * w[i];
+      continue;
+    }
     /* v = Eh u + dt/2 k2 */
     rot_apply(n, L, nu, f, 0.5 * dt, uh, v);
     for (int64_t i = 0; i < tot; i++) v[i] += 0.5 * dt * k2[i];

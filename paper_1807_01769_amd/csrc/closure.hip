@@ -517,8 +517,8 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
   *out = nullptr;
   if (!is_3d_f32(coarse)) return fail(FS_E_UNSUPPORTED, "the LES needs a 3D single-precision plan");
   if (coarse->p.failed) return fail(FS_E_DEVICE, "plan failed earlier");
-  if (model && (coarse->p.cfl > 0 || coarse->p.scheme != FS_SCHEME_RK4))
-    return fail(FS_E_UNSUPPORTED, "the closure LES steps with fixed-dt RK4 plans");
+  if (model && (coarse->p.cfl > 0 || coarse->p.scheme != FS_SCHEME_RK4 || coarse->p.rotf != 0))
+    return fail(FS_E_UNSUPPORTED, "the closure LES steps with fixed-dt, non-rotating RK4 plans");
   fs_les* les = new fs_les;
   les->plan = coarse;
   les->net = model;

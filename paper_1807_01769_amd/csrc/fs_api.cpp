@@ -151,6 +151,7 @@ void fs_plan_opts_default(fs_plan_opts* o) {
   o->scheme = FS_SCHEME_RK4;
   o->cfl = 0.0;
   o->n2 = 0.0;
+  o->rotation = 0.0;
 }
 
 fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
@@ -174,6 +175,11 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   if ((o.flags & FS_BOUSSINESQ) && o.ndim != 2)
     return fail(FS_E_UNSUPPORTED, "FS_BOUSSINESQ is implemented for ndim = 2");
   if (!(isfin(o.n2) && o.n2 >= 0)) return fail(FS_E_INVALID, "n2 must be finite and >= 0");
+  if (!isfin(o.rotation)) return fail(FS_E_INVALID, "rotation must be finite");
+  if (o.rotation != 0.0 && o.ndim != 3)
+    return fail(FS_E_UNSUPPORTED, "rotation is implemented for ndim = 3");
+  if (o.rotation != 0.0 && o.cfl > 0)
+    return fail(FS_E_UNSUPPORTED, "rotation is implemented with fixed steps");
   if (!(isfin(o.forcing_power) && o.forcing_power >= 0))
     return fail(FS_E_INVALID, "forcing_power must be finite and >= 0");
   if (o.scheme != FS_SCHEME_RK4 && o.scheme != FS_SCHEME_RK2)
@@ -225,6 +231,7 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   p->cfl = o.cfl;
   p->nfield = (o.flags & FS_BOUSSINESQ) ? 2 : 1;
   p->n2 = o.n2;
+  p->rotf = o.rotation;
   p->stream = (hipStream_t)o.stream;
   p->launch = p->stream;
   if (o.ndim == 3)

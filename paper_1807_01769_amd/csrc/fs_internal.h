@@ -72,6 +72,7 @@ struct Plan {
   double cfl = 0;           // > 0: dt_n = min(dt, cfl (L/n) / max|u_c|) every step
   int nfield = 1;           // 2D state fields: 1 (vorticity) or 2 (+ buoyancy)
   double n2 = 0;            // 2D Boussinesq: squared buoyancy frequency
+  double rotf = 0;          // 3D rotating frame: Coriolis parameter
   double t_fixed = 0;       // elapsed time of fixed-dt steps (host)
   int device = 0;
   hipStream_t stream = nullptr;  // caller's stream

@@ -315,7 +315,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
 // (do_p1) the next stage's six inverse z transforms into w1.
 // MODE kModeTend writes the tendency to a.tend instead.  Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, bool ROT = false>
 __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
     k3_z(const cx<T>* __restrict__ w4, cx<T>* __restrict__ w1, StageArgs<T> a, int do_p1) {
   using G = Geo<N, false>;
@@ -392,16 +392,45 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
       const T E = a.e1[mx] * a.e1[iy] * a.e1[iz];
       const T Eh = a.eh1[mx] * a.eh1[iy] * a.eh1[iz];
       const size_t ao = (((size_t)xt * G::M + jy) * G::M + jz) * kTile + sub * C::LB + b;
+      if constexpr (ROT) {
+        // rotating frame: the combination acts on the mode's 3-vectors
+        cx<T> u[3], acc[3], nxt[3];
 #pragma unroll
-      for (int c = 0; c < 3; c++) {
-        cx<T> acc = {0, 0};
-        cx<T> u = {0, 0};
-        if constexpr (mode_reads_state(MODE)) u = a.state[c * cstride + so];
-        if constexpr (mode_reads_acc(MODE)) acc = a.acc[c * acstride + ao];
-        const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, dt);
-        if constexpr (mode_writes_state(MODE)) a.state[c * cstride + so] = nxt;
-        if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc;
-        v[c][e] = nxt;
+        for (int c = 0; c < 3; c++) {
+          u[c] = acc[c] = cx<T>{0, 0};
+          if constexpr (mode_reads_state(MODE)) u[c] = a.state[c * cstride + so];
+          if constexpr (mode_reads_acc(MODE)) acc[c] = a.acc[c * acstride + ao];
+        }
+        RotProp<T> R;
+        const T kn = sqrt(k2);
+        const T ikn = k2 > (T)0 ? (T)1 / kn : (T)0;
+        R.kh[0] = kx * ikn;
+        R.kh[1] = ky * ikn;
+        R.kh[2] = kz * ikn;
+        const T sg = a.rotf * kz * ikn;
+        R.s1 = sin(sg * dt);
+        R.c1 = cos(sg * dt);
+        R.s2 = sin(sg * dt * (T)0.5);
+        R.c2 = cos(sg * dt * (T)0.5);
+        rot_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          if constexpr (mode_writes_state(MODE)) a.state[c * cstride + so] = nxt[c];
+          if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc[c];
+          v[c][e] = nxt[c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+          cx<T> acc = {0, 0};
+          cx<T> u = {0, 0};
+          if constexpr (mode_reads_state(MODE)) u = a.state[c * cstride + so];
+          if constexpr (mode_reads_acc(MODE)) acc = a.acc[c * acstride + ao];
+          const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, dt);
+          if constexpr (mode_writes_state(MODE)) a.state[c * cstride + so] = nxt;
+          if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc;
+          v[c][e] = nxt;
+        }
       }
       if (band && do_p1) {
 #pragma unroll

@@ -99,6 +99,7 @@ struct StageArgs {
   const T* dtp;        // device step of the current step (adaptive steps), or null
   cx<T>* sin;          // 2D Boussinesq: stage input [2][XT][M][16] (else null)
   T n2;                // 2D Boussinesq: squared buoyancy frequency
+  T rotf;              // 3D rotating frame: Coriolis parameter f (z axis)
   int bw;              // half width of the forcing-band cube (modes)
   int m2min, m2max;    // band: m2min <= |m|^2 <= m2max; m2max < 0 => off
 };
@@ -157,6 +158,68 @@ __device__ __forceinline__ cx<T> rk4_combine(cx<T> u, cx<T>& a, cx<T> nl, T E, T
     return cscale(u + cscale(nl, d2), Eh);
   } else {
     return cscale(u, E) + cscale(nl, dt * Eh);
+  }
+}
+
+// The same stage combinations in a frame rotating about z: the linear
+// propagator of viscosity and Coriolis force on solenoidal fields is
+//   E(t) w = exp(-nu k^2 t) (cos(sigma t) w - sin(sigma t) khat x w),
+// sigma = f kz / |k|, applied to the 3-vectors of one mode (E, Eh carry the
+// viscous factors; c1, s1 / c2, s2 the cosines and sines of sigma dt and
+// sigma dt / 2).
+template <typename T>
+struct RotProp {
+  T kh[3];
+  T c1, s1, c2, s2;
+  __device__ __forceinline__ void apply(const cx<T> (&w)[3], T d, bool half, cx<T> (&o)[3]) const {
+    const T c = half ? c2 : c1, s = half ? s2 : s1;
+    const cx<T> x[3] = {cscale(w[2], kh[1]) - cscale(w[1], kh[2]),
+                        cscale(w[0], kh[2]) - cscale(w[2], kh[0]),
+                        cscale(w[1], kh[0]) - cscale(w[0], kh[1])};
+#pragma unroll
+    for (int q = 0; q < 3; q++) o[q] = cscale(cscale(w[q], c) - cscale(x[q], s), d);
+  }
+};
+
+template <int MODE, typename T>
+__device__ __forceinline__ void rot_combine(const cx<T> (&u)[3], cx<T> (&a)[3],
+                                            const cx<T> (&nl)[3], T E, T Eh, T dt,
+                                            const RotProp<T>& R, cx<T> (&next)[3]) {
+  const T d2 = dt * (T)0.5, d3 = dt / (T)3, d6 = dt / (T)6;
+  cx<T> w[3], o[3];
+  if constexpr (MODE == kStage1) {
+#pragma unroll
+    for (int q = 0; q < 3; q++) w[q] = u[q] + cscale(nl[q], d6);
+    R.apply(w, E, false, a);
+#pragma unroll
+    for (int q = 0; q < 3; q++) w[q] = u[q] + cscale(nl[q], d2);
+    R.apply(w, Eh, true, next);
+  } else if constexpr (MODE == kStage2) {
+    R.apply(nl, Eh, true, o);
+#pragma unroll
+    for (int q = 0; q < 3; q++) a[q] = a[q] + cscale(o[q], d3);
+    R.apply(u, Eh, true, o);
+#pragma unroll
+    for (int q = 0; q < 3; q++) next[q] = o[q] + cscale(nl[q], d2);
+  } else if constexpr (MODE == kStage3) {
+    R.apply(nl, Eh, true, o);
+#pragma unroll
+    for (int q = 0; q < 3; q++) a[q] = a[q] + cscale(o[q], d3);
+    R.apply(u, E, false, w);
+#pragma unroll
+    for (int q = 0; q < 3; q++) next[q] = w[q] + cscale(o[q], dt);
+  } else if constexpr (MODE == kStage4) {
+#pragma unroll
+    for (int q = 0; q < 3; q++) next[q] = a[q] + cscale(nl[q], d6);
+  } else if constexpr (MODE == kRk2a) {
+#pragma unroll
+    for (int q = 0; q < 3; q++) w[q] = u[q] + cscale(nl[q], d2);
+    R.apply(w, Eh, true, next);
+  } else {
+    R.apply(nl, Eh, true, o);
+    R.apply(u, E, false, w);
+#pragma unroll
+    for (int q = 0; q < 3; q++) next[q] = w[q] + cscale(o[q], dt);
   }
 }
 

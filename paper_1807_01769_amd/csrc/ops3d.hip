@@ -21,6 +21,9 @@ StageArgs<T> stage_args(Plan* p, void* state, void* tend) {
   a.kb = (T)(2.0 * M_PI / p->L);
   a.dt = (T)p->dt;
   a.dtp = (const T*)p->dtdev;
+  a.sin = nullptr;
+  a.n2 = (T)0;
+  a.rotf = (T)p->rotf;
   a.bw = p->bw;
   a.m2min = p->m2min;
   a.m2max = p->m2max;
@@ -72,9 +75,14 @@ struct L3 {
   template <int MODE>
   static void zk(Plan* p, void* state, void* tend, int do_p1) {
     p->begin(KID_Z);
-    hipLaunchKernelGGL((k3_z<T, N, MODE>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)), dim3(ZC::THREADS), 0,
-                       p->launch, (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend),
-                       do_p1);
+    if (MODE != kModeTend && p->rotf != 0.0)
+      hipLaunchKernelGGL((k3_z<T, N, MODE, true>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)),
+                         dim3(ZC::THREADS), 0, p->launch, (const cx<T>*)B(p), A(p),
+                         stage_args<T>(p, state, tend), do_p1);
+    else
+      hipLaunchKernelGGL((k3_z<T, N, MODE>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)),
+                         dim3(ZC::THREADS), 0, p->launch, (const cx<T>*)B(p), A(p),
+                         stage_args<T>(p, state, tend), do_p1);
     launched(p, "k3_z");
     p->end(KID_Z);
   }

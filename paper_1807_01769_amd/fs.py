@@ -39,6 +39,7 @@ class Opts(C.Structure):
         ("scheme", C.c_int),
         ("cfl", C.c_double),
         ("n2", C.c_double),
+        ("rotation", C.c_double),
     ]
 
 
@@ -96,7 +97,7 @@ class Plan:
                  ndim: int = 3, precision: str = "f32", stream=None, forcing_power: float = 0.0,
                  forcing_kmin: float = 2.0, forcing_kmax: float = 3.0, graphs: bool = True,
                  profile: bool = False, scheme: str = "rk4", cfl: float = 0.0,
-                 boussinesq: bool = False, n2: float = 0.0):
+                 boussinesq: bool = False, n2: float = 0.0, rotation: float = 0.0):
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1807_01769_amd.fs needs a HIP device")
         self.n, self.L, self.nu, self.dt, self.ndim = int(n), float(L), float(nu), float(dt), int(ndim)
@@ -115,6 +116,7 @@ class Plan:
         o.flags = ((0 if graphs else FS_NO_GRAPH) | (FS_PROFILE if profile else 0) |
                    (FS_BOUSSINESQ if boussinesq else 0))
         o.n2 = float(n2)
+        o.rotation = float(rotation)
         self.nfield = 2 if boussinesq else 1
         o.scheme = {"rk4": FS_SCHEME_RK4, "rk2": FS_SCHEME_RK2}[scheme]
         o.cfl = float(cfl)

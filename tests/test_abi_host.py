@@ -36,7 +36,7 @@ class Opts(C.Structure):
     _fields_ = [("ndim", C.c_int), ("precision", C.c_int), ("stream", C.c_void_p),
                 ("forcing_power", C.c_double), ("forcing_kmin", C.c_double),
                 ("forcing_kmax", C.c_double), ("flags", C.c_uint), ("scheme", C.c_int),
-                ("cfl", C.c_double), ("n2", C.c_double)]
+                ("cfl", C.c_double), ("n2", C.c_double), ("rotation", C.c_double)]
 
 
 def _create(lib, n, L, nu, dt, **kw):
@@ -78,6 +78,9 @@ def _create(lib, n, L, nu, dt, **kw):
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8}, -2),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "ndim": 2, "n2": -1.0}, -1),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x10}, -1),
+    ((64, 6.28, 0.1, 0.01), {"rotation": float("inf")}, -1),
+    ((64, 6.28, 0.1, 0.01), {"rotation": 1.0, "ndim": 2}, -2),
+    ((64, 6.28, 0.1, 0.01), {"rotation": 1.0, "cfl": 0.5}, -2),
 ])
 def test_create_validates_before_device(lib, args, kw, expect):
     st, h = _create(lib, *args, **kw)
@@ -168,7 +171,8 @@ def test_closure_and_les_null_arguments(lib):
 def test_opts_defaults(lib):
     lib.fs_plan_opts_default.argtypes = [C.POINTER(Opts)]
     o = Opts()
-    o.scheme, o.cfl, o.n2 = 7, 3.0, 1.0
+    o.scheme, o.cfl, o.n2, o.rotation = 7, 3.0, 1.0, 2.0
     lib.fs_plan_opts_default(C.byref(o))
-    assert (o.ndim, o.precision, o.flags, o.scheme, o.cfl, o.n2) == (3, 0, 0, 0, 0.0, 0.0)
+    assert (o.ndim, o.precision, o.flags, o.scheme, o.cfl, o.n2, o.rotation) == \
+        (3, 0, 0, 0, 0.0, 0.0, 0.0)
     assert (o.forcing_power, o.forcing_kmin, o.forcing_kmax) == (0.0, 2.0, 3.0)

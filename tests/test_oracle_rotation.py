@@ -74,3 +74,18 @@ def test_coriolis_written_out_agrees(oracle_mod):
     effect = np.abs(ref_norot - u).max() / np.abs(u).max()
     assert effect > 1e-3
     assert err < 1e-9, (err, effect)
+
+
+def test_rk2_helical_and_f_zero(oracle_mod):
+    n, nu, f, dt, steps = 16, 0.01, 3.0, 0.05, 20
+    m = (2, 1, 3)
+    u0, h, kh = _helical(n, m, 0.4)
+    u = oracle_mod.step3d_rot(u0, nu, dt, f, steps, scheme=2)
+    k2 = float(np.dot(m, m))
+    T = dt * steps
+    want = u0 * np.exp(-nu * k2 * T - 1j * f * m[2] / np.sqrt(k2) * T)
+    assert np.abs(u - want).max() <= 1e-14
+    r = I.random_solenoidal_3d(16, seed=103)
+    a = oracle_mod.step3d_rot(r, 0.01, 2e-3, 0.0, 3, scheme=2)
+    b, _ = oracle_mod.step3d_ex(r, 0.01, 2e-3, 3, scheme=2)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
