@@ -123,6 +123,9 @@ def lib():
         L.or_spectra1d3d.argtypes = [i, vp, vp]
         L.or_tendency2d_strat.argtypes = [i, d, d, vp, vp]
         L.or_step3d_rot.argtypes = [i, d, d, d, d, d, d, d, i, vp, i]
+        L.or_strat_propagate.argtypes = [i, d, d, d, d, vp, vp]
+        L.or_tendency3d_strat.argtypes = [i, d, vp, d, d, d, vp]
+        L.or_step3d_strat.argtypes = [i, d, d, d, d, d, d, d, i, vp, i]
         L.or_step2d_strat.argtypes = [i, d, d, d, d, vp, i]
         L.or_spectra1d2d.argtypes = [i, d, vp, vp]
         L.or_transfer3d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
@@ -262,6 +265,34 @@ def diag2d(wh, nbins, L=2 * np.pi):
     e, z = C.c_double(), C.c_double()
     lib().or_diag2d(w.shape[0], float(L), _p(w), int(nbins), _p(spec), C.byref(e), C.byref(z))
     return spec, e.value, z.value
+
+
+def strat_propagate(s, nu, N2, t, L=2 * np.pi):
+    """Exact propagator of viscosity, buoyancy force and stratification on a
+    [4][n][n][n/2+1] state (kept modes; zero elsewhere)."""
+    a = _c128(s)
+    out = np.empty_like(a)
+    lib().or_strat_propagate(a.shape[1], float(L), float(nu), float(N2), float(t), _p(a), _p(out))
+    return out
+
+
+def tendency3d_strat(s, L=2 * np.pi, alpha=0.0, kf_min=2.0, kf_max=3.0):
+    """Nonlinear tendency of the 3D Boussinesq system (P[u x w] + forcing,
+    -i k.(u b)^); the linear terms belong to the propagator."""
+    a = _c128(s)
+    out = np.empty_like(a)
+    lib().or_tendency3d_strat(a.shape[1], float(L), _p(a), float(alpha), float(kf_min),
+                              float(kf_max), _p(out))
+    return out
+
+
+def step3d_strat(s, nu, dt, N2, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0,
+                 scheme=4):
+    """Lawson RK4 (or RK2) of the 3D Boussinesq system."""
+    a = _c128(s).copy()
+    lib().or_step3d_strat(a.shape[1], float(L), float(nu), float(dt), float(N2), float(power),
+                          float(kf_min), float(kf_max), int(scheme), _p(a), int(nsteps))
+    return a
 
 
 def step3d_rot(uh, nu, dt, f, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0, scheme=4):

@@ -588,48 +588,44 @@ static void rot_apply(int n, double L, double nu, double f, double t, const cplx
   }
 }
 
-struct rot_ctx {
-  struct grid_ctx g;
-  double nu, f;
-};
+/* Lawson RK4 (scheme 4) or RK2 (scheme 2) with an operator propagator      */
+/* prop(t, in, out) = E(t) in over `tot` complex values (E = E(dt),           */
+/* Eh = E(dt/2)); hook (if any) runs on u_n before the step's first stage.   */
+typedef void (*prop_fn)(double t, const cplx *in, cplx *out, void *ctx);
 
-/* Lawson RK4 (scheme 4) or RK2 (scheme 2) with the operator propagator
- * (E = E(dt), Eh = E(dt/2)). */
-void or_step3d_rot(int n, double L, double nu, double dt, double f, double power, double kf_min,
-                   double kf_max, int scheme, cplx *uh, int nsteps) {
-  struct grid_ctx c = {n, L, 0.0, power, kf_min, kf_max};
-  const int64_t tot = 3 * (int64_t)n * n * (n / 2 + 1);
+static void lawson_prop(int64_t tot, double dt, int scheme, cplx *uh, int nsteps, tend_fn tend,
+                        hook_fn hook, prop_fn prop, void *ctx) {
   cplx *k1 = malloc(sizeof(cplx) * tot), *k2 = malloc(sizeof(cplx) * tot);
   cplx *k3 = malloc(sizeof(cplx) * tot), *k4 = malloc(sizeof(cplx) * tot);
   cplx *v = malloc(sizeof(cplx) * tot), *w = malloc(sizeof(cplx) * tot);
   cplx *acc = malloc(sizeof(cplx) * tot);
   for (int s = 0; s < nsteps; s++) {
-    alpha3(uh, &c);
-    tend3(uh, k1, &c);
+    if (hook) hook(uh, ctx);
+    tend(uh, k1, ctx);
     /* v = Eh (u + dt/2 k1) */
     for (int64_t i = 0; i < tot; i++) w[i] = uh[i] + 0.5 * dt * k1[i];
-    rot_apply(n, L, nu, f, 0.5 * dt, w, v);
-    tend3(v, k2, &c);
+    prop(0.5 * dt, w, v, ctx);
+    tend(v, k2, ctx);
     if (scheme == 2) { /* midpoint rule: u' = E u + dt Eh k2 */
-      rot_apply(n, L, nu, f, 0.5 * dt, k2, w);
-      rot_apply(n, L, nu, f, dt, uh, v);
+      prop(0.5 * dt, k2, w, ctx);
+      prop(dt, uh, v, ctx);
       for (int64_t i = 0; i < tot; i++) uh[i] = v[i] + dt * w[i];
       continue;
     }
     /* v = Eh u + dt/2 k2 */
-    rot_apply(n, L, nu, f, 0.5 * dt, uh, v);
+    prop(0.5 * dt, uh, v, ctx);
     for (int64_t i = 0; i < tot; i++) v[i] += 0.5 * dt * k2[i];
-    tend3(v, k3, &c);
+    tend(v, k3, ctx);
     /* v = E u + dt Eh k3 */
-    rot_apply(n, L, nu, f, 0.5 * dt, k3, w);
-    rot_apply(n, L, nu, f, dt, uh, v);
+    prop(0.5 * dt, k3, w, ctx);
+    prop(dt, uh, v, ctx);
     for (int64_t i = 0; i < tot; i++) v[i] += dt * w[i];
-    tend3(v, k4, &c);
+    tend(v, k4, ctx);
     /* u' = E (u + dt/6 k1) + dt/3 Eh (k2 + k3) + dt/6 k4 */
     for (int64_t i = 0; i < tot; i++) w[i] = uh[i] + dt / 6.0 * k1[i];
-    rot_apply(n, L, nu, f, dt, w, acc);
+    prop(dt, w, acc, ctx);
     for (int64_t i = 0; i < tot; i++) w[i] = k2[i] + k3[i];
-    rot_apply(n, L, nu, f, 0.5 * dt, w, v);
+    prop(0.5 * dt, w, v, ctx);
     for (int64_t i = 0; i < tot; i++) uh[i] = acc[i] + dt / 3.0 * v[i] + dt / 6.0 * k4[i];
   }
   free(k1);
@@ -639,6 +635,126 @@ void or_step3d_rot(int n, double L, double nu, double dt, double f, double power
   free(v);
   free(w);
   free(acc);
+}
+
+struct rot_ctx {
+  struct grid_ctx g;
+  double nu, f;
+};
+
+static void rot_prop(double t, const cplx *in, cplx *out, void *ctx) {
+  struct rot_ctx *c = ctx;
+  rot_apply(c->g.n, c->g.L, c->nu, c->f, t, in, out);
+}
+static void rot_tend(const cplx *u, cplx *out, void *ctx) { tend3(u, out, &((struct rot_ctx *)ctx)->g); }
+static void rot_hook(const cplx *u, void *ctx) { alpha3(u, &((struct rot_ctx *)ctx)->g); }
+
+void or_step3d_rot(int n, double L, double nu, double dt, double f, double power, double kf_min,
+                   double kf_max, int scheme, cplx *uh, int nsteps) {
+  struct rot_ctx c = {{n, L, 0.0, power, kf_min, kf_max}, nu, f};
+  lawson_prop(3 * (int64_t)n * n * (n / 2 + 1), dt, scheme, uh, nsteps, rot_tend, rot_hook,
+              rot_prop, &c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3D Boussinesq (stably stratified) flow, gravity along -z, buoyancy b,     */
+/* squared buoyancy frequency N2, Prandtl number 1:                          */
+/*   du/dt = u x w - grad(p + |u|^2/2) + b z + nu lap u,   div u = 0         */
+/*   db/dt + u . grad b = -N2 uz + nu lap b                                  */
+/* State [4][n][n][n/2+1] = (ux, uy, uz, b) hats.  The nonlinear tendency is */
+/*   N_u = P[(u x w)^] (+ band forcing),  N_b = -i k . (u b)^               */
+/* (dealiased, zero at k = 0).  The linear part L(u, b) = (P[b z], -N2 uz)   */
+/* has P[b z] = b q with q = z - khat khat_z; a = uz and b then oscillate    */
+/* with sigma = N |k_h| / |k| (g2 = |k_h|^2 / |k|^2 = q_z):                  */
+/*   a' = g2 b,  b' = -N2 a,                                                 */
+/* so exp(tL)(u, b) = (u + [(c - 1) a / g2 + b S] q,  c b - N2 S a)          */
+/* with c = cos(sigma t), S = sin(sigma t) / sigma (S = t at sigma = 0) and  */
+/* c - 1 = -2 sin^2(sigma t / 2); with viscosity every component also decays */
+/* by exp(-nu k^2 t).  This is the propagator of the Lawson scheme.          */
+/* ------------------------------------------------------------------------ */
+void or_strat_propagate(int n, double L, double nu, double N2, double t, const cplx *in,
+                        cplx *out) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
+  const double kb = 2.0 * M_PI / L, Nb = sqrt(N2);
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int m[3] = {ix, mode_full(iy, n), mode_full(iz, n)};
+    const int keep = keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n);
+    const double k[3] = {kb * m[0], kb * m[1], kb * m[2]};
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    if (!keep || k2 == 0) {
+      for (int c = 0; c < 4; c++) out[c * ns + i] = 0;
+      continue;
+    }
+    const double g2 = (k[0] * k[0] + k[1] * k[1]) / k2;
+    const double q[3] = {-k[0] * k[2] / k2, -k[1] * k[2] / k2, g2};
+    const double sg = Nb * sqrt(g2);
+    const double cm1 = -2.0 * pow(sin(0.5 * sg * t), 2); /* cos(sg t) - 1 */
+    const double S = sg > 0 ? sin(sg * t) / sg : t;
+    const double d = exp(-nu * k2 * t);
+    const cplx u[3] = {in[i], in[ns + i], in[2 * ns + i]}, b = in[3 * ns + i];
+    const cplx coef = (g2 > 0 ? cm1 * u[2] / g2 : 0) + S * b;
+    for (int c = 0; c < 3; c++) out[c * ns + i] = d * (u[c] + coef * q[c]);
+    out[3 * ns + i] = d * ((1.0 + cm1) * b - N2 * S * u[2]);
+  }
+}
+
+void or_tendency3d_strat(int n, double L, const cplx *s, double alpha, double kf_min,
+                         double kf_max, cplx *out) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h, np = (int64_t)n * n * n;
+  const double kb = 2.0 * M_PI / L;
+  /* velocity part: the 3D tendency of the first three fields */
+  or_tendency3d(n, L, s, alpha, kf_min, kf_max, out);
+  /* buoyancy: -i k . (u b)^ of the masked fields */
+  cplx *g = malloc(sizeof(cplx) * 4 * ns), *fh = malloc(sizeof(cplx) * 3 * ns);
+  double *r = malloc(sizeof(double) * 4 * np), *f = malloc(sizeof(double) * 3 * np);
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int keep = keep1(ix, n) && keep1(mode_full(iy, n), n) && keep1(mode_full(iz, n), n);
+    for (int c = 0; c < 4; c++) g[c * ns + i] = keep ? s[c * ns + i] : 0;
+  }
+  for (int c = 0; c < 4; c++) or_irfftn(3, n, g + c * ns, r + c * np);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < np; i++)
+    for (int c = 0; c < 3; c++) f[c * np + i] = r[c * np + i] * r[3 * np + i];
+  for (int c = 0; c < 3; c++) or_rfftn(3, n, f + c * np, fh + c * ns);
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int m[3] = {ix, mode_full(iy, n), mode_full(iz, n)};
+    int keep = keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n) &&
+               (m[0] != 0 || m[1] != 0 || m[2] != 0);
+    cplx d = 0;
+    for (int c = 0; c < 3; c++) d += kb * m[c] * fh[c * ns + i];
+    out[3 * ns + i] = keep ? -I * d : 0;
+  }
+  free(g);
+  free(fh);
+  free(r);
+  free(f);
+}
+
+struct strat3_ctx {
+  struct grid_ctx g;
+  double nu, N2;
+};
+
+static void strat3_prop(double t, const cplx *in, cplx *out, void *ctx) {
+  struct strat3_ctx *c = ctx;
+  or_strat_propagate(c->g.n, c->g.L, c->nu, c->N2, t, in, out);
+}
+static void strat3_tend(const cplx *u, cplx *out, void *ctx) {
+  struct grid_ctx *g = &((struct strat3_ctx *)ctx)->g;
+  or_tendency3d_strat(g->n, g->L, u, g->alpha, g->kf_min, g->kf_max, out);
+}
+static void strat3_hook(const cplx *u, void *ctx) { alpha3(u, &((struct strat3_ctx *)ctx)->g); }
+
+/* Lawson RK4 / RK2 of the 3D Boussinesq system with the exact propagator of
+ * viscosity, buoyancy force and stratification; forcing acts on u only. */
+void or_step3d_strat(int n, double L, double nu, double dt, double N2, double power,
+                     double kf_min, double kf_max, int scheme, cplx *s, int nsteps) {
+  struct strat3_ctx c = {{n, L, 0.0, power, kf_min, kf_max}, nu, N2};
+  lawson_prop(4 * (int64_t)n * n * (n / 2 + 1), dt, scheme, s, nsteps, strat3_tend, strat3_hook,
+              strat3_prop, &c);
 }
 
 /* Largest |u_c| over the grid points and velocity components of a kept-set
