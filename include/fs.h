@@ -22,6 +22,7 @@
  *
  * Layouts (C order, interleaved complex, contiguous):
  *   3D state / tendency : complex[3][N][N][N/2+1]   (component, kz, ky, kx)
+ *                         (FS_BOUSSINESQ: complex[4][...], + buoyancy)
  *   2D state / tendency : complex[N][N/2+1]         (ky, kx), vorticity
  *                         (FS_BOUSSINESQ: complex[2][N][N/2+1], + buoyancy)
  *   3D physical field   : real[N][N][N]             (z, y, x)
@@ -71,12 +72,24 @@ enum { FS_SCHEME_RK4 = 0, FS_SCHEME_RK2 = 1 };
 #define FS_NO_GRAPH 0x1u /* launch kernels one by one instead of a captured graph */
 #define FS_PROFILE 0x2u  /* time every kernel with events (see fs_profile_read) */
 #define FS_NO_AUTOTUNE 0x4u /* ensembles: keep the default schedules */
-/* 2D only: Boussinesq flow in the vertical plane (gravity along -y) with a
- * buoyancy field b (Prandtl number 1, squared buoyancy frequency opts.n2):
- *   dw/dt + u.grad w = db/dx + nu lap w,  db/dt + u.grad b = -n2 v + nu lap b.
- * The state is then complex[2][N][N/2+1] (w_hat, b_hat); the coupling terms
- * are part of the tendency, the diffusion stays exact.  Diagnostics,
- * transfer and 1D spectra describe the vorticity (kinetic) part. */
+/* Boussinesq (stably stratified) flow with a buoyancy field b (Prandtl
+ * number 1, squared buoyancy frequency opts.n2), advected in conservative
+ * form and dealiased like the velocity.
+ * 2D, vertical plane, gravity along -y:
+ *   dw/dt + u.grad w = db/dx + nu lap w,  db/dt + u.grad b = -n2 v + nu lap b;
+ *   state complex[2][N][N/2+1] (w_hat, b_hat); the coupling terms are part of
+ *   the tendency, the diffusion stays exact.
+ * 3D, gravity along -z:
+ *   du/dt + w x u = -grad p + b z + nu lap u,  db/dt + u.grad b = -n2 uz + nu lap b;
+ *   state complex[4][N][N][N/2+1] (ux, uy, uz, b hats).  The linear terms
+ *   (buoyancy force, stratification, diffusion) are integrated exactly: with
+ *   q = z - khat khat_z, g2 = |k_h|^2/|k|^2, s = sqrt(n2 g2), c = cos(s t),
+ *   S = sin(s t)/s (t when s = 0),
+ *   E(t)(u, b) = exp(-nu k^2 t) (u + [(c-1) uz/g2 + S b] q,  c b - n2 S uz);
+ *   fs_tendency returns the nonlinear terms (-i k.(u b)^ for b).  Fixed
+ *   steps only (cfl = 0), no rotation; forcing acts on u.
+ * Diagnostics, transfer and 1D spectra describe the velocity (2D: vorticity)
+ * part. */
 #define FS_BOUSSINESQ 0x8u
 
 typedef struct fs_plan fs_plan;
@@ -100,7 +113,7 @@ typedef struct {
                            the exact linear propagator: for solenoidal fields
                            E(t) u = exp(-nu k^2 t)(cos(s t) u - sin(s t) khat x u),
                            s = f kz / |k|; fs_tendency excludes it; fixed steps
-                           only (cfl = 0) */
+                           only (cfl = 0), not with FS_BOUSSINESQ */
 } fs_plan_opts;
 
 /* Fill *opts with the defaults listed above. */

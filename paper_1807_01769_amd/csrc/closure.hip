@@ -241,7 +241,10 @@ fs_status fail(fs_status s, const char* fmt, ...) {
   return s;
 }
 
-bool is_3d_f32(const fs_plan* p) { return p->p.ndim == 3 && p->p.prec == FS_F32; }
+// 3D single-precision plan of the plain velocity state (no buoyancy field)
+bool is_3d_f32(const fs_plan* p) {
+  return p->p.ndim == 3 && p->p.prec == FS_F32 && p->p.nfield == 3;
+}
 
 int64_t spec_elems(int n) { return (int64_t)n * n * (n / 2 + 1); }
 int64_t phys_elems(int n) { return (int64_t)n * n * n; }
@@ -280,7 +283,7 @@ fs_status fs_closure_create(fs_closure** out, fs_plan* fine, fs_plan* coarse) {
   if (!out || !fine || !coarse) return fail(FS_E_INVALID, "NULL argument");
   *out = nullptr;
   if (!is_3d_f32(fine) || !is_3d_f32(coarse))
-    return fail(FS_E_UNSUPPORTED, "closure samples need two 3D single-precision plans");
+    return fail(FS_E_UNSUPPORTED, "closure samples need two 3D single-precision velocity plans");
   const int nf = fine->p.n, nc = coarse->p.n;
   if (nc >= nf) return fail(FS_E_INVALID, "coarse n = %d must be below fine n = %d", nc, nf);
   if (std::fabs(fine->p.L - coarse->p.L) > 1e-12 * fine->p.L)
@@ -515,7 +518,7 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
                         const float* tau_scale, float clip) {
   if (!out || !coarse) return fail(FS_E_INVALID, "NULL argument");
   *out = nullptr;
-  if (!is_3d_f32(coarse)) return fail(FS_E_UNSUPPORTED, "the LES needs a 3D single-precision plan");
+  if (!is_3d_f32(coarse)) return fail(FS_E_UNSUPPORTED, "the LES needs a 3D single-precision velocity plan");
   if (coarse->p.failed) return fail(FS_E_DEVICE, "plan failed earlier");
   if (model && (coarse->p.cfl > 0 || coarse->p.scheme != FS_SCHEME_RK4 || coarse->p.rotf != 0))
     return fail(FS_E_UNSUPPORTED, "the closure LES steps with fixed-dt, non-rotating RK4 plans");

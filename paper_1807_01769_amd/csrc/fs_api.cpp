@@ -172,14 +172,14 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
     return fail(FS_E_INVALID, "precision = %d must be FS_F32 or FS_F64", o.precision);
   if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE | FS_BOUSSINESQ))
     return fail(FS_E_INVALID, "unknown flags");
-  if ((o.flags & FS_BOUSSINESQ) && o.ndim != 2)
-    return fail(FS_E_UNSUPPORTED, "FS_BOUSSINESQ is implemented for ndim = 2");
   if (!(isfin(o.n2) && o.n2 >= 0)) return fail(FS_E_INVALID, "n2 must be finite and >= 0");
   if (!isfin(o.rotation)) return fail(FS_E_INVALID, "rotation must be finite");
   if (o.rotation != 0.0 && o.ndim != 3)
     return fail(FS_E_UNSUPPORTED, "rotation is implemented for ndim = 3");
-  if (o.rotation != 0.0 && o.cfl > 0)
-    return fail(FS_E_UNSUPPORTED, "rotation is implemented with fixed steps");
+  if (o.rotation != 0.0 && (o.flags & FS_BOUSSINESQ))
+    return fail(FS_E_UNSUPPORTED, "rotation and FS_BOUSSINESQ together are not implemented");
+  if (o.ndim == 3 && (o.rotation != 0.0 || (o.flags & FS_BOUSSINESQ)) && o.cfl > 0)
+    return fail(FS_E_UNSUPPORTED, "3D rotation and stratification are implemented with fixed steps");
   if (!(isfin(o.forcing_power) && o.forcing_power >= 0))
     return fail(FS_E_INVALID, "forcing_power must be finite and >= 0");
   if (o.scheme != FS_SCHEME_RK4 && o.scheme != FS_SCHEME_RK2)
@@ -229,13 +229,14 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   p->flags = o.flags;
   p->scheme = o.scheme;
   p->cfl = o.cfl;
-  p->nfield = (o.flags & FS_BOUSSINESQ) ? 2 : 1;
+  p->nfield = (o.ndim == 3 ? 3 : 1) + ((o.flags & FS_BOUSSINESQ) ? 1 : 0);
   p->n2 = o.n2;
   p->rotf = o.rotation;
   p->stream = (hipStream_t)o.stream;
   p->launch = p->stream;
   if (o.ndim == 3)
-    p->ops = o.precision == FS_F32 ? fs::make_ops3<float>(n) : fs::make_ops3<double>(n);
+    p->ops = o.precision == FS_F32 ? fs::make_ops3<float>(n, p->nfield)
+                                   : fs::make_ops3<double>(n, p->nfield);
   else
     p->ops = o.precision == FS_F32 ? fs::make_ops2<float>(n, p->nfield)
                                    : fs::make_ops2<double>(n, p->nfield);
@@ -354,7 +355,7 @@ fs_status fs_plan_set_stream(fs_plan* plan, void* stream) {
 fs_status fs_state_elems(const fs_plan* plan, size_t* n_complex) {
   if (!plan || !n_complex) return fail(FS_E_INVALID, "NULL argument");
   const size_t n = plan->p.n;
-  *n_complex = plan->p.ndim == 3 ? 3 * n * n * (n / 2 + 1) : plan->p.nfield * n * (n / 2 + 1);
+  *n_complex = (size_t)plan->p.nfield * (plan->p.ndim == 3 ? n : 1) * n * (n / 2 + 1);
   return FS_OK;
 }
 

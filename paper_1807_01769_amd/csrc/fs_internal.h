@@ -70,8 +70,8 @@ struct Plan {
   unsigned flags = 0;
   int scheme = FS_SCHEME_RK4;
   double cfl = 0;           // > 0: dt_n = min(dt, cfl (L/n) / max|u_c|) every step
-  int nfield = 1;           // 2D state fields: 1 (vorticity) or 2 (+ buoyancy)
-  double n2 = 0;            // 2D Boussinesq: squared buoyancy frequency
+  int nfield = 1;           // state fields: 2D 1 (vorticity), 3D 3 (velocity); + 1 buoyancy
+  double n2 = 0;            // Boussinesq: squared buoyancy frequency
   double rotf = 0;          // 3D rotating frame: Coriolis parameter
   double t_fixed = 0;       // elapsed time of fixed-dt steps (host)
   int device = 0;
@@ -116,7 +116,7 @@ void set_error(const char* fmt, ...);
 bool launched(Plan* p, const char* what);
 
 template <typename T>
-Ops make_ops3(int n);
+Ops make_ops3(int n, int nfield);
 template <typename T>
 Ops make_ops2(int n, int nfield);
 

@@ -14,6 +14,10 @@
 // Only kept modes are ever moved: the z passes touch the M x H kept
 // (ky, kx) columns, the y passes the H kept kx planes, and the x pass reads
 // and writes the H kept kx values of every row.
+//
+// Stratified (Boussinesq) flow carries a buoyancy field b as a fourth state
+// component: the inverse passes move seven fields (u, w, b), the x pass also
+// forms the buoyancy flux u b, and the forward passes move six (u x w, u b).
 #pragma once
 #include "ns_common.h"
 
@@ -28,19 +32,32 @@ namespace fs {
 // pair needs one LDS line and about 100 VGPRs.  With umax, the largest
 // |u_c| of the physical velocity is max-reduced into *umax.
 // in : Wn[6][N][XT][N][16]   out: Wn[3][N][XT][N][16]
-// Grid: (N/2/RP, N).
+// STRAT: in Wn[7] (+ b), out Wn[6] (+ u b, v b, w b); b of the two rows is
+// one complex line, the flux (fx + i fy) of each row and (fz(y0) + i fz(y1))
+// three more forward lines.
+// Grid: (N/2/RP, N) with RP = XRows<T, N, STRAT>::RP.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__((RowPairs<N>::THREADS))
+// Row pairs of a block: the seven staged fields of a double-precision
+// stratified pass take half as many row pairs per block, so that the block
+// stays within 64 KiB of LDS.
+template <typename T, int N, bool STRAT>
+using XRows = RowPairs<N, (STRAT && sizeof(T) == 8) ? 32 : 64>;
+
+template <typename T, int N, bool STRAT = false>
+__global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
     k3_x(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
          T scale, unsigned long long* __restrict__ umax) {
   using G = Geo<N, false>;
-  using R = RowPairs<N>;
+  using R = XRows<T, N, STRAT>;
   constexpr int P = G::P;
+  constexpr int FIN = STRAT ? 7 : 6;  // input fields
   // staging: the row pair's kept coefficients, [field][row][xt][16] (tiles
   // of one row 128 bytes apart, so 32 lanes reading consecutive kx of a row
   // hit distinct LDS banks)
-  constexpr int SPAIR = 6 * G::XT * 2 * kTile;
+  constexpr int SPAIR = FIN * G::XT * 2 * kTile;
+  static_assert(STRAT == false || N > 512 || sizeof(T) == 4 ||
+                    (size_t)R::RP * (SPAIR + R::NPAD) * sizeof(cx<T>) <= 65536,
+                "x-pass staging exceeds 64 KiB of LDS");
   __shared__ cx<T> stage[R::RP * SPAIR];
   __shared__ cx<T> lds[R::RP * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
@@ -56,7 +73,7 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   // coefficients in memory; move them with 16-byte loads, all in flight.
   {
     constexpr int PER = 16 / (int)sizeof(cx<T>);        // coefficients per load
-    constexpr int LOADS = 6 * G::XT * 2 * kTile / PER;  // per row pair
+    constexpr int LOADS = FIN * G::XT * 2 * kTile / PER;  // per row pair
     const uint4* src4 = reinterpret_cast<const uint4*>(in);
     uint4* st4 = reinterpret_cast<uint4*>(st);
 #pragma unroll
@@ -84,10 +101,8 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
     kind[e] = k <= G::K ? (k == 0 ? 2 : 1) : (k >= N - G::K ? -1 : 0);
     off[e] = m;
   }
-  // inverse transform of fields (2g, 2g+1) of row r into v
-  auto inverse_pair = [&](int g, int r, cx<T> (&v)[1][8]) {
-    const cx<T>* ba = st + ((2 * g) * 2 + r) * G::XT * kTile;
-    const cx<T>* bb = ba + 2 * G::XT * kTile;
+  // inverse transform of the complex line A + i B (half spectra ba, bb)
+  auto inverse_line = [&](const cx<T>* ba, const cx<T>* bb, cx<T> (&v)[1][8]) {
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       cx<T> res = {0, 0};
@@ -99,6 +114,11 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
       v[0][e] = res;
     }
     fft_lines<T, N, +1, 1>(v, t, line, lidx, twr);
+  };
+  // fields (2g, 2g+1) of row r
+  auto inverse_pair = [&](int g, int r, cx<T> (&v)[1][8]) {
+    const cx<T>* ba = st + ((2 * g) * 2 + r) * G::XT * kTile;
+    inverse_line(ba, ba + 2 * G::XT * kTile, v);
   };
 
   cx<T>* outz = out + (size_t)z * G::XT * N * kTile;
@@ -124,6 +144,18 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
   // waits to be paired with pz of the second.
   T pz0[8];
   double um = 0.0;  // largest |u_c| seen (only when umax is requested)
+  // buoyancy of both rows (b(y0) + i b(y1)) and the first row's fz
+  T bq[2][8], fz0[8];
+  if constexpr (STRAT) {
+    cx<T> v[1][8];
+    const cx<T>* ba = st + 6 * 2 * G::XT * kTile;
+    inverse_line(ba, ba + G::XT * kTile, v);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      bq[0][e] = v[0][e].re * scale;
+      bq[1][e] = v[0][e].im * scale;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 2; r++) {
     T ux[8], uy[8], uz[8], qy[8], qz[8];
@@ -143,6 +175,20 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
       const T wx = v[0][e].im;
       qy[e] = uz[e] * wx;   // py = uz wx - ux wz
       qz[e] = -uy[e] * wx;  // pz = ux wy - uy wx
+    }
+    if constexpr (STRAT) {
+      // buoyancy flux u b (b carries the scale): (fx + i fy) now, fz paired
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        v[0][e] = {ux[e] * bq[r][e], uy[e] * bq[r][e]};
+        if (r == 0) fz0[e] = uz[e] * bq[0][e];
+      }
+      forward_store(v, 3, y0 + r, 4, y0 + r);
+      if (r == 1) {
+#pragma unroll
+        for (int e = 0; e < 8; e++) v[0][e] = {fz0[e], uz[e] * bq[1][e]};
+        forward_store(v, 5, y0, 5, y0 + 1);
+      }
     }
     inverse_pair(2, r, v);
 #pragma unroll
@@ -170,9 +216,11 @@ __global__ void __launch_bounds__((RowPairs<N>::THREADS))
 // transforms of the other; double precision keeps the register budget.
 template <typename T, int N>
 using ZCfg = Strided<T, N, cmin(kTile, cmax(1, 512 / (N / 8)))>;
-template <typename T>
+// linear propagator of a fused z pass
+enum LinearProp : int { kPropVisc = 0, kPropRot = 1, kPropStrat = 2 };
+template <typename T, int PROP = kPropVisc>
 constexpr int zpass_waves() {
-  return sizeof(T) == 4 ? 4 : 1;
+  return sizeof(T) == 4 ? (PROP == kPropStrat ? 2 : 4) : 1;
 }
 // twiddle table of a z pass: the LDS copy `twl` (filled by the block) in single
 // precision, the global table otherwise
@@ -190,10 +238,11 @@ __device__ __forceinline__ const cx<T>* zpass_twiddles(const cx<T>* __restrict__
 // ---------------------------------------------------------------------------
 // Inverse z transforms of the six fields (u, w = i k x v) of a stage input v
 // held in registers as v[c][e] at z-position t + e*P of line b; writes
-// Wm[6][N][XT][M][16] (fields ordered ux uy uz wx wy wz).
+// Wm[6][N][XT][M][16] (fields ordered ux uy uz wx wy wz).  NC = 4 adds the
+// buoyancy v[3] as field 6.
 // ---------------------------------------------------------------------------
-template <typename T, int N, class TW>
-__device__ __forceinline__ void z_inverse_six(cx<T> (&v)[3][8], int t, int b, int jy, int xt,
+template <typename T, int N, int NC, class TW>
+__device__ __forceinline__ void z_inverse_six(cx<T> (&v)[NC][8], int t, int b, int jy, int xt,
                                               int sub, int mx, int my, T kb,
                                               cx<T>* __restrict__ w1, cx<T>* lds,
                                               const TW& tw) {
@@ -225,12 +274,12 @@ __device__ __forceinline__ void z_inverse_six(cx<T> (&v)[3][8], int t, int b, in
     for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = w[0][e];
   }
 #pragma unroll
-  for (int c = 0; c < 3; c++) {
+  for (int c = 0; c < NC; c++) {
     cx<T> w[1][8];
 #pragma unroll
     for (int e = 0; e < 8; e++) w[0][e] = v[c][e];
     fft_lines<T, N, +1, 1>(w, t, lds, lidx, tw);
-    cx<T>* dst = dst0 + c * fstride;
+    cx<T>* dst = dst0 + (c < 3 ? c : 6) * fstride;
 #pragma unroll
     for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = w[0][e];
   }
@@ -266,10 +315,11 @@ __device__ __forceinline__ T recip(T x) {
 
 // ---------------------------------------------------------------------------
 // First inverse pass of a stage, from the caller's state (ABI layout
-// [3][N][N][N/2+1]): masks to the kept set, records the band values, and
-// writes the six inverse-z-transformed fields.  Grid: M * XT * SUB.
+// [NC][N][N][N/2+1]): masks to the kept set, records the band values, and
+// writes the six (NC = 4: seven) inverse-z-transformed fields.
+// Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, int NC = 3>
 __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
     k3_p1(const cx<T>* __restrict__ state, cx<T>* __restrict__ w1, StageArgs<T> a) {
   using G = Geo<N, false>;
@@ -288,14 +338,14 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   const bool col = mx < G::H;
   const int m2xy = band_column(a, mx, my);
   const size_t cstride = (size_t)N * N * NH;
-  cx<T> v[3][8];
+  cx<T> v[NC][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int iz = t + e * P;
     const bool kept = col && G::i2j(iz) >= 0;
     const size_t o = ((size_t)iz * N + iy) * NH + mx;
 #pragma unroll
-    for (int c = 0; c < 3; c++) v[c][e] = kept ? state[c * cstride + o] : cx<T>{0, 0};
+    for (int c = 0; c < NC; c++) v[c][e] = kept ? state[c * cstride + o] : cx<T>{0, 0};
     if (kept) {
       const int mz = iz <= N / 2 ? iz : iz - N;
       if (in_band(a, m2xy, mz)) {
@@ -306,22 +356,27 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
       }
     }
   }
-  z_inverse_six<T, N>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
+  z_inverse_six<T, N, NC>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
 }
 
 // ---------------------------------------------------------------------------
 // Z pass: forward z transforms of the stage's products (Wm[3][N][XT][M][16]),
 // projection + forcing -> tendency of this stage, Lawson RK4 combine, and
 // (do_p1) the next stage's six inverse z transforms into w1.
-// MODE kModeTend writes the tendency to a.tend instead.  Grid: M * XT * SUB.
+// MODE kModeTend writes the tendency to a.tend instead.  PROP selects the
+// linear propagator of the combine: viscosity, + rotation (about z), or
+// + buoyancy force and stratification (kPropStrat: products Wm[6], the
+// flux u b giving the buoyancy tendency -i k.(u b)^, four state components,
+// seven inverse transforms).  Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int MODE, bool ROT = false>
-__global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
+template <typename T, int N, int MODE, int PROP = kPropVisc>
+__global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()))
     k3_z(const cx<T>* __restrict__ w4, cx<T>* __restrict__ w1, StageArgs<T> a, int do_p1) {
   using G = Geo<N, false>;
   using C = ZCfg<T, N>;
   constexpr int P = G::P;
   constexpr int NH = N / 2 + 1;
+  constexpr int NC = PROP == kPropStrat ? 4 : 3;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
   __shared__ cx<T> twl[sizeof(T) == 4 ? N : 1];
@@ -339,7 +394,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
   const size_t zstride = (size_t)G::XT * G::M * kTile;
   const cx<T>* src0 = w4 + (size_t)xt * G::M * kTile + (size_t)jy * kTile + sub * C::LB + b;
   // all three components' loads are issued before the first transform
-  cx<T> v[3][8];
+  cx<T> v[NC][8];
 #pragma unroll
   for (int c = 0; c < 3; c++)
 #pragma unroll
@@ -347,13 +402,31 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
 #pragma unroll
   for (int c = 0; c < 3; c++)
     fft_lines<T, N, -1, 1>(reinterpret_cast<cx<T>(&)[1][8]>(v[c]), t, lds, lidx, twr);
+  const T kx = a.kb * (T)mx, ky = a.kb * (T)my;
+  if constexpr (PROP == kPropStrat) {
+    // buoyancy tendency -i k.(u b)^, one flux component at a time
+#pragma unroll
+    for (int e = 0; e < 8; e++) v[3][e] = {0, 0};
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      cx<T> f[1][8];
+#pragma unroll
+      for (int e = 0; e < 8; e++) f[0][e] = src0[(3 + c) * fstride + (size_t)(t + e * P) * zstride];
+      fft_lines<T, N, -1, 1>(f, t, lds, lidx, twr);
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        const int iz = t + e * P;
+        const T kc = c == 0 ? kx : (c == 1 ? ky : a.kb * (T)(iz <= N / 2 ? iz : iz - N));
+        v[3][e] = v[3][e] - mul_i(cscale(f[0][e], kc));
+      }
+    }
+  }
 
   const size_t cstride = (size_t)N * N * NH;
   const size_t acstride = (size_t)G::XT * G::M * G::M * kTile;
   const int bn = (2 * a.bw + 1) * (2 * a.bw + 1) * (a.bw + 1);
   const T alpha = a.m2max >= 0 ? a.alpha[0] : (T)0;
   const T dt = stage_dt(a);
-  const T kx = a.kb * (T)mx, ky = a.kb * (T)my;
   const int m2xy = band_column(a, mx, my);
 #pragma unroll
   for (int e = 0; e < 8; e++) {
@@ -362,21 +435,23 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
     const bool kept = col && jz >= 0;
     if (!kept) {
 #pragma unroll
-      for (int c = 0; c < 3; c++) v[c][e] = {0, 0};
+      for (int c = 0; c < NC; c++) v[c][e] = {0, 0};
       continue;
     }
     const int mz = iz <= N / 2 ? iz : iz - N;
     const T kz = a.kb * (T)mz;
     const T k2 = kx * kx + ky * ky + kz * kz;
-    cx<T> nl[3];
+    cx<T> nl[NC];
     if (k2 > (T)0) {
       const T ik2 = recip(k2);
       const cx<T> kp = cscale(cscale(v[0][e], kx) + cscale(v[1][e], ky) + cscale(v[2][e], kz), ik2);
       nl[0] = v[0][e] - cscale(kp, kx);
       nl[1] = v[1][e] - cscale(kp, ky);
       nl[2] = v[2][e] - cscale(kp, kz);
+      if constexpr (NC == 4) nl[3] = v[3][e];
     } else {
-      nl[0] = nl[1] = nl[2] = {0, 0};
+#pragma unroll
+      for (int c = 0; c < NC; c++) nl[c] = {0, 0};
     }
     const bool band = in_band(a, m2xy, mz);
     const int bi = band ? band_index<T>(mx, my, mz, a.bw) : 0;
@@ -387,34 +462,39 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
     const size_t so = ((size_t)iz * N + iy) * NH + mx;
     if constexpr (MODE == kModeTend) {
 #pragma unroll
-      for (int c = 0; c < 3; c++) a.tend[c * cstride + so] = nl[c];
+      for (int c = 0; c < NC; c++) a.tend[c * cstride + so] = nl[c];
     } else {
       const T E = a.e1[mx] * a.e1[iy] * a.e1[iz];
       const T Eh = a.eh1[mx] * a.eh1[iy] * a.eh1[iz];
       const size_t ao = (((size_t)xt * G::M + jy) * G::M + jz) * kTile + sub * C::LB + b;
-      if constexpr (ROT) {
-        // rotating frame: the combination acts on the mode's 3-vectors
-        cx<T> u[3], acc[3], nxt[3];
+      if constexpr (PROP != kPropVisc) {
+        // the combination acts on the mode's NC-vectors
+        cx<T> u[NC], acc[NC], nxt[NC];
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
+        for (int c = 0; c < NC; c++) {
           u[c] = acc[c] = cx<T>{0, 0};
           if constexpr (mode_reads_state(MODE)) u[c] = a.state[c * cstride + so];
           if constexpr (mode_reads_acc(MODE)) acc[c] = a.acc[c * acstride + ao];
         }
-        RotProp<T> R;
-        const T kn = sqrt(k2);
-        const T ikn = k2 > (T)0 ? (T)1 / kn : (T)0;
-        R.kh[0] = kx * ikn;
-        R.kh[1] = ky * ikn;
-        R.kh[2] = kz * ikn;
-        const T sg = a.rotf * kz * ikn;
-        R.s1 = sin(sg * dt);
-        R.c1 = cos(sg * dt);
-        R.s2 = sin(sg * dt * (T)0.5);
-        R.c2 = cos(sg * dt * (T)0.5);
-        rot_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+        if constexpr (PROP == kPropRot) {
+          RotProp<T> R;
+          const T ikn = k2 > (T)0 ? (T)1 / sqrt(k2) : (T)0;
+          R.kh[0] = kx * ikn;
+          R.kh[1] = ky * ikn;
+          R.kh[2] = kz * ikn;
+          const T sg = a.rotf * kz * ikn;
+          R.s1 = sin(sg * dt);
+          R.c1 = cos(sg * dt);
+          R.s2 = sin(sg * dt * (T)0.5);
+          R.c2 = cos(sg * dt * (T)0.5);
+          prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+        } else {
+          StratProp<T> R;
+          R.set(kx, ky, kz, a.n2, dt);
+          prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+        }
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
+        for (int c = 0; c < NC; c++) {
           if constexpr (mode_writes_state(MODE)) a.state[c * cstride + so] = nxt[c];
           if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc[c];
           v[c][e] = nxt[c];
@@ -439,7 +519,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T>()))
     }
   }
   if constexpr (MODE != kModeTend) {
-    if (do_p1) z_inverse_six<T, N>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
+    if (do_p1) z_inverse_six<T, N, NC>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
   }
 }
 

@@ -56,11 +56,12 @@ struct Strided {
 // Lines per block of the y passes.
 constexpr int kYLines = kTile;
 
-// Row pairs per block of an x pass (a row pair is owned by P lanes).
-template <int N>
+// Row pairs per block of an x pass (a row pair is owned by P lanes; at most
+// LANES lanes per block unless one row pair needs more).
+template <int N, int LANES = 64>
 struct RowPairs {
   static constexpr int P = N / 8;
-  static constexpr int RP = cmax(1, cmin(64 / P, N / 2));
+  static constexpr int RP = cmax(1, cmin(LANES / P, N / 2));
   static constexpr int THREADS = RP * P;
   static constexpr int NPAD = N + N / 8;  // LDS line stride, +1 slot per 8
   __host__ __device__ static constexpr int pad(int pos) { return pos + (pos >> 3); }
@@ -98,7 +99,7 @@ struct StageArgs {
   T dt;                // step (used when dtp is null)
   const T* dtp;        // device step of the current step (adaptive steps), or null
   cx<T>* sin;          // 2D Boussinesq: stage input [2][XT][M][16] (else null)
-  T n2;                // 2D Boussinesq: squared buoyancy frequency
+  T n2;                // Boussinesq: squared buoyancy frequency
   T rotf;              // 3D rotating frame: Coriolis parameter f (z axis)
   int bw;              // half width of the forcing-band cube (modes)
   int m2min, m2max;    // band: m2min <= |m|^2 <= m2max; m2max < 0 => off
@@ -161,14 +162,17 @@ __device__ __forceinline__ cx<T> rk4_combine(cx<T> u, cx<T>& a, cx<T> nl, T E, T
   }
 }
 
-// The same stage combinations in a frame rotating about z: the linear
-// propagator of viscosity and Coriolis force on solenoidal fields is
-//   E(t) w = exp(-nu k^2 t) (cos(sigma t) w - sin(sigma t) khat x w),
-// sigma = f kz / |k|, applied to the 3-vectors of one mode (E, Eh carry the
-// viscous factors; c1, s1 / c2, s2 the cosines and sines of sigma dt and
-// sigma dt / 2).
+// Exact linear propagators of one mode, for the Lawson stage combinations
+// below; apply(w, d, half, o) sets o = E(t) w with t = dt (half: dt / 2) and d
+// the viscous factor exp(-nu k^2 t).
+//
+// Frame rotating about z: on solenoidal fields the Coriolis force is
+// -sigma khat x w, sigma = f kz / |k|, so
+//   E(t) w = exp(-nu k^2 t) (cos(sigma t) w - sin(sigma t) khat x w)
+// (c1, s1 / c2, s2: cosine and sine of sigma dt and sigma dt / 2).
 template <typename T>
 struct RotProp {
+  static constexpr int NC = 3;
   T kh[3];
   T c1, s1, c2, s2;
   __device__ __forceinline__ void apply(const cx<T> (&w)[3], T d, bool half, cx<T> (&o)[3]) const {
@@ -181,45 +185,94 @@ struct RotProp {
   }
 };
 
-template <int MODE, typename T>
-__device__ __forceinline__ void rot_combine(const cx<T> (&u)[3], cx<T> (&a)[3],
-                                            const cx<T> (&nl)[3], T E, T Eh, T dt,
-                                            const RotProp<T>& R, cx<T> (&next)[3]) {
+// Stratified (Boussinesq) flow, w = (u, b): the buoyancy force projects to
+// b q with q = z - khat khat_z, and a = uz, b oscillate at
+// sigma = N |k_h| / |k| (g2 = |k_h|^2 / |k|^2):
+//   E(t) (u, b) = exp(-nu k^2 t) (u + [(c - 1) a / g2 + S b] q,  c b - N^2 S a)
+// with c = cos(sigma t), S = sin(sigma t) / sigma (t when sigma = 0); cm1 is
+// c - 1, computed as -2 sin^2(sigma t / 2).  ig2 = 1 / g2 (0 when k_h = 0,
+// where q = 0).
+template <typename T>
+struct StratProp {
+  static constexpr int NC = 4;
+  T q[3];
+  T ig2, n2;
+  T cm1f, sf, cm1h, sh;  // full step, half step
+  __device__ __forceinline__ void set(T kx, T ky, T kz, T N2, T dt) {
+    const T kh2 = kx * kx + ky * ky, k2 = kh2 + kz * kz;
+    const T ik2 = k2 > (T)0 ? (T)1 / k2 : (T)0;
+    const T g2 = kh2 * ik2;
+    q[0] = -kx * kz * ik2;
+    q[1] = -ky * kz * ik2;
+    q[2] = g2;
+    ig2 = g2 > (T)0 ? (T)1 / g2 : (T)0;
+    n2 = N2;
+    const T sg = sqrt(N2 * g2);
+    // sines and cosines of sigma dt / 4 give both steps by double angles
+    const T s4 = sin(sg * dt * (T)0.25), c4 = cos(sg * dt * (T)0.25);
+    const T s2 = (T)2 * s4 * c4, c2 = (T)1 - (T)2 * s4 * s4;  // of sigma dt / 2
+    cm1h = (T)-2 * s4 * s4;
+    cm1f = (T)-2 * s2 * s2;
+    if (sg > (T)0) {
+      const T isg = (T)1 / sg;
+      sh = s2 * isg;
+      sf = (T)2 * s2 * c2 * isg;
+    } else {
+      sh = dt * (T)0.5;
+      sf = dt;
+    }
+  }
+  __device__ __forceinline__ void apply(const cx<T> (&w)[4], T d, bool half, cx<T> (&o)[4]) const {
+    const T cm1 = half ? cm1h : cm1f, S = half ? sh : sf;
+    const cx<T> coef = cscale(w[2], cm1 * ig2) + cscale(w[3], S);
+#pragma unroll
+    for (int c = 0; c < 3; c++) o[c] = cscale(w[c] + cscale(coef, q[c]), d);
+    o[3] = cscale(cscale(w[3], (T)1 + cm1) - cscale(w[2], n2 * S), d);
+  }
+};
+
+// The Lawson stage combinations of rk4_combine with a propagator acting on
+// the NC components of one mode.
+template <int MODE, class Prop, typename T, int NC>
+__device__ __forceinline__ void prop_combine(const cx<T> (&u)[NC], cx<T> (&a)[NC],
+                                             const cx<T> (&nl)[NC], T E, T Eh, T dt,
+                                             const Prop& R, cx<T> (&next)[NC]) {
+  static_assert(Prop::NC == NC, "propagator and mode vector differ in size");
   const T d2 = dt * (T)0.5, d3 = dt / (T)3, d6 = dt / (T)6;
-  cx<T> w[3], o[3];
+  cx<T> w[NC], o[NC];
   if constexpr (MODE == kStage1) {
 #pragma unroll
-    for (int q = 0; q < 3; q++) w[q] = u[q] + cscale(nl[q], d6);
+    for (int q = 0; q < NC; q++) w[q] = u[q] + cscale(nl[q], d6);
     R.apply(w, E, false, a);
 #pragma unroll
-    for (int q = 0; q < 3; q++) w[q] = u[q] + cscale(nl[q], d2);
+    for (int q = 0; q < NC; q++) w[q] = u[q] + cscale(nl[q], d2);
     R.apply(w, Eh, true, next);
   } else if constexpr (MODE == kStage2) {
     R.apply(nl, Eh, true, o);
 #pragma unroll
-    for (int q = 0; q < 3; q++) a[q] = a[q] + cscale(o[q], d3);
+    for (int q = 0; q < NC; q++) a[q] = a[q] + cscale(o[q], d3);
     R.apply(u, Eh, true, o);
 #pragma unroll
-    for (int q = 0; q < 3; q++) next[q] = o[q] + cscale(nl[q], d2);
+    for (int q = 0; q < NC; q++) next[q] = o[q] + cscale(nl[q], d2);
   } else if constexpr (MODE == kStage3) {
     R.apply(nl, Eh, true, o);
 #pragma unroll
-    for (int q = 0; q < 3; q++) a[q] = a[q] + cscale(o[q], d3);
+    for (int q = 0; q < NC; q++) a[q] = a[q] + cscale(o[q], d3);
     R.apply(u, E, false, w);
 #pragma unroll
-    for (int q = 0; q < 3; q++) next[q] = w[q] + cscale(o[q], dt);
+    for (int q = 0; q < NC; q++) next[q] = w[q] + cscale(o[q], dt);
   } else if constexpr (MODE == kStage4) {
 #pragma unroll
-    for (int q = 0; q < 3; q++) next[q] = a[q] + cscale(nl[q], d6);
+    for (int q = 0; q < NC; q++) next[q] = a[q] + cscale(nl[q], d6);
   } else if constexpr (MODE == kRk2a) {
 #pragma unroll
-    for (int q = 0; q < 3; q++) w[q] = u[q] + cscale(nl[q], d2);
+    for (int q = 0; q < NC; q++) w[q] = u[q] + cscale(nl[q], d2);
     R.apply(w, Eh, true, next);
   } else {
     R.apply(nl, Eh, true, o);
     R.apply(u, E, false, w);
 #pragma unroll
-    for (int q = 0; q < 3; q++) next[q] = w[q] + cscale(o[q], dt);
+    for (int q = 0; q < NC; q++) next[q] = w[q] + cscale(o[q], dt);
   }
 }
 

@@ -1,4 +1,5 @@
 // ops3d.hip -- launch sequences of the 3D solver for every supported size.
+#include <algorithm>
 #include <cmath>
 
 #include "fs_internal.h"
@@ -22,7 +23,7 @@ StageArgs<T> stage_args(Plan* p, void* state, void* tend) {
   a.dt = (T)p->dt;
   a.dtp = (const T*)p->dtdev;
   a.sin = nullptr;
-  a.n2 = (T)0;
+  a.n2 = (T)p->n2;
   a.rotf = (T)p->rotf;
   a.bw = p->bw;
   a.m2min = p->m2min;
@@ -30,8 +31,12 @@ StageArgs<T> stage_args(Plan* p, void* state, void* tend) {
   return a;
 }
 
-template <typename T, int N>
+// STRAT: Boussinesq flow (state u, b; seven inverse and six forward fields)
+template <typename T, int N, bool STRAT>
 struct L3 {
+  static constexpr int NC = STRAT ? 4 : 3;    // state components
+  static constexpr int FINV = STRAT ? 7 : 6;  // fields of the inverse passes
+  static constexpr int FFWD = STRAT ? 6 : 3;  // fields of the forward passes
   using G = Geo<N, false>;
   using GF = Geo<N, true>;
   using C = Strided<T, N>;
@@ -44,7 +49,7 @@ struct L3 {
 
   static void p1(Plan* p, const void* state) {
     p->begin(KID_P1);
-    hipLaunchKernelGGL((k3_p1<T, N>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)), dim3(ZC::THREADS), 0,
+    hipLaunchKernelGGL((k3_p1<T, N, NC>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)), dim3(ZC::THREADS), 0,
                        p->launch, (const cx<T>*)state, A(p),
                        stage_args<T>(p, (void*)state, nullptr));
     launched(p, "k3_p1");
@@ -52,14 +57,15 @@ struct L3 {
   }
   static void yinv(Plan* p) {
     p->begin(KID_YINV);
-    hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(xcd_grid(6 * N, G::XT * YC::SUB)),
-                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), 6 * N);
+    hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(xcd_grid(FINV * N, G::XT * YC::SUB)),
+                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), FINV * N);
     launched(p, "k_y_inv");
     p->end(KID_YINV);
   }
   static void x(Plan* p, bool umax = false) {
     p->begin(KID_X);
-    hipLaunchKernelGGL((k3_x<T, N>), dim3(N / 2 / R::RP, N), dim3(R::THREADS), 0, p->launch,
+    using XR = XRows<T, N, STRAT>;
+    hipLaunchKernelGGL((k3_x<T, N, STRAT>), dim3(N / 2 / XR::RP, N), dim3(XR::THREADS), 0, p->launch,
                        (const cx<T>*)B(p), A(p), TW(p), (T)(1.0 / ((double)N * N * N)),
                        umax ? p->umaxdev : nullptr);
     launched(p, "k3_x");
@@ -67,22 +73,24 @@ struct L3 {
   }
   static void yfwd(Plan* p) {
     p->begin(KID_YFWD);
-    hipLaunchKernelGGL((k_y_fwd<T, N, false>), dim3(xcd_grid(3 * N, G::XT * YC::SUB)),
-                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), 3 * N);
+    hipLaunchKernelGGL((k_y_fwd<T, N, false>), dim3(xcd_grid(FFWD * N, G::XT * YC::SUB)),
+                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), FFWD * N);
     launched(p, "k_y_fwd");
     p->end(KID_YFWD);
   }
   template <int MODE>
   static void zk(Plan* p, void* state, void* tend, int do_p1) {
     p->begin(KID_Z);
-    if (MODE != kModeTend && p->rotf != 0.0)
-      hipLaunchKernelGGL((k3_z<T, N, MODE, true>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)),
-                         dim3(ZC::THREADS), 0, p->launch, (const cx<T>*)B(p), A(p),
-                         stage_args<T>(p, state, tend), do_p1);
+    const dim3 grid(xcd_grid(G::M, G::XT * ZC::SUB));
+    if constexpr (STRAT)
+      hipLaunchKernelGGL((k3_z<T, N, MODE, kPropStrat>), grid, dim3(ZC::THREADS), 0, p->launch,
+                         (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend), do_p1);
+    else if (MODE != kModeTend && p->rotf != 0.0)
+      hipLaunchKernelGGL((k3_z<T, N, MODE, kPropRot>), grid, dim3(ZC::THREADS), 0, p->launch,
+                         (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend), do_p1);
     else
-      hipLaunchKernelGGL((k3_z<T, N, MODE>), dim3(xcd_grid(G::M, G::XT * ZC::SUB)),
-                         dim3(ZC::THREADS), 0, p->launch, (const cx<T>*)B(p), A(p),
-                         stage_args<T>(p, state, tend), do_p1);
+      hipLaunchKernelGGL((k3_z<T, N, MODE>), grid, dim3(ZC::THREADS), 0, p->launch,
+                         (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend), do_p1);
     launched(p, "k3_z");
     p->end(KID_Z);
   }
@@ -102,7 +110,7 @@ struct L3 {
     }
   }
   static void tendency(Plan* p, const void* state, void* out, bool fresh_alpha) {
-    launch_fill<T>(p, out, (size_t)3 * N * N * (N / 2 + 1));
+    launch_fill<T>(p, out, (size_t)NC * N * N * (N / 2 + 1));
     if (p->m2max >= 0 && fresh_alpha) launch_alpha<T>(p, state);
     p1(p, state);
     yinv(p);
@@ -168,12 +176,13 @@ struct L3 {
     o.diag = launch_diag<T>;
     o.transfer = launch_transfer<T>;
     o.spectra1d = launch_spectra1d<T>;
-    const size_t wm6 = (size_t)6 * N * G::XT * G::M * kTile;
-    const size_t wn6 = (size_t)6 * N * G::XT * N * kTile;
+    // A: z-pass output Wm[FINV], later the x-pass output Wn[FFWD];
+    // B: y-inverse output Wn[FINV], later the y-forward output Wm[FFWD]
+    const size_t wm = (size_t)N * G::XT * G::M * kTile, wn = (size_t)N * G::XT * N * kTile;
     const size_t wfull = (size_t)N * GF::XT * N * kTile;
-    o.elems_a = wm6 > wfull ? wm6 : wfull;
-    o.elems_b = wn6 > wfull ? wn6 : wfull;
-    o.elems_acc = (size_t)3 * G::XT * G::M * G::M * kTile;
+    o.elems_a = std::max({FINV * wm, FFWD * wn, wfull});
+    o.elems_b = std::max({FINV * wn, FFWD * wm, wfull});
+    o.elems_acc = (size_t)NC * G::XT * G::M * G::M * kTile;
     o.elems_full = wfull;
     return o;
   }
@@ -181,21 +190,26 @@ struct L3 {
 
 }  // namespace
 
-template <typename T>
-Ops make_ops3(int n) {
+template <typename T, bool STRAT>
+Ops ops3_of(int n) {
   switch (n) {
-    case 16: return L3<T, 16>::ops();
-    case 32: return L3<T, 32>::ops();
-    case 64: return L3<T, 64>::ops();
-    case 128: return L3<T, 128>::ops();
-    case 256: return L3<T, 256>::ops();
-    case 512: return L3<T, 512>::ops();
-    case 1024: return L3<T, 1024>::ops();
+    case 16: return L3<T, 16, STRAT>::ops();
+    case 32: return L3<T, 32, STRAT>::ops();
+    case 64: return L3<T, 64, STRAT>::ops();
+    case 128: return L3<T, 128, STRAT>::ops();
+    case 256: return L3<T, 256, STRAT>::ops();
+    case 512: return L3<T, 512, STRAT>::ops();
+    case 1024: return L3<T, 1024, STRAT>::ops();
     default: return Ops{};
   }
 }
 
-template Ops make_ops3<float>(int);
-template Ops make_ops3<double>(int);
+template <typename T>
+Ops make_ops3(int n, int nfield) {
+  return nfield == 4 ? ops3_of<T, true>(n) : ops3_of<T, false>(n);
+}
+
+template Ops make_ops3<float>(int, int);
+template Ops make_ops3<double>(int, int);
 
 }  // namespace fs

@@ -117,7 +117,7 @@ class Plan:
                    (FS_BOUSSINESQ if boussinesq else 0))
         o.n2 = float(n2)
         o.rotation = float(rotation)
-        self.nfield = 2 if boussinesq else 1
+        self.nfield = (3 if self.ndim == 3 else 1) + (1 if boussinesq else 0)
         o.scheme = {"rk4": FS_SCHEME_RK4, "rk2": FS_SCHEME_RK2}[scheme]
         o.cfl = float(cfl)
         h = _vp()
@@ -130,7 +130,7 @@ class Plan:
     def state_shape(self):
         n = self.n
         if self.ndim == 3:
-            return (3, n, n, n // 2 + 1)
+            return (self.nfield, n, n, n // 2 + 1)
         return (2, n, n // 2 + 1) if self.nfield == 2 else (n, n // 2 + 1)
 
     @property

@@ -75,7 +75,8 @@ def _create(lib, n, L, nu, dt, **kw):
     ((64, 6.28, 0.1, 0.01), {"scheme": -1}, -1),
     ((64, 6.28, 0.1, 0.01), {"cfl": -0.5}, -1),
     ((64, 6.28, 0.1, 0.01), {"cfl": float("nan")}, -1),
-    ((64, 6.28, 0.1, 0.01), {"flags": 0x8}, -2),
+    ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "rotation": 1.0}, -2),
+    ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "cfl": 0.5}, -2),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "ndim": 2, "n2": -1.0}, -1),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x10}, -1),
     ((64, 6.28, 0.1, 0.01), {"rotation": float("inf")}, -1),
