@@ -126,6 +126,7 @@ def lib():
         L.or_strat_propagate.argtypes = [i, d, d, d, d, vp, vp]
         L.or_tendency3d_strat.argtypes = [i, d, vp, d, d, d, vp]
         L.or_step3d_strat.argtypes = [i, d, d, d, d, d, d, d, i, vp, i]
+        L.or_structure.argtypes = [i, i, d, vp, i, vp, i, vp]
         L.or_step2d_strat.argtypes = [i, d, d, d, d, vp, i]
         L.or_spectra1d2d.argtypes = [i, d, vp, vp]
         L.or_transfer3d.argtypes = [i, d, vp, vp, i, vp, vp, vp]
@@ -293,6 +294,19 @@ def step3d_strat(s, nu, dt, N2, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_m
     lib().or_step3d_strat(a.shape[1], float(L), float(nu), float(dt), float(N2), float(power),
                           float(kf_min), float(kf_max), int(scheme), _p(a), int(nsteps))
     return a
+
+
+def structure(state, ndim, r, pmax, L=2 * np.pi):
+    """Longitudinal structure functions: (signed[nr][pmax], absolute[nr][pmax])
+    of the kept-mode velocity (2D: from the vorticity) for separations r (grid
+    spacings), averaged over grid points and axes."""
+    a = _c128(state)
+    n = a.shape[-2]
+    rr = np.ascontiguousarray(r, dtype=np.int32)
+    out = np.zeros(2 * len(rr) * pmax)
+    lib().or_structure(int(ndim), n, float(L), _p(a), len(rr), rr.ctypes.data, int(pmax), _p(out))
+    out = out.reshape(2, len(rr), pmax)
+    return out[0], out[1]
 
 
 def step3d_rot(uh, nu, dt, f, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0, scheme=4):

@@ -958,6 +958,62 @@ void or_spectra1d2d(int n, double L, const cplx *wh, double *out) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Longitudinal structure functions of the physical velocity (the output of  */
+/* velocity increments): du_a(x, r) = u_a(x + r e_a) - u_a(x) for a          */
+/* separation of r grid spacings along axis a (periodic), with u the         */
+/* velocity of the kept modes (2D: from the vorticity).  Averaged over every */
+/* grid point and the d axes:                                                */
+/*   out[j * pmax + p - 1]              = < du^p >                          */
+/*   out[(nr + j) * pmax + p - 1]       = < |du|^p >,   p = 1..pmax.         */
+/* ------------------------------------------------------------------------ */
+void or_structure(int ndim, int n, double L, const cplx *st, int nr, const int *r, int pmax,
+                  double *out) {
+  const int64_t h = n / 2 + 1, ns = (ndim == 3 ? (int64_t)n : 1) * n * h;
+  const int64_t np = (ndim == 3 ? (int64_t)n : 1) * n * n;
+  const double kb = 2.0 * M_PI / L;
+  cplx *g = malloc(sizeof(cplx) * ns);
+  double *u = malloc(sizeof(double) * np);
+  for (int i = 0; i < 2 * nr * pmax; i++) out[i] = 0.0;
+  for (int a = 0; a < ndim; a++) {
+    /* velocity component a of the kept modes */
+    for (int64_t i = 0; i < ns; i++) {
+      int mx = (int)(i % h), my = mode_full((int)((i / h) % n), n);
+      int mz = ndim == 3 ? mode_full((int)(i / (n * h)), n) : 0;
+      int keep = keep1(mx, n) && keep1(my, n) && keep1(mz, n);
+      cplx v = 0;
+      if (keep && ndim == 3) {
+        v = st[a * ns + i];
+      } else if (keep && (mx != 0 || my != 0)) {
+        double kx = kb * mx, ky = kb * my, k2 = kx * kx + ky * ky;
+        v = a == 0 ? I * ky * st[i] / k2 : -I * kx * st[i] / k2;
+      }
+      g[i] = v;
+    }
+    or_irfftn(ndim, n, g, u);
+    /* axis a has stride n^a in the physical layout (x fastest) */
+    const int64_t stride = a == 0 ? 1 : (a == 1 ? n : (int64_t)n * n);
+    for (int j = 0; j < nr; j++) {
+      double sp[8] = {0}, ap[8] = {0};
+      for (int64_t x = 0; x < np; x++) {
+        int64_t q = (x / stride) % n, q2 = (q + r[j]) % n;
+        double d = u[x + (q2 - q) * stride] - u[x], dp = 1.0;
+        for (int p = 0; p < pmax; p++) {
+          dp *= d;
+          sp[p] += dp;
+          ap[p] += fabs(dp);
+        }
+      }
+      for (int p = 0; p < pmax; p++) {
+        out[j * pmax + p] += sp[p] / ((double)np * ndim);
+        out[(nr + j) * pmax + p] += ap[p] / ((double)np * ndim);
+      }
+    }
+  }
+  free(g);
+  free(u);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Spectral energy budget: with E = 1/2 sum w |u_hat|^2 and du_hat/dt = N_hat  */
 /* (no viscosity), dE/dt = sum w Re(conj(u_hat) . N_hat); its shell sums are   */
 /* the transfer T(s), s = floor(|m| + 1/2) (bins >= nbins dropped from T       */
