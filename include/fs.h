@@ -221,6 +221,25 @@ fs_status fs_energy_spectrum(fs_plan *plan, const void *state, double *spectrum,
 fs_status fs_energy_spectra_1d(fs_plan *plan, const void *state, double *out);
 
 /*
+ * Longitudinal structure functions of the velocity (the statistics of
+ * velocity increments the paper's output object provides, section
+ * "Implementation and architecture"): with u the physical velocity of the
+ * kept modes (2D: from the vorticity) and du_a(x, r) = u_a(x + r e_a) -
+ * u_a(x) for r grid spacings along axis a (periodic), averaged over every
+ * grid point and the d axes,
+ *   out[j * pmax + p - 1]        = < du^p >      (signed moments)
+ *   out[(nr + j) * pmax + p - 1] = < |du|^p >    (absolute moments)
+ * for p = 1..pmax (1 <= pmax <= 8) and the nr separations r[j] (host array,
+ * 1 <= nr <= 64, 1 <= r[j] <= n-1).  out holds 2 * nr * pmax device doubles.
+ * Increments are formed in FP64 from the working-precision velocity and
+ * summed in FP64, deterministically.  Uses the plan's transform workspace as
+ * scratch (no other call may run on the plan concurrently); for
+ * FS_BOUSSINESQ states the velocity part is used.
+ */
+fs_status fs_structure_functions(fs_plan *plan, const void *state, int nr, const int *r, int pmax,
+                                 double *out);
+
+/*
  * Spectral energy budget of a tendency (the spectra of energy transfer the
  * paper's output object provides, section "Implementation and
  * architecture"): with tend = d state / dt (e.g. from fs_tendency; viscosity

@@ -1,6 +1,6 @@
 // diag.hip -- FP64 diagnostics (energy, enstrophy, shell spectrum; the
-// spectral energy transfer of a tendency), the constant-power forcing
-// coefficient and a fill kernel.
+// spectral energy transfer of a tendency; 1D spectra; structure functions),
+// the constant-power forcing coefficient and a fill kernel.
 //
 // All reductions are deterministic: every partial sum is formed in a fixed
 // order (per-lane accumulators, fixed shuffle trees, wave-private LDS bins,
@@ -360,6 +360,108 @@ __global__ void k_fill_zero(cx<T>* __restrict__ p, size_t n) {
     p[i] = cx<T>{0, 0};
 }
 
+// ---------------------------------------------------------------------------
+// Longitudinal structure functions.  k_vel_comp writes velocity component c
+// of the kept modes of a state (2D: from the vorticity) as one spectral field
+// [n..][n/2+1]; after its inverse transform, k_incr forms the increments
+// du = u(x + r e_c) - u(x) (differences of the stored values taken in FP64)
+// and per-lane FP64 sums of du^p and |du|^p, p = 1..pmax, over a contiguous
+// chunk of grid points (blockIdx.x) for separation j (blockIdx.y); a fixed
+// shuffle tree and the block's waves in order give one partial per block.
+// k_incr_final adds the partials over components and chunks in order.
+// ---------------------------------------------------------------------------
+constexpr int kSfChunks = 256;
+constexpr int kSfThreads = 256;
+struct SfSeps {
+  int r[kSfMaxR];
+};
+
+template <typename T>
+__global__ void k_vel_comp(const cx<T>* __restrict__ state, int ndim, int n, int K, T kb, int c,
+                           cx<T>* __restrict__ out) {
+  const int NH = n / 2 + 1;
+  const size_t ns = (size_t)(ndim == 3 ? n : 1) * n * NH;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < ns;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int mx = (int)(i % NH), my = dmode((int)((i / NH) % n), n);
+    const int mz = ndim == 3 ? dmode((int)(i / ((size_t)n * NH)), n) : 0;
+    const bool keep = mx <= K && abs(my) <= K && abs(mz) <= K;
+    cx<T> v = {0, 0};
+    if (keep && ndim == 3) {
+      v = state[c * ns + i];
+    } else if (keep && (mx != 0 || my != 0)) {
+      const T kx = kb * (T)mx, ky = kb * (T)my, k2 = kx * kx + ky * ky;
+      const cx<T> w = state[i];
+      // u = i ky w / k^2, v = -i kx w / k^2
+      v = c == 0 ? cx<T>{-ky * w.im / k2, ky * w.re / k2} : cx<T>{kx * w.im / k2, -kx * w.re / k2};
+    }
+    out[i] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSfThreads)
+    k_incr(const T* __restrict__ u, int n, int logn, int ndim, int axis, SfSeps sep, int nr,
+           int pmax, double* __restrict__ part) {
+  __shared__ double red[kSfThreads / 64][2 * kSfMaxP];
+  const long long np = (long long)n * n * (ndim == 3 ? n : 1);
+  const int j = blockIdx.y, r = sep.r[j];
+  const int ls = axis * logn;  // log2 of the axis stride
+  const long long per = (np + gridDim.x - 1) / gridDim.x;
+  const long long b0 = (long long)blockIdx.x * per;
+  const long long b1 = b0 + per < np ? b0 + per : np;
+  double sp[kSfMaxP], ap[kSfMaxP];
+#pragma unroll
+  for (int p = 0; p < kSfMaxP; p++) sp[p] = ap[p] = 0.0;
+  for (long long x = b0 + threadIdx.x; x < b1; x += kSfThreads) {
+    const int q = (int)((x >> ls) & (n - 1));
+    const int q2 = q + r < n ? q + r : q + r - n;
+    const double d = (double)u[x + ((long long)(q2 - q) << ls)] - (double)u[x];
+    double dp = 1.0;
+#pragma unroll
+    for (int p = 0; p < kSfMaxP; p++) {
+      if (p < pmax) {
+        dp *= d;
+        sp[p] += dp;
+        ap[p] += fabs(dp);
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < kSfMaxP; p++) {
+    for (int o = 32; o >= 1; o >>= 1) {
+      sp[p] += __shfl_xor(sp[p], o, 64);
+      ap[p] += __shfl_xor(ap[p], o, 64);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int p = 0; p < kSfMaxP; p++) {
+      red[wave][p] = sp[p];
+      red[wave][kSfMaxP + p] = ap[p];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kSfMaxP) {
+    double t = 0.0;
+    for (int w = 0; w < kSfThreads / 64; w++) t += red[w][threadIdx.x];
+    part[(((size_t)axis * nr + j) * gridDim.x + blockIdx.x) * 2 * kSfMaxP + threadIdx.x] = t;
+  }
+}
+
+__global__ void k_incr_final(const double* __restrict__ part, int ndim, int nr, int pmax,
+                             int chunks, double inv, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nr * pmax) return;
+  const int which = t / (nr * pmax), j = (t / pmax) % nr, p = t % pmax;
+  double s = 0.0;
+  for (int a = 0; a < ndim; a++)
+    for (int b = 0; b < chunks; b++)
+      s += part[(((size_t)a * nr + j) * chunks + b) * 2 * kSfMaxP + which * kSfMaxP + p];
+  out[t] = s * inv;
+}
+
 }  // namespace
 
 template <typename T>
@@ -440,6 +542,59 @@ void launch_spectra1d(Plan* p, const void* state, double* out) {
   p->end(KID_DIAG);
 }
 
+// Structure functions: component c of the velocity is written as a spectral
+// field, inverse transformed and its increments reduced, using the plan's
+// transform workspace (3D: spectral field at B + F, transform through A and B,
+// physical field at A + F; 2D: spectral field at A + F, physical field at A,
+// transform through B; F = one undealiased field).
+template <typename T>
+void launch_structure(Plan* p, const void* state, int nr, const int* r, int pmax, double* out) {
+  const int n = p->n, nd = p->ndim, K = (n - 1) / 3;
+  const size_t F = p->ops.elems_full;
+  const size_t ns = (size_t)(nd == 3 ? n : 1) * n * (n / 2 + 1);
+  const size_t nphys = (size_t)(nd == 3 ? n : 1) * n * n;
+  const size_t phys_c = (nphys * sizeof(T) + sizeof(cx<T>) - 1) / sizeof(cx<T>);
+  const bool fits = nd == 3 ? (F + phys_c <= p->ops.elems_a && F + ns <= p->ops.elems_b)
+                            : (F + ns <= p->ops.elems_a && phys_c <= F);
+  const size_t part_elems = (size_t)nd * nr * kSfChunks * 2 * kSfMaxP;
+  if (!fits || ns > F || part_elems > (size_t)kDiagMaxBlocks * (kDiagMaxBins + 2)) {
+    set_error("structure-function scratch exceeds the plan workspace");
+    p->failed = true;
+    return;
+  }
+  cx<T>* A = (cx<T>*)p->bufA;
+  cx<T>* B = (cx<T>*)p->bufB;
+  cx<T>* spec = nd == 3 ? B + F : A + F;
+  T* phys = nd == 3 ? (T*)(A + F) : (T*)A;
+  SfSeps sep{};
+  for (int j = 0; j < nr; j++) sep.r[j] = r[j];
+  int logn = 0;
+  while ((1 << logn) < n) logn++;
+  const int vb = (int)((ns + kDiagThreads - 1) / kDiagThreads);
+  for (int c = 0; c < nd; c++) {
+    p->begin(KID_DIAG);
+    hipLaunchKernelGGL((k_vel_comp<T>), dim3(vb < 4096 ? vb : 4096), dim3(kDiagThreads), 0,
+                       p->launch, (const cx<T>*)state, nd, n, K, (T)(2.0 * M_PI / p->L), c, spec);
+    launched(p, "k_vel_comp");
+    p->end(KID_DIAG);
+    if (nd == 3)
+      p->ops.fft_inv_n(p, spec, phys, 1, A, B);
+    else
+      p->ops.fft_inv(p, spec, phys);
+    p->begin(KID_DIAG);
+    hipLaunchKernelGGL((k_incr<T>), dim3(kSfChunks, nr), dim3(kSfThreads), 0, p->launch,
+                       (const T*)phys, n, logn, nd, c, sep, nr, pmax, p->dpart);
+    launched(p, "k_incr");
+    p->end(KID_DIAG);
+  }
+  p->begin(KID_DIAG);
+  hipLaunchKernelGGL(k_incr_final, dim3((2 * nr * pmax + 255) / 256), dim3(256), 0, p->launch,
+                     (const double*)p->dpart, nd, nr, pmax, kSfChunks,
+                     1.0 / ((double)nphys * nd), out);
+  launched(p, "k_incr_final");
+  p->end(KID_DIAG);
+}
+
 template <typename T>
 void launch_alpha(Plan* p, const void* state) {
   p->begin(KID_ALPHA);
@@ -488,6 +643,8 @@ template void launch_transfer<double>(Plan*, const void*, const void*, double*, 
                                       double*, double*);
 template void launch_spectra1d<float>(Plan*, const void*, double*);
 template void launch_spectra1d<double>(Plan*, const void*, double*);
+template void launch_structure<float>(Plan*, const void*, int, const int*, int, double*);
+template void launch_structure<double>(Plan*, const void*, int, const int*, int, double*);
 template void launch_alpha<float>(Plan*, const void*);
 template void launch_alpha<double>(Plan*, const void*);
 template void launch_dtstep<float>(Plan*);

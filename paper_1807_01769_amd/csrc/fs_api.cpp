@@ -445,6 +445,21 @@ fs_status fs_energy_spectra_1d(fs_plan* plan, const void* state, double* out) {
   return device_status(&plan->p);
 }
 
+fs_status fs_structure_functions(fs_plan* plan, const void* state, int nr, const int* r, int pmax,
+                                 double* out) {
+  if (fs_status s = usable(plan)) return s;
+  if (!state || !r || !out) return fail(FS_E_INVALID, "NULL array");
+  if (nr < 1 || nr > fs::kSfMaxR)
+    return fail(FS_E_INVALID, "nr = %d must be in 1..%d", nr, fs::kSfMaxR);
+  if (pmax < 1 || pmax > fs::kSfMaxP)
+    return fail(FS_E_INVALID, "pmax = %d must be in 1..%d", pmax, fs::kSfMaxP);
+  for (int j = 0; j < nr; j++)
+    if (r[j] < 1 || r[j] >= plan->p.n)
+      return fail(FS_E_INVALID, "r[%d] = %d must be in 1..n-1", j, r[j]);
+  plan->p.ops.structure(&plan->p, state, nr, r, pmax, out);
+  return device_status(&plan->p);
+}
+
 fs_status fs_energy_transfer(fs_plan* plan, const void* state, const void* tend, double* transfer,
                              double* flux, int nbins, double* energy_rate,
                              double* enstrophy_rate) {

@@ -53,6 +53,8 @@ struct Ops {
                double* enstrophy);
   // 1D spectra of the velocity components
   void (*spectra1d)(Plan*, const void* state, double* out);
+  // longitudinal structure functions of the velocity (r: host array)
+  void (*structure)(Plan*, const void* state, int nr, const int* r, int pmax, double* out);
   // spectral energy transfer of a tendency
   void (*transfer)(Plan*, const void* state, const void* tend, double* transfer, double* flux,
                    int nbins, double* energy_rate, double* enstrophy_rate);
@@ -127,6 +129,8 @@ void launch_diag(Plan* p, const void* state, double* spectrum, int nbins, double
 template <typename T>
 void launch_spectra1d(Plan* p, const void* state, double* out);
 template <typename T>
+void launch_structure(Plan* p, const void* state, int nr, const int* r, int pmax, double* out);
+template <typename T>
 void launch_transfer(Plan* p, const void* state, const void* tend, double* transfer,
                      double* flux, int nbins, double* energy_rate, double* enstrophy_rate);
 template <typename T>
@@ -153,6 +157,8 @@ int mlp_nparams();
 
 constexpr int kDiagThreads = 256;
 constexpr int kDiagMaxBins = 1024;
+constexpr int kSfMaxR = 64;  // separations per structure-function call
+constexpr int kSfMaxP = 8;   // highest moment
 constexpr int kDiagMaxBlocks = 1024;
 
 }  // namespace fs

@@ -1,4 +1,5 @@
 // ops2d.hip -- launch sequences of the 2D solver for every supported size.
+#include <algorithm>
 #include <cmath>
 
 #include "fs_internal.h"
@@ -122,10 +123,14 @@ struct L2 {
     o.dtstep = launch_dtstep<T>;
     o.transfer = launch_transfer<T>;
     o.spectra1d = launch_spectra1d<T>;
+    o.structure = launch_structure<T>;
     const size_t wn3 = (size_t)(2 + NF) * G::XT * N * kTile;  // (u, v, w[, b])
     const size_t wn2 = (size_t)2 * NF * G::XT * N * kTile;    // products
     const size_t wfull = (size_t)GF::XT * N * kTile;
-    o.elems_a = wn3 > wfull ? wn3 : wfull;
+    // diagnostics keep one spectral and one physical field in A
+    const size_t two = wfull + (size_t)N * (N / 2 + 1);
+    o.elems_a = std::max({wn3, wfull, two});
+    o.elems_full = wfull;
     o.elems_b = wn2 > wfull ? wn2 : wfull;
     o.elems_acc = (size_t)NF * G::XT * G::M * kTile;
     o.elems_sin = NF > 1 ? (size_t)NF * G::XT * G::M * kTile : 0;

@@ -176,11 +176,15 @@ struct L3 {
     o.diag = launch_diag<T>;
     o.transfer = launch_transfer<T>;
     o.spectra1d = launch_spectra1d<T>;
+    o.structure = launch_structure<T>;
     // A: z-pass output Wm[FINV], later the x-pass output Wn[FFWD];
-    // B: y-inverse output Wn[FINV], later the y-forward output Wm[FFWD]
+    // B: y-inverse output Wn[FINV], later the y-forward output Wm[FFWD].
+    // Diagnostics also keep one undealiased field plus one physical field
+    // (N^3 reals) in A.
     const size_t wm = (size_t)N * G::XT * G::M * kTile, wn = (size_t)N * G::XT * N * kTile;
     const size_t wfull = (size_t)N * GF::XT * N * kTile;
-    o.elems_a = std::max({FINV * wm, FFWD * wn, wfull});
+    const size_t phys = ((size_t)N * N * N * sizeof(T) + sizeof(cx<T>) - 1) / sizeof(cx<T>);
+    o.elems_a = std::max({FINV * wm, FFWD * wn, wfull + phys});
     o.elems_b = std::max({FINV * wn, FFWD * wm, wfull});
     o.elems_acc = (size_t)NC * G::XT * G::M * G::M * kTile;
     o.elems_full = wfull;

@@ -59,6 +59,7 @@ lib.fs_step_rk4.argtypes = [_vp, _vp, _i]
 lib.fs_energy_spectrum.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
 lib.fs_energy_transfer.argtypes = [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp]
 lib.fs_energy_spectra_1d.argtypes = [_vp, _vp, _vp]
+lib.fs_structure_functions.argtypes = [_vp, _vp, _i, _vp, _i, _vp]
 lib.fs_plan_time.argtypes = [_vp, _vp, _vp]
 lib.fs_profile_read.argtypes = [_vp, C.POINTER(_d), C.POINTER(C.c_long), C.POINTER(C.c_char_p), _i]
 lib.fs_status_str.argtypes = [_i]
@@ -68,7 +69,8 @@ lib.fs_last_error.restype = C.c_char_p
 for _f in ("fs_plan_create", "fs_plan_destroy", "fs_plan_set_stream", "fs_state_elems",
            "fs_workspace_bytes", "fs_spectrum_bins", "fs_fft_forward", "fs_fft_inverse",
            "fs_tendency", "fs_step_rk4", "fs_energy_spectrum", "fs_energy_transfer",
-           "fs_energy_spectra_1d", "fs_plan_time", "fs_profile_read"):
+           "fs_energy_spectra_1d", "fs_structure_functions", "fs_plan_time",
+           "fs_profile_read"):
     getattr(lib, _f).restype = _i
 
 
@@ -226,6 +228,17 @@ class Plan:
             self._h, self._arg(state, self.state_shape, self.complex_dtype, "state"),
             out.data_ptr()), "fs_energy_spectra_1d")
         return out
+
+    def structure_functions(self, state: torch.Tensor, r, pmax: int = 6):
+        """Longitudinal structure functions of the velocity for separations r
+        (grid spacings): device float64 (signed[nr][pmax], absolute[nr][pmax])
+        with signed[j][p-1] = <du^p> and absolute[j][p-1] = <|du|^p>."""
+        rr = (C.c_int * len(r))(*[int(x) for x in r])
+        out = torch.empty((2, len(r), int(pmax)), dtype=torch.float64, device=state.device)
+        _check(lib.fs_structure_functions(
+            self._h, self._arg(state, self.state_shape, self.complex_dtype, "state"), len(r),
+            C.cast(rr, _vp), int(pmax), out.data_ptr()), "fs_structure_functions")
+        return out[0], out[1]
 
     def energy_transfer(self, state: torch.Tensor, tend: torch.Tensor | None = None,
                         nbins: int | None = None):

@@ -97,6 +97,7 @@ def test_null_arguments(lib):
     for fn, nargs in [("fs_step_rk4", 3), ("fs_tendency", 3), ("fs_fft_forward", 3),
                       ("fs_fft_inverse", 3), ("fs_energy_spectrum", 6), ("fs_plan_set_stream", 2),
                       ("fs_energy_transfer", 8), ("fs_energy_spectra_1d", 3), ("fs_plan_time", 3),
+                      ("fs_structure_functions", 6),
                       ("fs_profile_read", 5)]:
         f = getattr(lib, fn)
         f.argtypes = [C.c_void_p] * nargs
