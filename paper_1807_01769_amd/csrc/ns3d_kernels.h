@@ -51,10 +51,10 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
   using R = XRows<T, N, STRAT>;
   constexpr int P = G::P;
   constexpr int FIN = STRAT ? 7 : 6;  // input fields
-  // staging: the row pair's kept coefficients, [field][row][xt][16] (tiles
-  // of one row 128 bytes apart, so 32 lanes reading consecutive kx of a row
-  // hit distinct LDS banks)
-  constexpr int SPAIR = FIN * G::XT * 2 * kTile;
+  // staging: kept coefficients [field][row][xt][16] of one row at a time
+  // (the stratified pass stages the pair: b of both rows forms one line)
+  constexpr int NRS = STRAT ? 2 : 1;
+  constexpr int SPAIR = FIN * G::XT * NRS * kTile;
   static_assert(STRAT == false || N > 512 || sizeof(T) == 4 ||
                     (size_t)R::RP * (SPAIR + R::NPAD) * sizeof(cx<T>) <= 65536,
                 "x-pass staging exceeds 64 KiB of LDS");
@@ -69,25 +69,26 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
   auto lidx = [=](int, int pos) { return R::pad(pos); };
   const size_t fstride = (size_t)N * G::XT * N * kTile;  // one field
 
-  // Phase 1: for each (field, tile) the two rows are 2*16 contiguous
-  // coefficients in memory; move them with 16-byte loads, all in flight.
-  {
-    constexpr int PER = 16 / (int)sizeof(cx<T>);        // coefficients per load
-    constexpr int LOADS = FIN * G::XT * 2 * kTile / PER;  // per row pair
+  // staging of rows y0 + r0 .. y0 + r0 + NRS - 1: for each (field, tile) the
+  // rows are NRS*16 contiguous coefficients; 16-byte loads, all in flight.
+  auto stage_rows = [&](int r0) {
+    constexpr int PER = 16 / (int)sizeof(cx<T>);          // coefficients per load
+    constexpr int LOADS = FIN * G::XT * NRS * kTile / PER;  // per stage
     const uint4* src4 = reinterpret_cast<const uint4*>(in);
     uint4* st4 = reinterpret_cast<uint4*>(st);
 #pragma unroll
     for (int i0 = 0; i0 < LOADS; i0 += P) {
       const int i = i0 + t;
       if (i < LOADS) {
-        const int c = i / (2 * kTile / PER), l = i % (2 * kTile / PER);
+        const int c = i / (NRS * kTile / PER), l = i % (NRS * kTile / PER);
         const int f = c / G::XT, xt = c % G::XT;
         const int r = l / (kTile / PER), lo = l % (kTile / PER);
-        const size_t g = ((((size_t)f * N + z) * G::XT + xt) * N + y0) * kTile;  // coefficient
-        st4[((f * 2 + r) * G::XT + xt) * (kTile / PER) + lo] = src4[g / PER + l];
+        const size_t g = ((((size_t)f * N + z) * G::XT + xt) * N + y0 + r0) * kTile;
+        st4[((f * NRS + r) * G::XT + xt) * (kTile / PER) + lo] = src4[g / PER + l];
       }
     }
-  }
+  };
+  stage_rows(0);
   __syncthreads();
 
   // Register e holds position k = t + e*P of the complex line a + i b; it
@@ -117,8 +118,8 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
   };
   // fields (2g, 2g+1) of row r
   auto inverse_pair = [&](int g, int r, cx<T> (&v)[1][8]) {
-    const cx<T>* ba = st + ((2 * g) * 2 + r) * G::XT * kTile;
-    inverse_line(ba, ba + 2 * G::XT * kTile, v);
+    const cx<T>* ba = st + ((2 * g) * NRS + (NRS == 2 ? r : 0)) * G::XT * kTile;
+    inverse_line(ba, ba + NRS * G::XT * kTile, v);
   };
 
   cx<T>* outz = out + (size_t)z * G::XT * N * kTile;
@@ -158,6 +159,11 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
   }
 #pragma unroll
   for (int r = 0; r < 2; r++) {
+    if (NRS == 1 && r == 1) {
+      // every read of row 0 ended before the last barrier of its stores
+      stage_rows(1);
+      __syncthreads();
+    }
     T ux[8], uy[8], uz[8], qy[8], qz[8];
     cx<T> v[1][8];
     inverse_pair(0, r, v);
