@@ -134,8 +134,8 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
       cx<T> A = {0, 0}, B = {0, 0};
       if (m < G::H) r2c_untangle(line[lidx(0, m)], line[lidx(0, (N - m) & (N - 1))], A, B);
       const size_t o = ((size_t)(m >> 4) * N) * kTile + (m & 15);
-      outz[fa * fstride + o + (size_t)ya * kTile] = A;
-      outz[fb * fstride + o + (size_t)yb * kTile] = B;
+      st_nt(&outz[fa * fstride + o + (size_t)ya * kTile], A);
+      st_nt(&outz[fb * fstride + o + (size_t)yb * kTile], B);
     }
     __syncthreads();
   };

@@ -23,6 +23,23 @@ namespace fs {
 
 constexpr int kTile = 16;
 
+// Streaming access to intermediates that are written once and read once by
+// the next pass (far larger than the caches): non-temporal loads and stores.
+template <typename T>
+__device__ __forceinline__ void st_nt(cx<T>* p, cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 x;
+  x.x = v.re;
+  x.y = v.im;
+  __builtin_nontemporal_store(x, reinterpret_cast<v2*>(p));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> ld_nt(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 x = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return cx<T>{x.x, x.y};
+}
+
 template <int N, bool FULL>
 struct Geo {
   static constexpr int K = FULL ? N / 2 : (N - 1) / 3;
@@ -306,12 +323,12 @@ __global__ void __launch_bounds__((Strided<T, N, kYLines>::THREADS))
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int j = G::i2j(t + e * G::P);
-    v[0][e] = j >= 0 ? src[j * kTile] : cx<T>{0, 0};
+    v[0][e] = j >= 0 ? ld_nt(&src[j * kTile]) : cx<T>{0, 0};
   }
   fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
   cx<T>* dst = out + tile * N * kTile + sub * C::LB + b;
 #pragma unroll
-  for (int e = 0; e < 8; e++) dst[(t + e * G::P) * kTile] = v[0][e];
+  for (int e = 0; e < 8; e++) st_nt(&dst[(t + e * G::P) * kTile], v[0][e]);
 }
 
 template <typename T, int N, bool FULL>
@@ -336,7 +353,7 @@ __global__ void __launch_bounds__((Strided<T, N, kYLines>::THREADS))
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int j = G::i2j(t + e * G::P);
-    if (j >= 0) dst[j * kTile] = v[0][e];
+    if (j >= 0) st_nt(&dst[j * kTile], v[0][e]);
   }
 }
 
