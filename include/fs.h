@@ -59,7 +59,7 @@ typedef enum {
   FS_E_UNSUPPORTED = -2, /* valid but not implemented (e.g. n not 2^k in 16..1024) */
   FS_E_NOMEM = -3,       /* device allocation failed at plan creation */
   FS_E_DEVICE = -4,      /* HIP runtime error; the plan is unusable */
-  FS_E_NONFINITE = -5    /* reserved: non-finite values detected */
+  FS_E_NONFINITE = -5    /* FS_CHECK_FINITE: the last step wrote non-finite values */
 } fs_status;
 
 enum { FS_F32 = 0, FS_F64 = 1 };
@@ -91,6 +91,14 @@ enum { FS_SCHEME_RK4 = 0, FS_SCHEME_RK2 = 1 };
  * Diagnostics, transfer and 1D spectra describe the velocity (2D: vorticity)
  * part. */
 #define FS_BOUSSINESQ 0x8u
+/* Check every step for non-finite values: the last stage of each step flags
+ * any non-finite value it writes to the state (one device flag, set by the
+ * step's own kernels, copied to pinned host memory after each fs_step_rk4
+ * call).  The next fs_step_rk4, fs_tendency, fs_energy_spectrum or
+ * fs_plan_time call waits for that copy and, if the flag is set, clears it
+ * and returns FS_E_NONFINITE without enqueuing anything; the plan stays
+ * usable.  Costs one host wait per call on the previous step call. */
+#define FS_CHECK_FINITE 0x10u
 
 typedef struct fs_plan fs_plan;
 
@@ -101,7 +109,8 @@ typedef struct {
   double forcing_power; /* 3D only: constant injected power P; 0 = no forcing */
   double forcing_kmin;  /* forcing band kmin <= |k| <= kmax (default 2, 3) */
   double forcing_kmax;
-  unsigned flags;       /* FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE */
+  unsigned flags;       /* FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE | FS_BOUSSINESQ |
+                           FS_CHECK_FINITE */
   int scheme;           /* FS_SCHEME_RK4 (default) or FS_SCHEME_RK2 */
   double cfl;           /* > 0: adaptive steps, dt_n = min(dt, cfl (L/n) / umax_n) with
                            umax_n the largest |u_c| of the physical velocity of u_n
@@ -114,6 +123,13 @@ typedef struct {
                            E(t) u = exp(-nu k^2 t)(cos(s t) u - sin(s t) khat x u),
                            s = f kz / |k|; fs_tendency excludes it; fixed steps
                            only (cfl = 0), not with FS_BOUSSINESQ */
+  void *workspace;      /* optional caller-owned device workspace (e.g. a torch
+                           tensor), 256-byte aligned, of at least
+                           fs_plan_workspace_bytes bytes; the plan uses it instead
+                           of allocating and never frees it; it must outlive the
+                           plan and not be shared with another live plan.
+                           NULL (default): the plan allocates its own */
+  size_t workspace_bytes; /* size of workspace in bytes */
 } fs_plan_opts;
 
 /* Fill *opts with the defaults listed above. */
@@ -141,11 +157,18 @@ fs_status fs_plan_destroy(fs_plan *plan);
 /* Replace the stream the plan enqueues on (NULL = null stream). */
 fs_status fs_plan_set_stream(fs_plan *plan, void *stream);
 
-/* Number of complex elements of a state: 3*N*N*(N/2+1) (3D) or N*(N/2+1) (2D). */
+/* Number of complex elements of a state: 3*N*N*(N/2+1) (3D) or N*(N/2+1) (2D),
+ * times 4/3 (3D) or 2 (2D) with FS_BOUSSINESQ. */
 fs_status fs_state_elems(const fs_plan *plan, size_t *n_complex);
 
-/* Device bytes owned by the plan (workspace and tables). */
+/* Device bytes of the plan's workspace and tables (its own allocation or the
+ * part of the caller's workspace it uses). */
 fs_status fs_workspace_bytes(const fs_plan *plan, size_t *bytes);
+
+/* Device workspace a plan of size n with these options needs (NULL opts:
+ * defaults), before creating it; validates n and opts like fs_plan_create
+ * (L, nu and dt do not change the size).  Needs no device. */
+fs_status fs_plan_workspace_bytes(int n, const fs_plan_opts *opts, size_t *bytes);
 
 /* Number of spectrum bins that covers every kept mode:
  * floor(sqrt(d) * K + 1/2) + 1 with K = floor((N-1)/3). */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -98,8 +99,25 @@ void release(Plan* p) {
   p->pool.clear();
   if (p->cap) hipStreamDestroy(p->cap);
   p->cap = nullptr;
-  if (p->base) hipFree(p->base);
+  if (p->base && p->owns_base) hipFree(p->base);
   p->base = nullptr;
+  if (p->nonfin_host) hipHostFree(p->nonfin_host);
+  p->nonfin_host = nullptr;
+  if (p->nonfin_ev) hipEventDestroy(p->nonfin_ev);
+  p->nonfin_ev = nullptr;
+}
+
+// FS_CHECK_FINITE: the flag copied after the last step call; reports (and
+// clears) a non-finite value written by it.
+fs_status check_finite(Plan* p) {
+  if (!p->nonfin_pending) return FS_OK;
+  p->nonfin_pending = false;
+  if (!p->ok(hipEventSynchronize(p->nonfin_ev), "flag event")) return FS_E_DEVICE;
+  if (*p->nonfin_host == 0) return FS_OK;
+  *p->nonfin_host = 0;
+  if (!p->ok(hipMemsetAsync(p->nonfin, 0, sizeof(unsigned), p->stream), "clear flag"))
+    return FS_E_DEVICE;
+  return fail(FS_E_NONFINITE, "the last fs_step_rk4 call wrote non-finite values");
 }
 
 // One RK4 step (forcing coefficient, four stages) on p->launch.
@@ -137,30 +155,8 @@ int K_of(int n) { return (n - 1) / 3; }
 
 }  // namespace
 
-extern "C" {
-
-void fs_plan_opts_default(fs_plan_opts* o) {
-  if (!o) return;
-  o->ndim = 3;
-  o->precision = FS_F32;
-  o->stream = nullptr;
-  o->forcing_power = 0.0;
-  o->forcing_kmin = 2.0;
-  o->forcing_kmax = 3.0;
-  o->flags = 0;
-  o->scheme = FS_SCHEME_RK4;
-  o->cfl = 0.0;
-  o->n2 = 0.0;
-  o->rotation = 0.0;
-}
-
-fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
-                         const fs_plan_opts* opts) {
-  if (!out) return fail(FS_E_INVALID, "out is NULL");
-  *out = nullptr;
-  fs_plan_opts o;
-  fs_plan_opts_default(&o);
-  if (opts) o = *opts;
+// Validation and the host side of a plan (fields, kernels); no device call.
+fs_status configure(Plan* p, int n, double L, double nu, double dt, const fs_plan_opts& o) {
   if (n <= 0) return fail(FS_E_INVALID, "n = %d must be positive", n);
   if (!is_pow2(n) || n < 16 || n > 1024)
     return fail(FS_E_UNSUPPORTED, "n = %d: supported sizes are powers of two 16..1024", n);
@@ -170,7 +166,7 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   if (o.ndim != 2 && o.ndim != 3) return fail(FS_E_INVALID, "ndim = %d must be 2 or 3", o.ndim);
   if (o.precision != FS_F32 && o.precision != FS_F64)
     return fail(FS_E_INVALID, "precision = %d must be FS_F32 or FS_F64", o.precision);
-  if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE | FS_BOUSSINESQ))
+  if (o.flags & ~(FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE | FS_BOUSSINESQ | FS_CHECK_FINITE))
     return fail(FS_E_INVALID, "unknown flags");
   if (!(isfin(o.n2) && o.n2 >= 0)) return fail(FS_E_INVALID, "n2 must be finite and >= 0");
   if (!isfin(o.rotation)) return fail(FS_E_INVALID, "rotation must be finite");
@@ -207,13 +203,8 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
     if (m2max < 0) return fail(FS_E_INVALID, "forcing band contains no mode");
     if (bw < 1) bw = 1;
   }
-
   if (o.ndim == 3 && o.precision == FS_F64 && n > 512)
     return fail(FS_E_UNSUPPORTED, "3D FP64 plans support n <= 512");
-
-  fs_plan* h = new (std::nothrow) fs_plan();
-  if (!h) return fail(FS_E_NOMEM, "host allocation failed");
-  Plan* p = &h->p;
   p->n = n;
   p->ndim = o.ndim;
   p->prec = o.precision;
@@ -240,36 +231,99 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   else
     p->ops = o.precision == FS_F32 ? fs::make_ops2<float>(n, p->nfield)
                                    : fs::make_ops2<double>(n, p->nfield);
-  if (!p->ops.stage) {
+  if (!p->ops.stage) return fail(FS_E_UNSUPPORTED, "no kernels for n = %d", n);
+  return FS_OK;
+}
+
+constexpr int kPieces = 11;
+
+// Byte sizes and offsets of the pieces carved out of the plan's one
+// workspace allocation; returns the total.
+size_t carve(const Plan* p, size_t off[kPieces], size_t sz[kPieces]) {
+  const int n = p->n, bw = p->bw;
+  const size_t rs = p->prec == FS_F32 ? 4 : 8, cs = 2 * rs;
+  const int band_elems = 3 * (2 * bw + 1) * (2 * bw + 1) * (bw + 1);
+  const size_t dpart = (size_t)fs::kDiagMaxBlocks * (fs::kDiagMaxBins + 2) * sizeof(double);
+  const size_t v[kPieces] = {cs * n,
+                             rs * n,
+                             rs * n,
+                             cs * p->ops.elems_a,
+                             cs * p->ops.elems_b,
+                             cs * p->ops.elems_acc,
+                             cs * (size_t)(band_elems > 0 ? band_elems : 1),
+                             rs * 2,
+                             dpart,
+                             64,  // step, elapsed time, velocity maximum, non-finite flag
+                             cs * (p->ops.elems_sin ? p->ops.elems_sin : 1)};
+  size_t total = 0;
+  for (int i = 0; i < kPieces; i++) {
+    sz[i] = v[i];
+    off[i] = total;
+    total += align256(v[i]);
+  }
+  return total;
+}
+
+extern "C" {
+
+void fs_plan_opts_default(fs_plan_opts* o) {
+  if (!o) return;
+  o->ndim = 3;
+  o->precision = FS_F32;
+  o->stream = nullptr;
+  o->forcing_power = 0.0;
+  o->forcing_kmin = 2.0;
+  o->forcing_kmax = 3.0;
+  o->flags = 0;
+  o->scheme = FS_SCHEME_RK4;
+  o->cfl = 0.0;
+  o->n2 = 0.0;
+  o->rotation = 0.0;
+  o->workspace = nullptr;
+  o->workspace_bytes = 0;
+}
+
+fs_status fs_plan_workspace_bytes(int n, const fs_plan_opts* opts, size_t* bytes) {
+  if (!bytes) return fail(FS_E_INVALID, "bytes is NULL");
+  fs_plan_opts o;
+  fs_plan_opts_default(&o);
+  if (opts) o = *opts;
+  Plan p;
+  if (fs_status st = configure(&p, n, 2.0 * M_PI, 0.0, 1.0, o)) return st;
+  size_t off[kPieces], sz[kPieces];
+  *bytes = carve(&p, off, sz);
+  return FS_OK;
+}
+
+fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
+                         const fs_plan_opts* opts) {
+  if (!out) return fail(FS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fs_plan_opts o;
+  fs_plan_opts_default(&o);
+  if (opts) o = *opts;
+  fs_plan* h = new (std::nothrow) fs_plan();
+  if (!h) return fail(FS_E_NOMEM, "host allocation failed");
+  Plan* p = &h->p;
+  if (fs_status st = configure(p, n, L, nu, dt, o)) {
     delete h;
-    return fail(FS_E_UNSUPPORTED, "no kernels for n = %d", n);
+    return st;
+  }
+  size_t off[kPieces], sz[kPieces];
+  const size_t total = carve(p, off, sz);
+  if (o.workspace && (o.workspace_bytes < total || ((uintptr_t)o.workspace & 255))) {
+    delete h;
+    return fail(FS_E_INVALID, "workspace must be 256-byte aligned and hold %zu bytes", total);
   }
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete h;
     return fail(FS_E_DEVICE, "no HIP device");
   }
-  const size_t rs = o.precision == FS_F32 ? 4 : 8, cs = 2 * rs;
-  const int band_elems = 3 * (2 * bw + 1) * (2 * bw + 1) * (bw + 1);
-  const size_t dpart = (size_t)fs::kDiagMaxBlocks * (fs::kDiagMaxBins + 2) * sizeof(double);
-  constexpr int kPieces = 11;
-  size_t off[kPieces];
-  size_t sz[kPieces] = {cs * n,
-                        rs * n,
-                        rs * n,
-                        cs * p->ops.elems_a,
-                        cs * p->ops.elems_b,
-                        cs * p->ops.elems_acc,
-                        cs * (size_t)(band_elems > 0 ? band_elems : 1),
-                        rs * 2,
-                        dpart,
-                        64,  // step, elapsed time, velocity maximum
-                        cs * (p->ops.elems_sin ? p->ops.elems_sin : 1)};
-  size_t total = 0;
-  for (int i = 0; i < kPieces; i++) {
-    off[i] = total;
-    total += align256(sz[i]);
-  }
-  if (hipMalloc(&p->base, total) != hipSuccess) {
+  const size_t rs = o.precision == FS_F32 ? 4 : 8;
+  if (o.workspace) {
+    p->base = o.workspace;
+    p->owns_base = false;
+  } else if (hipMalloc(&p->base, total) != hipSuccess) {
     hipGetLastError();
     delete h;
     return fail(FS_E_NOMEM, "hipMalloc of %zu bytes failed", total);
@@ -289,9 +343,21 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   p->umaxdev = (unsigned long long*)(b + off[9] + 8);
   p->dtdev = b + off[9] + 16;
   p->sin = p->ops.elems_sin ? b + off[10] : nullptr;
+  p->nonfin = (unsigned*)(b + off[9] + 24);
   p->dpart_blocks = fs::kDiagMaxBlocks;
+  if ((o.flags & FS_CHECK_FINITE) &&
+      (!p->ok(hipHostMalloc((void**)&p->nonfin_host, sizeof(unsigned), hipHostMallocDefault),
+              "pinned flag") ||
+       !p->ok(hipEventCreateWithFlags(&p->nonfin_ev, hipEventDisableTiming), "flag event"))) {
+    std::string msg = fs::g_err;
+    release(p);
+    delete h;
+    return fail(FS_E_DEVICE, "%s", msg.c_str());
+  }
+  if (p->nonfin_host) *p->nonfin_host = 0;
 
   const float dt32 = (float)dt;
+  const double kb = 2.0 * M_PI / L;
   // FP64 tables, rounded once
   std::vector<char> host(sz[0] + sz[1] + sz[2]);
   for (int m = 0; m < n; m++) {
@@ -390,6 +456,7 @@ fs_status fs_tendency(fs_plan* plan, const void* state, void* tend) {
   if (fs_status s = usable(plan)) return s;
   if (!state || !tend) return fail(FS_E_INVALID, "NULL array");
   if (state == tend) return fail(FS_E_INVALID, "state and tend must not overlap");
+  if (fs_status st = check_finite(&plan->p)) return st;
   plan->p.ops.tendency(&plan->p, state, tend, true);
   return device_status(&plan->p);
 }
@@ -400,6 +467,7 @@ fs_status fs_step_rk4(fs_plan* plan, void* state, int nsteps) {
   if (nsteps < 0) return fail(FS_E_INVALID, "nsteps = %d must be >= 0", nsteps);
   if (nsteps == 0) return FS_OK;
   Plan* p = &plan->p;
+  if (fs_status st = check_finite(p)) return st;
   p->ops.p1(p, state);
   const bool graphs = !(p->flags & (FS_NO_GRAPH | FS_PROFILE));
   if (graphs) {
@@ -419,11 +487,19 @@ fs_status fs_step_rk4(fs_plan* plan, void* state, int nsteps) {
     for (int s = 0; s < nsteps; s++) enqueue_step(p, state, s + 1 < nsteps);
   }
   if (p->cfl <= 0) p->t_fixed += nsteps * p->dt;
+  if (p->nonfin_host && !p->failed) {
+    p->ok(hipMemcpyAsync(p->nonfin_host, p->nonfin, sizeof(unsigned), hipMemcpyDeviceToHost,
+                         p->stream),
+          "copy flag");
+    p->ok(hipEventRecord(p->nonfin_ev, p->stream), "flag event");
+    p->nonfin_pending = !p->failed;
+  }
   return device_status(p);
 }
 
 fs_status fs_plan_time(fs_plan* plan, double* time, double* last_dt) {
   if (fs_status s = usable(plan)) return s;
+  if (fs_status st = check_finite(&plan->p)) return st;
   fs::launch_time(&plan->p, time, last_dt);
   return device_status(&plan->p);
 }
@@ -434,6 +510,7 @@ fs_status fs_energy_spectrum(fs_plan* plan, const void* state, double* spectrum,
   if (!state || !spectrum) return fail(FS_E_INVALID, "NULL array");
   if (nbins < 1 || nbins > fs::kDiagMaxBins)
     return fail(FS_E_INVALID, "nbins = %d must be in 1..%d", nbins, fs::kDiagMaxBins);
+  if (fs_status st = check_finite(&plan->p)) return st;
   plan->p.ops.diag(&plan->p, state, spectrum, nbins, energy, enstrophy);
   return device_status(&plan->p);
 }

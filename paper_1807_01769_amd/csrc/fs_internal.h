@@ -83,6 +83,7 @@ struct Plan {
   Ops ops{};
   // device memory (one allocation, carved)
   void* base = nullptr;
+  bool owns_base = true;  // false when the caller supplied the workspace
   size_t bytes_total = 0;
   void *tw = nullptr, *e1 = nullptr, *eh1 = nullptr;
   void *bufA = nullptr, *bufB = nullptr, *acc = nullptr, *vband = nullptr, *alpha = nullptr;
@@ -91,6 +92,10 @@ struct Plan {
   void* sin = nullptr;      // 2D Boussinesq stage input
   double* tdev = nullptr;   // elapsed time of adaptive steps
   unsigned long long* umaxdev = nullptr;  // velocity maximum of the step (double bits)
+  unsigned* nonfin = nullptr;     // FS_CHECK_FINITE: set when a step wrote a non-finite value
+  unsigned* nonfin_host = nullptr;  // pinned copy of *nonfin, written after each step call
+  hipEvent_t nonfin_ev = nullptr;   // completion of that copy
+  bool nonfin_pending = false;
   int dpart_blocks = 0;
   // captured step graphs for one state pointer
   hipGraphExec_t gmid = nullptr, glast = nullptr;

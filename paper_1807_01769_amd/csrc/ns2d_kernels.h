@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(LB * N / 8)
   const T kx = a.kb * (T)mx;
   const T dt = stage_dt(a);
   cx<T> w[NF][8];
+  bool bad = false;  // a non-finite value written to the state
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int iy = t + e * P;
@@ -249,12 +250,18 @@ __global__ void __launch_bounds__(LB * N / 8)
         if constexpr (mode_reads_state(MODE)) u = a.state[(size_t)c * N * NH + so];
         if constexpr (mode_reads_acc(MODE)) acc = a.acc[c * kField + ao];
         const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, dt);
-        if constexpr (mode_writes_state(MODE)) a.state[(size_t)c * N * NH + so] = nxt;
+        if constexpr (mode_writes_state(MODE)) {
+          a.state[(size_t)c * N * NH + so] = nxt;
+          bad |= nonfinite(nxt);
+        }
         if constexpr (mode_writes_acc(MODE)) a.acc[c * kField + ao] = acc;
         if constexpr (NF == 2) a.sin[c * kField + ci] = nxt;
         w[c][e] = nxt;
       }
     }
+  }
+  if constexpr (mode_writes_state(MODE)) {
+    if (a.nonfin) flag_wave(a.nonfin, bad);
   }
   if constexpr (MODE != kModeTend) {
     if (do_p1) y_inverse_fields<T, N, LB, NF>(w, t, b, mx, a.kb, w1, lds, twr);

@@ -433,7 +433,12 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
   const int bn = (2 * a.bw + 1) * (2 * a.bw + 1) * (a.bw + 1);
   const T alpha = a.m2max >= 0 ? a.alpha[0] : (T)0;
   const T dt = stage_dt(a);
-  const int m2xy = band_column(a, mx, my);
+  // forcing-band modes exist only in blocks whose kx range starts within the
+  // band and whose ky is in it: a block-uniform test, so that the per-mode
+  // test below stays out of every other block's register budget
+  const bool blk_band = a.m2max >= 0 && xt * kTile + sub * C::LB <= a.bw && my <= a.bw &&
+                        my >= -a.bw;
+  bool bad = false;  // a non-finite value written to the state
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int iz = t + e * P;
@@ -459,11 +464,15 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
 #pragma unroll
       for (int c = 0; c < NC; c++) nl[c] = {0, 0};
     }
-    const bool band = in_band(a, m2xy, mz);
-    const int bi = band ? band_index<T>(mx, my, mz, a.bw) : 0;
-    if (band) {
+    bool band = false;
+    int bi = 0;
+    if (blk_band) {
+      band = in_band(a, band_column(a, mx, my), mz);
+      if (band) {
+        bi = band_index<T>(mx, my, mz, a.bw);
 #pragma unroll
-      for (int c = 0; c < 3; c++) nl[c] = nl[c] + cscale(a.vband[c * bn + bi], alpha);
+        for (int c = 0; c < 3; c++) nl[c] = nl[c] + cscale(a.vband[c * bn + bi], alpha);
+      }
     }
     const size_t so = ((size_t)iz * N + iy) * NH + mx;
     if constexpr (MODE == kModeTend) {
@@ -501,7 +510,10 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
         }
 #pragma unroll
         for (int c = 0; c < NC; c++) {
-          if constexpr (mode_writes_state(MODE)) a.state[c * cstride + so] = nxt[c];
+          if constexpr (mode_writes_state(MODE)) {
+            a.state[c * cstride + so] = nxt[c];
+            bad |= nonfinite(nxt[c]);
+          }
           if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc[c];
           v[c][e] = nxt[c];
         }
@@ -513,7 +525,10 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
           if constexpr (mode_reads_state(MODE)) u = a.state[c * cstride + so];
           if constexpr (mode_reads_acc(MODE)) acc = a.acc[c * acstride + ao];
           const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, dt);
-          if constexpr (mode_writes_state(MODE)) a.state[c * cstride + so] = nxt;
+          if constexpr (mode_writes_state(MODE)) {
+            a.state[c * cstride + so] = nxt;
+            bad |= nonfinite(nxt);
+          }
           if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc;
           v[c][e] = nxt;
         }
@@ -523,6 +538,9 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
         for (int c = 0; c < 3; c++) a.vband[c * bn + bi] = v[c][e];
       }
     }
+  }
+  if constexpr (mode_writes_state(MODE)) {
+    if (a.nonfin) flag_wave(a.nonfin, bad);
   }
   if constexpr (MODE != kModeTend) {
     if (do_p1) z_inverse_six<T, N, NC>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);

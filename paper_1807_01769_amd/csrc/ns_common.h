@@ -118,6 +118,7 @@ struct StageArgs {
   cx<T>* sin;          // 2D Boussinesq: stage input [2][XT][M][16] (else null)
   T n2;                // Boussinesq: squared buoyancy frequency
   T rotf;              // 3D rotating frame: Coriolis parameter f (z axis)
+  unsigned* nonfin;    // non-null: flag set when the last stage writes a non-finite value
   int bw;              // half width of the forcing-band cube (modes)
   int m2min, m2max;    // band: m2min <= |m|^2 <= m2max; m2max < 0 => off
 };
@@ -291,6 +292,16 @@ __device__ __forceinline__ void prop_combine(const cx<T> (&u)[NC], cx<T> (&a)[NC
 #pragma unroll
     for (int q = 0; q < NC; q++) next[q] = w[q] + cscale(o[q], dt);
   }
+}
+
+// Non-finite check of the values a lane wrote: one atomic per wave that saw one.
+template <typename T>
+__device__ __forceinline__ bool nonfinite(cx<T> v) {
+  return !(__builtin_isfinite(v.re) && __builtin_isfinite(v.im));
+}
+__device__ __forceinline__ void flag_wave(unsigned* flag, bool bad) {
+  const unsigned long long m = __ballot(bad);
+  if (m != 0 && (threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicOr(flag, 1u);
 }
 
 // Largest |value| of a velocity sample into a device maximum (non-negative

@@ -11,7 +11,7 @@ namespace {
 
 template <typename T>
 StageArgs<T> stage_args2(Plan* p, void* state, void* tend) {
-  StageArgs<T> a;
+  StageArgs<T> a{};
   a.state = (cx<T>*)state;
   a.acc = (cx<T>*)p->acc;
   a.tend = (cx<T>*)tend;
@@ -28,6 +28,7 @@ StageArgs<T> stage_args2(Plan* p, void* state, void* tend) {
   a.bw = 0;
   a.m2min = 0;
   a.m2max = -1;
+  a.nonfin = (p->flags & FS_CHECK_FINITE) ? p->nonfin : nullptr;
   return a;
 }
 

@@ -10,7 +10,7 @@ namespace {
 
 template <typename T>
 StageArgs<T> stage_args(Plan* p, void* state, void* tend) {
-  StageArgs<T> a;
+  StageArgs<T> a{};
   a.state = (cx<T>*)state;
   a.acc = (cx<T>*)p->acc;
   a.tend = (cx<T>*)tend;
@@ -28,6 +28,7 @@ StageArgs<T> stage_args(Plan* p, void* state, void* tend) {
   a.bw = p->bw;
   a.m2min = p->m2min;
   a.m2max = p->m2max;
+  a.nonfin = (p->flags & FS_CHECK_FINITE) ? p->nonfin : nullptr;
   return a;
 }
 

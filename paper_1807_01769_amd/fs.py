@@ -22,7 +22,8 @@ lib = C.CDLL(LIB_PATH)
 FS_OK, FS_E_INVALID, FS_E_UNSUPPORTED, FS_E_NOMEM, FS_E_DEVICE, FS_E_NONFINITE = 0, -1, -2, -3, -4, -5
 FS_F32, FS_F64 = 0, 1
 FS_SCHEME_RK4, FS_SCHEME_RK2 = 0, 1
-FS_NO_GRAPH, FS_PROFILE, FS_BOUSSINESQ = 0x1, 0x2, 0x8
+FS_NO_GRAPH, FS_PROFILE, FS_BOUSSINESQ, FS_CHECK_FINITE = 0x1, 0x2, 0x8, 0x10
+FS_E_NONFINITE = -5
 KERNEL_NAMES = ["p1", "y_inverse", "x_c2r_product_r2c", "y_forward", "z_stage",
                 "forcing_alpha", "fill", "fft_only", "diagnostics"]
 
@@ -40,6 +41,8 @@ class Opts(C.Structure):
         ("cfl", C.c_double),
         ("n2", C.c_double),
         ("rotation", C.c_double),
+        ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_size_t),
     ]
 
 
@@ -51,6 +54,7 @@ lib.fs_plan_destroy.argtypes = [_vp]
 lib.fs_plan_set_stream.argtypes = [_vp, _vp]
 lib.fs_state_elems.argtypes = [_vp, C.POINTER(C.c_size_t)]
 lib.fs_workspace_bytes.argtypes = [_vp, C.POINTER(C.c_size_t)]
+lib.fs_plan_workspace_bytes.argtypes = [_i, C.POINTER(Opts), C.POINTER(C.c_size_t)]
 lib.fs_spectrum_bins.argtypes = [_vp, C.POINTER(_i)]
 lib.fs_fft_forward.argtypes = [_vp, _vp, _vp]
 lib.fs_fft_inverse.argtypes = [_vp, _vp, _vp]
@@ -67,7 +71,7 @@ lib.fs_status_str.restype = C.c_char_p
 lib.fs_last_error.argtypes = []
 lib.fs_last_error.restype = C.c_char_p
 for _f in ("fs_plan_create", "fs_plan_destroy", "fs_plan_set_stream", "fs_state_elems",
-           "fs_workspace_bytes", "fs_spectrum_bins", "fs_fft_forward", "fs_fft_inverse",
+           "fs_workspace_bytes", "fs_plan_workspace_bytes", "fs_spectrum_bins", "fs_fft_forward", "fs_fft_inverse",
            "fs_tendency", "fs_step_rk4", "fs_energy_spectrum", "fs_energy_transfer",
            "fs_energy_spectra_1d", "fs_structure_functions", "fs_plan_time",
            "fs_profile_read"):
@@ -92,6 +96,25 @@ def _stream_ptr(stream) -> int:
     return int(stream.cuda_stream)
 
 
+def _opts(ndim=3, precision="f32", forcing_power=0.0, forcing_kmin=2.0, forcing_kmax=3.0,
+          graphs=True, profile=False, scheme="rk4", cfl=0.0, boussinesq=False, n2=0.0,
+          rotation=0.0, check_finite=False) -> Opts:
+    o = Opts()
+    lib.fs_plan_opts_default(C.byref(o))
+    o.ndim = int(ndim)
+    o.precision = FS_F32 if precision == "f32" else FS_F64
+    o.forcing_power = float(forcing_power)
+    o.forcing_kmin = float(forcing_kmin)
+    o.forcing_kmax = float(forcing_kmax)
+    o.flags = ((0 if graphs else FS_NO_GRAPH) | (FS_PROFILE if profile else 0) |
+               (FS_BOUSSINESQ if boussinesq else 0) | (FS_CHECK_FINITE if check_finite else 0))
+    o.n2 = float(n2)
+    o.rotation = float(rotation)
+    o.scheme = {"rk4": FS_SCHEME_RK4, "rk2": FS_SCHEME_RK2}[scheme]
+    o.cfl = float(cfl)
+    return o
+
+
 class Plan:
     """One solver configuration: grid n, box length L, viscosity nu, step dt."""
 
@@ -99,7 +122,12 @@ class Plan:
                  ndim: int = 3, precision: str = "f32", stream=None, forcing_power: float = 0.0,
                  forcing_kmin: float = 2.0, forcing_kmax: float = 3.0, graphs: bool = True,
                  profile: bool = False, scheme: str = "rk4", cfl: float = 0.0,
-                 boussinesq: bool = False, n2: float = 0.0, rotation: float = 0.0):
+                 boussinesq: bool = False, n2: float = 0.0, rotation: float = 0.0,
+                 check_finite: bool = False, workspace: torch.Tensor | None = None):
+        """workspace: optional device tensor of at least Plan.required_bytes(...)
+        bytes that the plan uses instead of allocating (kept referenced by the
+        plan); check_finite: report non-finite steps as FsError (FS_E_NONFINITE)
+        at the next call."""
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1807_01769_amd.fs needs a HIP device")
         self.n, self.L, self.nu, self.dt, self.ndim = int(n), float(L), float(nu), float(dt), int(ndim)
@@ -107,21 +135,16 @@ class Plan:
         self.real_dtype = {"f32": torch.float32, "f64": torch.float64}[precision]
         self.complex_dtype = {"f32": torch.complex64, "f64": torch.complex128}[precision]
         self.stream = stream
-        o = Opts()
-        lib.fs_plan_opts_default(C.byref(o))
-        o.ndim = self.ndim
-        o.precision = FS_F32 if precision == "f32" else FS_F64
+        o = _opts(ndim, precision, forcing_power, forcing_kmin, forcing_kmax, graphs, profile,
+                  scheme, cfl, boussinesq, n2, rotation, check_finite)
         o.stream = _stream_ptr(stream)
-        o.forcing_power = float(forcing_power)
-        o.forcing_kmin = float(forcing_kmin)
-        o.forcing_kmax = float(forcing_kmax)
-        o.flags = ((0 if graphs else FS_NO_GRAPH) | (FS_PROFILE if profile else 0) |
-                   (FS_BOUSSINESQ if boussinesq else 0))
-        o.n2 = float(n2)
-        o.rotation = float(rotation)
+        self._workspace = workspace
+        if workspace is not None:
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous device tensor")
+            o.workspace = workspace.data_ptr()
+            o.workspace_bytes = workspace.numel() * workspace.element_size()
         self.nfield = (3 if self.ndim == 3 else 1) + (1 if boussinesq else 0)
-        o.scheme = {"rk4": FS_SCHEME_RK4, "rk2": FS_SCHEME_RK2}[scheme]
-        o.cfl = float(cfl)
         h = _vp()
         _check(lib.fs_plan_create(C.byref(h), self.n, self.L, self.nu, self.dt, C.byref(o)),
                "fs_plan_create")
@@ -149,6 +172,16 @@ class Plan:
     @property
     def phys_shape(self):
         return (self.n,) * self.ndim
+
+    @staticmethod
+    def required_bytes(n: int, **opts) -> int:
+        """Workspace bytes of a plan of size n with these options (keywords as
+        for Plan), without creating it; needs no device."""
+        o = _opts(**opts)
+        b = C.c_size_t()
+        _check(lib.fs_plan_workspace_bytes(int(n), C.byref(o), C.byref(b)),
+               "fs_plan_workspace_bytes")
+        return int(b.value)
 
     def workspace_bytes(self) -> int:
         b = C.c_size_t()

@@ -36,7 +36,8 @@ class Opts(C.Structure):
     _fields_ = [("ndim", C.c_int), ("precision", C.c_int), ("stream", C.c_void_p),
                 ("forcing_power", C.c_double), ("forcing_kmin", C.c_double),
                 ("forcing_kmax", C.c_double), ("flags", C.c_uint), ("scheme", C.c_int),
-                ("cfl", C.c_double), ("n2", C.c_double), ("rotation", C.c_double)]
+                ("cfl", C.c_double), ("n2", C.c_double), ("rotation", C.c_double),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
 def _create(lib, n, L, nu, dt, **kw):
@@ -78,10 +79,13 @@ def _create(lib, n, L, nu, dt, **kw):
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "rotation": 1.0}, -2),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "cfl": 0.5}, -2),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "ndim": 2, "n2": -1.0}, -1),
-    ((64, 6.28, 0.1, 0.01), {"flags": 0x10}, -1),
+    ((64, 6.28, 0.1, 0.01), {"flags": 0x20}, -1),
     ((64, 6.28, 0.1, 0.01), {"rotation": float("inf")}, -1),
     ((64, 6.28, 0.1, 0.01), {"rotation": 1.0, "ndim": 2}, -2),
     ((64, 6.28, 0.1, 0.01), {"rotation": 1.0, "cfl": 0.5}, -2),
+    # a caller workspace that is too small or misaligned (checked before any device call)
+    ((64, 6.28, 0.1, 0.01), {"workspace": 1 << 20, "workspace_bytes": 4096}, -1),
+    ((64, 6.28, 0.1, 0.01), {"workspace": (1 << 40) + 16, "workspace_bytes": 1 << 40}, -1),
 ])
 def test_create_validates_before_device(lib, args, kw, expect):
     st, h = _create(lib, *args, **kw)
@@ -174,7 +178,40 @@ def test_opts_defaults(lib):
     lib.fs_plan_opts_default.argtypes = [C.POINTER(Opts)]
     o = Opts()
     o.scheme, o.cfl, o.n2, o.rotation = 7, 3.0, 1.0, 2.0
+    o.workspace, o.workspace_bytes = 4096, 99
     lib.fs_plan_opts_default(C.byref(o))
     assert (o.ndim, o.precision, o.flags, o.scheme, o.cfl, o.n2, o.rotation) == \
         (3, 0, 0, 0, 0.0, 0.0, 0.0)
+    assert not o.workspace and o.workspace_bytes == 0
     assert (o.forcing_power, o.forcing_kmin, o.forcing_kmax) == (0.0, 2.0, 3.0)
+
+
+def _ws_bytes(lib, n, **kw):
+    lib.fs_plan_workspace_bytes.argtypes = [C.c_int, C.POINTER(Opts), C.POINTER(C.c_size_t)]
+    lib.fs_plan_opts_default.argtypes = [C.POINTER(Opts)]
+    o = Opts()
+    lib.fs_plan_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    b = C.c_size_t()
+    st = lib.fs_plan_workspace_bytes(n, C.byref(o), C.byref(b))
+    return st, b.value
+
+
+def test_workspace_bytes_without_device(lib):
+    st, b64 = _ws_bytes(lib, 64)
+    assert st == 0 and b64 > 0
+    _, b128 = _ws_bytes(lib, 128)
+    _, b128d = _ws_bytes(lib, 128, precision=1)
+    _, b128s = _ws_bytes(lib, 128, flags=0x8)
+    _, b128_2d = _ws_bytes(lib, 128, ndim=2)
+    # a 3D plan holds kept-mode workspaces of a few states plus fixed tables
+    state = 3 * 128 * 128 * 65 * 8
+    assert 2 * state < b128 < 16 * state
+    assert b64 < b128 < b128d and b128 < b128s and b128_2d < b128 // 8
+    assert b128 % 256 == 0
+    # validated like fs_plan_create
+    assert _ws_bytes(lib, 48)[0] == -2
+    assert _ws_bytes(lib, 64, ndim=5)[0] == -1
+    lib.fs_plan_workspace_bytes.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
+    assert lib.fs_plan_workspace_bytes(64, None, None) == -1
