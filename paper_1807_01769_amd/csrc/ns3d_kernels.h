@@ -28,9 +28,11 @@ namespace fs {
 // (ux,uy) (uz,wx) (wy,wz) of each row, form p = (u x w) * scale, forward
 // transform (px + i py) of each row and (pz(y0) + i pz(y1)), store kept kx.
 // One transform line is in flight at a time and the cross product is built
-// as its factors arrive (u kept, partial products accumulated), so a row
-// pair needs one LDS line and about 100 VGPRs.  With umax, the largest
-// |u_c| of the physical velocity is max-reduced into *umax.
+// as its factors arrive (u kept, partial products accumulated).  The kept
+// coefficients of one row (six fields) are staged in LDS with 16-byte loads
+// before its transforms, so a 64-lane block needs 13 KB of LDS at N = 512
+// and twelve blocks fit a CU.  With umax, the largest |u_c| of the physical
+// velocity is max-reduced into *umax.
 // in : Wn[6][N][XT][N][16]   out: Wn[3][N][XT][N][16]
 // STRAT: in Wn[7] (+ b), out Wn[6] (+ u b, v b, w b); b of the two rows is
 // one complex line, the flux (fx + i fy) of each row and (fz(y0) + i fz(y1))
