@@ -50,7 +50,7 @@ Pins (tests/test_oracle_*.py, all CPU):
                          with forcing
   cutoff3d / grad3d      tr A = 0 for solenoidal fields, closed-form gradient
                          of Taylor-Green, cutoff idempotent and exact on kept
-  sgs_tau3d              zero for band-limited fields, symmetric, traceless,
+  sgs_tau3d              zero for band-limited fields (sharp cutoff), symmetric, traceless,
                          equals the triad definition on a small grid
   mlp_forward/loss_grad  central finite differences
   adam                   closed form of the first step (sign descent by lr)
@@ -104,9 +104,9 @@ def lib():
         L.or_kept.restype = i
         L.or_dft_mode3d.argtypes = [i, vp, i, i, i, vp, vp]
         L.or_lawson_scalar.argtypes = [d, d, d, i]
-        L.or_cutoff3d.argtypes = [i, vp, i, vp]
+        L.or_cutoff3d.argtypes = [i, vp, i, i, vp]
         L.or_grad3d.argtypes = [i, d, vp, vp]
-        L.or_sgs_tau3d.argtypes = [i, vp, i, vp]
+        L.or_sgs_tau3d.argtypes = [i, vp, i, i, vp]
         L.or_mlp_nparams.restype = i
         L.or_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
         L.or_mlp_loss_grad.argtypes = [vp, vp, vp, C.c_int64, vp]
@@ -387,8 +387,9 @@ def dft_mode3d(phys, m):
 TAU_COMPONENTS = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
 
 
-def cutoff3d(fine, nc):
-    """Sharp cube cutoff of a fine spectral field (or [3] stack) to the nc grid."""
+def cutoff3d(fine, nc, box=False):
+    """Sharp cube cutoff of a fine spectral field (or [3] stack) to the nc grid
+    (box: after the box filter of width L / (2 Kc))."""
     f = _c128(fine)
     lead = f.shape[:-3]
     nf = f.shape[-3]
@@ -397,7 +398,7 @@ def cutoff3d(fine, nc):
     for c in range(ff.shape[0]):
         fc = np.ascontiguousarray(ff[c])
         oc = np.empty((nc, nc, nc // 2 + 1), np.complex128)
-        lib().or_cutoff3d(nf, _p(fc), nc, _p(oc))
+        lib().or_cutoff3d(nf, _p(fc), nc, int(bool(box)), _p(oc))
         out[c] = oc
     return out.reshape(lead + (nc, nc, nc // 2 + 1))
 
@@ -411,11 +412,12 @@ def grad3d(uh, L=2 * np.pi):
     return A
 
 
-def sgs_tau3d(uf, nc):
-    """Deviatoric subgrid stress on the nc grid from a fine spectral velocity."""
+def sgs_tau3d(uf, nc, box=False):
+    """Deviatoric subgrid stress on the nc grid from a fine spectral velocity
+    (box: box filter of width L / (2 Kc), then the cutoff)."""
     u = _c128(uf)
     tau = np.empty((6, nc, nc, nc), np.float64)
-    lib().or_sgs_tau3d(u.shape[1], _p(u), nc, _p(tau))
+    lib().or_sgs_tau3d(u.shape[1], _p(u), nc, int(bool(box)), _p(tau))
     return tau
 
 

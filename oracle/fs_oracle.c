@@ -1086,7 +1086,17 @@ static const int TAU_I[6] = {0, 1, 2, 0, 0, 1}, TAU_J[6] = {0, 1, 2, 1, 2, 2};
 
 /* sharp cube cutoff: coarse(m) = fine(m) for |m_a| <= Kc, else 0.
  * fine: [nf][nf][nf/2+1] (one field), coarse: [nc][nc][nc/2+1]. */
-void or_cutoff3d(int nf, const cplx *fine, int nc, cplx *coarse) {
+/* With box != 0 the kept modes are first multiplied by the transfer function
+ * of the box (top-hat) filter of width D = L / (2 Kc) along each axis: the
+ * average of e^{i k x} over [x - D/2, x + D/2] is e^{i k x} sin(k D/2) / (k D/2),
+ * with k D / 2 = pi m / (2 Kc) for integer mode m. */
+static double box_gain(int m, int Kc) {
+  if (m == 0) return 1.0;
+  const double x = M_PI * m / (2.0 * Kc);
+  return sin(x) / x;
+}
+
+void or_cutoff3d(int nf, const cplx *fine, int nc, int box, cplx *coarse) {
   const int Kc = (nc - 1) / 3;
   const int64_t hf = nf / 2 + 1, hc = nc / 2 + 1;
   for (int iz = 0; iz < nc; iz++)
@@ -1097,6 +1107,7 @@ void or_cutoff3d(int nf, const cplx *fine, int nc, cplx *coarse) {
         if (abs(mz) <= Kc && abs(my) <= Kc && mx <= Kc) {
           const int fz = (mz + nf) % nf, fy = (my + nf) % nf;
           v = fine[((int64_t)fz * nf + fy) * hf + mx];
+          if (box) v *= box_gain(mx, Kc) * box_gain(my, Kc) * box_gain(mz, Kc);
         }
         coarse[((int64_t)iz * nc + iy) * hc + ix] = v;
       }
@@ -1123,8 +1134,9 @@ void or_grad3d(int n, double L, const cplx *u, double *A) {
 
 /* Subgrid stress on the coarse grid from a fine spectral velocity:
  * tau_ij = cutoff(u_i u_j) - ubar_i ubar_j at the coarse points, with the
- * fine product formed on the fine grid; the trace is then removed. */
-void or_sgs_tau3d(int nf, const cplx *uf, int nc, double *tau) {
+ * fine product formed on the fine grid; the trace is then removed.  With box
+ * the filter is the box filter followed by the cutoff (ubar included). */
+void or_sgs_tau3d(int nf, const cplx *uf, int nc, int box, double *tau) {
   const int64_t hf = nf / 2 + 1, nsf = (int64_t)nf * nf * hf, npf = (int64_t)nf * nf * nf;
   const int64_t hc = nc / 2 + 1, nsc = (int64_t)nc * nc * hc, npc = (int64_t)nc * nc * nc;
   double *uphys = malloc(sizeof(double) * 3 * npf), *prod = malloc(sizeof(double) * npf);
@@ -1139,7 +1151,7 @@ void or_sgs_tau3d(int nf, const cplx *uf, int nc, double *tau) {
       tmp[q] = keep ? uf[c * nsf + q] : 0;
     }
     or_irfftn(3, nf, tmp, uphys + c * npf);
-    or_cutoff3d(nf, tmp, nc, pc);
+    or_cutoff3d(nf, tmp, nc, box, pc);
     or_irfftn(3, nc, pc, ub + c * npc);
     free(tmp);
   }
@@ -1147,7 +1159,7 @@ void or_sgs_tau3d(int nf, const cplx *uf, int nc, double *tau) {
     const int i = TAU_I[s], j = TAU_J[s];
     for (int64_t q = 0; q < npf; q++) prod[q] = uphys[i * npf + q] * uphys[j * npf + q];
     or_rfftn(3, nf, prod, pf);
-    or_cutoff3d(nf, pf, nc, pc);
+    or_cutoff3d(nf, pf, nc, box, pc);
     or_irfftn(3, nc, pc, tau + s * npc);
     for (int64_t q = 0; q < npc; q++) tau[s * npc + q] -= ub[i * npc + q] * ub[j * npc + q];
   }

@@ -244,3 +244,71 @@ def test_les_tau_clip_and_scale(oracle_mod):
     tau = oracle_mod.les_tau3d(u, p, 1.0, ts, clip=1.0)
     want = np.array([1.0, -1.0, 0.5, -0.25, 1.0, -0.999]) * ts
     assert np.array_equal(tau.reshape(6, -1), np.repeat(want[:, None], n ** 3, axis=1))
+
+
+def _band_field(n, kmax, seed):
+    """Random solenoidal spectral velocity with modes |m_a| <= kmax only."""
+    u = I.random_solenoidal_3d(n, seed=seed)
+    m = np.fft.fftfreq(n, 1.0 / n)
+    keep = (np.abs(m)[:, None, None] <= kmax) & (np.abs(m)[None, :, None] <= kmax) & \
+        (np.arange(n // 2 + 1)[None, None, :] <= kmax)
+    return u * keep[None]
+
+
+def _eval(uh, pts):
+    """u(x) at arbitrary points from the half spectrum (weights 1 on kx = 0, 2 else)."""
+    n = uh.shape[-2]
+    m = np.fft.fftfreq(n, 1.0 / n)
+    kz, ky, kx = np.meshgrid(m, m, np.arange(n // 2 + 1), indexing="ij")
+    w = np.where(kx == 0, 1.0, 2.0)
+    nz = np.nonzero(np.abs(uh).sum(axis=0) > 0)
+    out = np.zeros((3, len(pts)))
+    for c in range(3):
+        coef = (w * uh[c])[nz]
+        ph = np.exp(1j * (np.outer(pts[:, 0], kx[nz]) + np.outer(pts[:, 1], ky[nz]) +
+                          np.outer(pts[:, 2], kz[nz])))
+        out[c] = np.real(ph @ coef)
+    return out
+
+
+def _tophat(uh, x0, D, f):
+    """Average of f(u) over the cube of side D centred at x0 (Gauss-Legendre, 12^3)."""
+    g, wg = np.polynomial.legendre.leggauss(12)
+    o = 0.5 * D * g
+    pts = np.stack(np.meshgrid(o, o, o, indexing="ij"), -1).reshape(-1, 3)
+    ww = np.einsum("i,j,k->ijk", wg, wg, wg).reshape(-1) / 8.0
+    return f(_eval(uh, x0[None, :] + pts)) @ ww
+
+
+def test_box_filter_is_the_tophat_average(oracle_mod):
+    nf, nc = 32, 16                     # Kc = 5, box width D = 2 pi / 10
+    Kc, D = 5, 2 * np.pi / 10
+    u = _band_field(nf, Kc, 601)        # nothing beyond the cutoff
+    ub = oracle_mod.cutoff3d(u, nc, box=True)
+    phys = np.stack([np.fft.irfftn(ub[c], s=(nc,) * 3, axes=(0, 1, 2)) * nc ** 3
+                     for c in range(3)])
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        iz, iy, ix = rng.integers(0, nc, 3)
+        x0 = 2 * np.pi * np.array([ix, iy, iz]) / nc
+        want = _tophat(u, x0, D, lambda v: v)
+        assert np.abs(phys[:, iz, iy, ix] - want).max() <= 1e-12 * np.abs(phys).max()
+
+
+def test_box_filter_stress_is_the_tophat_covariance(oracle_mod):
+    nf, nc = 32, 16
+    D = 2 * np.pi / 10
+    u = _band_field(nf, 2, 603)         # products reach |m| <= 4 < Kc: no cutoff loss
+    tau = oracle_mod.sgs_tau3d(u, nc, box=True)
+    rng = np.random.default_rng(4)
+    pairs = ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))
+    for _ in range(3):
+        iz, iy, ix = rng.integers(0, nc, 3)
+        x0 = 2 * np.pi * np.array([ix, iy, iz]) / nc
+        mean = _tophat(u, x0, D, lambda v: v)
+        cov = np.array([_tophat(u, x0, D, lambda v, i=i, j=j: v[i] * v[j]) - mean[i] * mean[j]
+                        for i, j in pairs])
+        cov[:3] -= cov[:3].mean()
+        assert np.abs(tau[:, iz, iy, ix] - cov).max() <= 1e-12 * np.abs(tau).max()
+    # unlike the sharp cutoff, the box filter leaves a stress on band-limited fields
+    assert np.abs(tau).max() > 1e-3 * np.abs(oracle_mod.sgs_tau3d(_band_field(nf, 8, 605), nc)).max()
