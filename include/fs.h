@@ -368,11 +368,21 @@ typedef struct fs_closure fs_closure;
 fs_status fs_closure_create(fs_closure **out, fs_plan *fine, fs_plan *coarse);
 fs_status fs_closure_destroy(fs_closure *c); /* NULL is a no-op */
 /*
+ * Filter of the samples (and of the coarse state they return):
+ *   FS_FILTER_SHARP (default): the sharp cube cutoff to the coarse kept set;
+ *   FS_FILTER_BOX: the box (top-hat) filter of width L / (2 Kc) along each
+ *     axis, i.e. every mode times prod_a sin(x_a) / x_a with x_a = pi m_a /
+ *     (2 Kc), then the same cutoff (Kc = floor((nc - 1) / 3)).
+ */
+#define FS_FILTER_SHARP 0
+#define FS_FILTER_BOX 1
+fs_status fs_closure_set_filter(fs_closure *c, int filter);
+/*
  * From a fine state ([3][nf][nf][nf/2+1], modes outside its kept set
  * ignored):
- *   coarse_state [3][nc][nc][nc/2+1]: the cutoff (every element written);
+ *   coarse_state [3][nc][nc][nc/2+1]: the filtered state (every element written);
  *   A   real[9][nc^3]: A[3i+j] = d ubar_i / d x_j at the coarse points;
- *   tau real[6][nc^3]: tau_ij = cutoff(u_i u_j) - ubar_i ubar_j, with the
+ *   tau real[6][nc^3]: tau_ij = filter(u_i u_j) - ubar_i ubar_j, with the
  *       fine product formed on the fine grid, trace removed; order xx, yy,
  *       zz, xy, xz, yz.
  */

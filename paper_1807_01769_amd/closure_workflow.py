@@ -58,6 +58,7 @@ class Config:
     lr_final: float = 1e-4
     clip: float = 6.0        # clip of the standardised network output
     net_seed: int = 7
+    filter: str = "sharp"    # "sharp" cube cutoff or "box" (top-hat, then the cutoff)
 
 
 def _steps(t: float, dt: float) -> int:
@@ -247,7 +248,7 @@ def run(cfg: Config) -> dict:
                    forcing_kmin=cfg.kf_min, forcing_kmax=cfg.kf_max)
     coarse = fs.Plan(cfg.nc, nu=cfg.nu, dt=cfg.dt * cfg.les_dt_factor, forcing_power=cfg.power,
                      forcing_kmin=cfg.kf_min, forcing_kmax=cfg.kf_max)
-    closure = fs.Closure(fine, coarse)
+    closure = fs.Closure(fine, coarse, filter=cfg.filter)
     u = torch.from_numpy(inputs.random_solenoidal_3d(cfg.nf, seed=cfg.seed, energy=cfg.energy0,
                                                      dtype=np.complex64)).cuda()
     result = {"config": asdict(cfg)}

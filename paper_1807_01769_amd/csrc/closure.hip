@@ -43,7 +43,7 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + kThr - 1) / kThr); }
 // coarse(m) = fine(m) on |m_a| <= Kc = floor((nc-1)/3), zero elsewhere; every
 // element of `coarse` is written.  blockIdx.y = field.
 __global__ void __launch_bounds__(kThr)
-    k_cutoff(const cf* __restrict__ fine, int nf, cf* __restrict__ coarse, int nc) {
+    k_cutoff(const cf* __restrict__ fine, int nf, cf* __restrict__ coarse, int nc, int box) {
   const int64_t hf = nf / 2 + 1, hc = nc / 2 + 1;
   const int64_t nsc = (int64_t)nc * nc * hc, nsf = (int64_t)nf * nf * hf;
   const int64_t q = (int64_t)blockIdx.x * kThr + threadIdx.x;
@@ -54,6 +54,16 @@ __global__ void __launch_bounds__(kThr)
   if (ix <= Kc && iabs(my) <= Kc && iabs(mz) <= Kc) {
     const int64_t fz = (mz + nf) % nf, fy = (my + nf) % nf;
     v = fine[blockIdx.y * nsf + (fz * nf + fy) * hf + ix];
+    if (box) {
+      // box filter of width L / (2 Kc): sin(x) / x per axis, x = pi m / (2 Kc)
+      const float c = 3.14159265358979f / (2.0f * (float)Kc);
+      const int ms[3] = {ix, my, mz};
+      float g = 1.0f;
+#pragma unroll
+      for (int a = 0; a < 3; a++)
+        if (ms[a] != 0) g *= sinf(c * (float)ms[a]) / (c * (float)ms[a]);
+      v = {v.re * g, v.im * g};
+    }
   }
   coarse[blockIdx.y * nsc + q] = v;
 }
@@ -275,6 +285,7 @@ struct fs_closure {
   cf* grad = nullptr;       // 9 coarse spectral gradient fields
   float* ub = nullptr;      // coarse physical filtered velocity [3][nc^3]
   void *wa = nullptr, *wb = nullptr;  // coarse transform workspaces for 9 fields
+  int box = 0;              // FS_FILTER_BOX: box filter before the cutoff
 };
 
 extern "C" {
@@ -323,6 +334,14 @@ fs_status fs_closure_create(fs_closure** out, fs_plan* fine, fs_plan* coarse) {
   return FS_OK;
 }
 
+fs_status fs_closure_set_filter(fs_closure* c, int filter) {
+  if (!c) return fail(FS_E_INVALID, "NULL closure");
+  if (filter != FS_FILTER_SHARP && filter != FS_FILTER_BOX)
+    return fail(FS_E_INVALID, "filter = %d must be FS_FILTER_SHARP or FS_FILTER_BOX", filter);
+  c->box = filter == FS_FILTER_BOX;
+  return FS_OK;
+}
+
 fs_status fs_closure_destroy(fs_closure* c) {
   if (!c) return FS_OK;
   if (c->base) hipFree(c->base);
@@ -353,7 +372,7 @@ fs_status fs_closure_samples(fs_closure* c, const void* fine_state, void* coarse
   hipStream_t s = pf->stream;
   // filtered state, its physical velocity and gradients
   hipLaunchKernelGGL(fs::k_cutoff, dim3(fs::blocks_for(nsc), 3), dim3(fs::kThr), 0, s, us, nf, uc,
-                     nc);
+                     nc, c->box);
   if (!fs::plan_ok(pc, "k_cutoff")) return FS_E_DEVICE;
   pc->ops.fft_inv_n(pc, uc, c->ub, 3, c->wa, c->wb);
   hipLaunchKernelGGL(fs::k_grad, dim3(fs::blocks_for(nsc)), dim3(fs::kThr), 0, s, (const cf*)uc,
@@ -376,7 +395,7 @@ fs_status fs_closure_samples(fs_closure* c, const void* fine_state, void* coarse
     if (!fs::plan_ok(pf, "k_mul")) return FS_E_DEVICE;
     pf->ops.fft_fwd(pf, c->prod, c->fspec);
     hipLaunchKernelGGL(fs::k_cutoff, dim3(fs::blocks_for(nsc), 1), dim3(fs::kThr), 0, s,
-                       (const cf*)c->fspec, nf, c->cspec, nc);
+                       (const cf*)c->fspec, nf, c->cspec, nc, c->box);
     if (!fs::plan_ok(pc, "k_cutoff")) return FS_E_DEVICE;
     pc->ops.fft_inv(pc, c->cspec, tau + st * npc);
   }

@@ -494,6 +494,7 @@ class Mlp:
 # ---- closure samples and LES -------------------------------------------------
 lib.fs_closure_create.argtypes = [C.POINTER(_vp), _vp, _vp]
 lib.fs_closure_destroy.argtypes = [_vp]
+lib.fs_closure_set_filter.argtypes = [_vp, _i]
 lib.fs_closure_samples.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.fs_closure_moments.argtypes = [_vp, _vp, _vp, _vp]
 lib.fs_closure_features.argtypes = [_vp, _vp, _vp, C.c_float, C.POINTER(C.c_float), _vp, _vp]
@@ -501,7 +502,8 @@ lib.fs_les_create.argtypes = [C.POINTER(_vp), _vp, _vp, C.c_float, C.POINTER(C.c
 lib.fs_les_destroy.argtypes = [_vp]
 lib.fs_les_tendency.argtypes = [_vp, _vp, _vp]
 lib.fs_les_step_rk4.argtypes = [_vp, _vp, _i]
-for _f in ("fs_closure_create", "fs_closure_destroy", "fs_closure_samples", "fs_closure_moments",
+for _f in ("fs_closure_create", "fs_closure_destroy", "fs_closure_set_filter",
+           "fs_closure_samples", "fs_closure_moments",
            "fs_closure_features", "fs_les_create", "fs_les_destroy", "fs_les_tendency",
            "fs_les_step_rk4"):
     getattr(lib, _f).restype = _i
@@ -517,10 +519,13 @@ def _six(v):
 class Closure:
     """Filtered-DNS samples: fine 3D f32 plan -> coarse 3D f32 plan."""
 
-    def __init__(self, fine: Plan, coarse: Plan):
+    def __init__(self, fine: Plan, coarse: Plan, filter: str = "sharp"):
+        """filter: "sharp" (cube cutoff) or "box" (top-hat of width L / (2 Kc), then the cutoff)."""
         h = _vp()
         _check(lib.fs_closure_create(C.byref(h), fine._h, coarse._h), "fs_closure_create")
         self._h, self.fine, self.coarse = h, fine, coarse
+        self.filter = filter
+        _check(lib.fs_closure_set_filter(h, {"sharp": 0, "box": 1}[filter]), "fs_closure_set_filter")
         self.np = coarse.n ** 3
 
     def samples(self, fine_state: torch.Tensor):

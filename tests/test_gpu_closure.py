@@ -49,20 +49,27 @@ def _flat_field(n, seed):
                                   dtype=np.complex64)
 
 
-@pytest.mark.parametrize("nf,nc", [(32, 16), (64, 32), (128, 16)])
-def test_samples_vs_oracle(fs, oracle_mod, nf, nc):
-    print(f"case closure samples nf={nf} nc={nc}", flush=True)
+@pytest.mark.parametrize("nf,nc,filt", [(32, 16, "sharp"), (64, 32, "sharp"), (128, 16, "sharp"),
+                                         (64, 32, "box"), (128, 16, "box")])
+def test_samples_vs_oracle(fs, oracle_mod, nf, nc, filt):
+    print(f"case closure samples nf={nf} nc={nc} {filt}", flush=True)
     u = _flat_field(nf, 40 + nf + nc)
     fine = fs.Plan(nf, nu=1e-3, dt=1e-3)
     coarse = fs.Plan(nc, nu=1e-3, dt=1e-3)
-    cl = fs.Closure(fine, coarse)
+    cl = fs.Closure(fine, coarse, filter=filt)
+    box = filt == "box"
     uc, A, tau = cl.samples(_dev(u))
     torch.cuda.synchronize()
     u64 = u.astype(np.complex128)
-    want_uc = oracle_mod.cutoff3d(u64, nc)
-    assert np.array_equal(uc.cpu().numpy().astype(np.complex128), want_uc)
+    want_uc = oracle_mod.cutoff3d(u64, nc, box=box)
+    got_uc = uc.cpu().numpy().astype(np.complex128)
+    if box:  # the gains are single-precision products of sines
+        assert np.abs(got_uc - want_uc).max() <= 3e-7 * np.abs(want_uc).max()
+        want_uc = got_uc
+    else:
+        assert np.array_equal(got_uc, want_uc)
     ref_A = oracle_mod.grad3d(want_uc).reshape(9, -1)
-    ref_tau = oracle_mod.sgs_tau3d(u64, nc).reshape(6, -1)
+    ref_tau = oracle_mod.sgs_tau3d(u64, nc, box=box).reshape(6, -1)
     uphys = np.stack([oracle_mod.irfftn(u64[c]) for c in range(3)])
     scale = float(np.abs(uphys).max()) ** 2
     eA = np.abs(A.cpu().numpy() - ref_A).max() / np.abs(ref_A).max()
