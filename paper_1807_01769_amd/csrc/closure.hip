@@ -90,24 +90,6 @@ __global__ void __launch_bounds__(kThr)
   out[q] = make_float4(x.x * y.x, x.y * y.y, x.z * y.z, x.w * y.w);
 }
 
-// g[3i+j] = i k_j u_i on the kept set, zero elsewhere (9 fields from 3)
-__global__ void __launch_bounds__(kThr)
-    k_grad(const cf* __restrict__ u, cf* __restrict__ g, int n, float kb) {
-  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
-  const int64_t q = (int64_t)blockIdx.x * kThr + threadIdx.x;
-  if (q >= ns) return;
-  const int ix = (int)(q % h), my = fmode((int)((q / h) % n), n), mz = fmode((int)(q / (h * n)), n);
-  const int K = (n - 1) / 3;
-  const bool keep = ix <= K && iabs(my) <= K && iabs(mz) <= K;
-  const float k[3] = {kb * (float)ix, kb * (float)my, kb * (float)mz};
-#pragma unroll
-  for (int i = 0; i < 3; i++) {
-    const cf v = keep ? u[i * ns + q] : cf{0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < 3; j++) g[(3 * i + j) * ns + q] = cf{-k[j] * v.im, k[j] * v.re};
-  }
-}
-
 // tau_s -= ubar_i ubar_j, then the trace is removed from the diagonal
 __global__ void __launch_bounds__(kThr)
     k_tau_finish(float* __restrict__ tau, const float* __restrict__ ub, int64_t np) {
@@ -170,16 +152,10 @@ __global__ void __launch_bounds__(kThr)
   }
 }
 
-// tend += P[-i k_j tau_ij^] on the kept set, k != 0 (P v = v - k (k.v)/|k|^2)
-__global__ void __launch_bounds__(kThr)
-    k_sgs(cf* __restrict__ tend, const cf* __restrict__ th, int n, float kb) {
-  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
-  const int64_t q = (int64_t)blockIdx.x * kThr + threadIdx.x;
-  if (q >= ns) return;
-  const int ix = (int)(q % h), my = fmode((int)((q / h) % n), n), mz = fmode((int)(q / (h * n)), n);
-  const int K = (n - 1) / 3;
-  if (!(ix <= K && iabs(my) <= K && iabs(mz) <= K) || (ix == 0 && my == 0 && mz == 0)) return;
-  const float k[3] = {kb * (float)ix, kb * (float)my, kb * (float)mz};
+// The subgrid term P[-i k_j tau_ij^] of one mode (k != 0; P v = v - k (k.v)/|k|^2)
+// from the six stress spectra th at element q, added to t[3].
+__device__ __forceinline__ void sgs_term(const cf* __restrict__ th, int64_t ns, int64_t q,
+                                         const float (&k)[3], cf (&t)[3]) {
   float sr[3] = {0.f, 0.f, 0.f}, si[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int c = 0; c < 6; c++) {
@@ -198,36 +174,62 @@ __global__ void __launch_bounds__(kThr)
   const float pi = (k[0] * si[0] + k[1] * si[1] + k[2] * si[2]) * inv;
 #pragma unroll
   for (int c = 0; c < 3; c++) {
-    cf v = tend[c * ns + q];
-    v.re += sr[c] - k[c] * pr;
-    v.im += si[c] - k[c] * pi;
-    tend[c * ns + q] = v;
+    t[c].re += sr[c] - k[c] * pr;
+    t[c].im += si[c] - k[c] * pi;
   }
 }
 
+// tend += P[-i k_j tau_ij^] on the kept set, k != 0
+__global__ void __launch_bounds__(kThr)
+    k_sgs(cf* __restrict__ tend, const cf* __restrict__ th, int n, float kb) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
+  const int64_t q = (int64_t)blockIdx.x * kThr + threadIdx.x;
+  if (q >= ns) return;
+  const int ix = (int)(q % h), my = fmode((int)((q / h) % n), n), mz = fmode((int)(q / (h * n)), n);
+  const int K = (n - 1) / 3;
+  if (!(ix <= K && iabs(my) <= K && iabs(mz) <= K) || (ix == 0 && my == 0 && mz == 0)) return;
+  const float k[3] = {kb * (float)ix, kb * (float)my, kb * (float)mz};
+  cf t[3] = {tend[q], tend[ns + q], tend[2 * ns + q]};
+  sgs_term(th, ns, q, k, t);
+#pragma unroll
+  for (int c = 0; c < 3; c++) tend[c * ns + q] = t[c];
+}
+
 // One Lawson stage combination on the kept set only (threads over the
-// compact M x M x H cube, blockIdx.y = component); E = exp(-nu |k|^2 dt) as
-// the product of the per-axis factors.
+// compact M x M x H cube, all three components of a mode per thread);
+// E = exp(-nu |k|^2 dt) as the product of the per-axis factors.  With th
+// (the six stress spectra), the subgrid term P[-i k_j tau_ij^] is added to
+// the stage tendency nl first.
 template <int MODE>
 __global__ void __launch_bounds__(kThr)
     k_lawson(cf* __restrict__ u, cf* __restrict__ acc, cf* __restrict__ v,
-             const cf* __restrict__ nl, const float* __restrict__ e1,
-             const float* __restrict__ eh1, int n, float dt) {
+             const cf* __restrict__ nl, const cf* __restrict__ th, const float* __restrict__ e1,
+             const float* __restrict__ eh1, int n, float kb, float dt) {
   const int K = (n - 1) / 3, M = 2 * K + 1, H = K + 1;
   const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
   const int64_t t = (int64_t)blockIdx.x * kThr + threadIdx.x;
   if (t >= (int64_t)M * M * H) return;
   const int ix = (int)(t % H), jy = (int)((t / H) % M), jz = (int)(t / ((int64_t)H * M));
   const int iy = jy <= K ? jy : jy + (n - M), iz = jz <= K ? jz : jz + (n - M);
-  const int64_t q = blockIdx.y * ns + ((int64_t)iz * n + iy) * h + ix;
+  const int64_t q = ((int64_t)iz * n + iy) * h + ix;
   const float E = e1[ix] * e1[iy] * e1[iz], Eh = eh1[ix] * eh1[iy] * eh1[iz];
-  cf a = acc[q];
-  const cf next = rk4_combine<MODE, float>(u[q], a, nl[q], E, Eh, dt);
-  if constexpr (MODE == kStage4) {
-    u[q] = next;
-  } else {
-    acc[q] = a;
-    v[q] = next;
+  cf k3[3] = {nl[q], nl[ns + q], nl[2 * ns + q]};
+  const int my = jy <= K ? jy : jy - M, mz = jz <= K ? jz : jz - M;
+  if (th && (ix != 0 || my != 0 || mz != 0)) {
+    const float k[3] = {kb * (float)ix, kb * (float)my, kb * (float)mz};
+    sgs_term(th, ns, q, k, k3);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    const int64_t qc = c * ns + q;
+    cf a = acc[qc];
+    const cf next = rk4_combine<MODE, float>(u[qc], a, k3[c], E, Eh, dt);
+    if constexpr (MODE == kStage4) {
+      u[qc] = next;
+    } else {
+      acc[qc] = a;
+      v[qc] = next;
+    }
   }
 }
 
@@ -282,7 +284,6 @@ struct fs_closure {
   float* uf = nullptr;      // fine physical velocity [3][nf^3]
   float* prod = nullptr;    // one fine physical product
   cf* cspec = nullptr;      // one coarse spectral field
-  cf* grad = nullptr;       // 9 coarse spectral gradient fields
   float* ub = nullptr;      // coarse physical filtered velocity [3][nc^3]
   void *wa = nullptr, *wb = nullptr;  // coarse transform workspaces for 9 fields
   int box = 0;              // FS_FILTER_BOX: box filter before the cutoff
@@ -309,7 +310,6 @@ fs_status fs_closure_create(fs_closure** out, fs_plan* fine, fs_plan* coarse) {
   const size_t o_uf = cv.take(sizeof(float) * 3 * phys_elems(nf));
   const size_t o_prod = cv.take(sizeof(float) * phys_elems(nf));
   const size_t o_cspec = cv.take(sizeof(cf) * spec_elems(nc));
-  const size_t o_grad = cv.take(sizeof(cf) * 9 * spec_elems(nc));
   const size_t o_ub = cv.take(sizeof(float) * 3 * phys_elems(nc));
   const size_t wfull = sizeof(cf) * 9 * coarse->p.ops.elems_full;
   const size_t o_wa = cv.take(wfull), o_wb = cv.take(wfull);
@@ -326,7 +326,6 @@ fs_status fs_closure_create(fs_closure** out, fs_plan* fine, fs_plan* coarse) {
   c->uf = (float*)(b + o_uf);
   c->prod = (float*)(b + o_prod);
   c->cspec = (cf*)(b + o_cspec);
-  c->grad = (cf*)(b + o_grad);
   c->ub = (float*)(b + o_ub);
   c->wa = b + o_wa;
   c->wb = b + o_wb;
@@ -374,11 +373,8 @@ fs_status fs_closure_samples(fs_closure* c, const void* fine_state, void* coarse
   hipLaunchKernelGGL(fs::k_cutoff, dim3(fs::blocks_for(nsc), 3), dim3(fs::kThr), 0, s, us, nf, uc,
                      nc, c->box);
   if (!fs::plan_ok(pc, "k_cutoff")) return FS_E_DEVICE;
-  pc->ops.fft_inv_n(pc, uc, c->ub, 3, c->wa, c->wb);
-  hipLaunchKernelGGL(fs::k_grad, dim3(fs::blocks_for(nsc)), dim3(fs::kThr), 0, s, (const cf*)uc,
-                     c->grad, nc, (float)(2.0 * M_PI / pc->L));
-  if (!fs::plan_ok(pc, "k_grad")) return FS_E_DEVICE;
-  pc->ops.fft_inv_n(pc, c->grad, A, 9, c->wa, c->wb);
+  pc->ops.fft_inv_n(pc, uc, c->ub, 3, c->wa, c->wb, false);
+  pc->ops.fft_inv_n(pc, uc, A, 9, c->wa, c->wb, true);  // the nine gradients
   // fine physical velocity (kept modes only)
   for (int i = 0; i < 3; i++) {
     hipLaunchKernelGGL(fs::k_mask, dim3(fs::blocks_for(nsf)), dim3(fs::kThr), 0, s, us + i * nsf,
@@ -447,7 +443,7 @@ struct fs_les {
   float inv_a = 1.f, clip = 0.f;
   fs::Six scale{};
   void* base = nullptr;
-  cf *acc = nullptr, *v = nullptr, *k = nullptr, *grad = nullptr, *th = nullptr;
+  cf *acc = nullptr, *v = nullptr, *k = nullptr, *th = nullptr;
   float *A = nullptr, *tau = nullptr;
   void *wa = nullptr, *wb = nullptr;
   hipGraphExec_t graph = nullptr;
@@ -456,18 +452,17 @@ struct fs_les {
 
 namespace {
 
-// tend = coarse tendency of `state` + P[-i k_j tau_ij^], tau = net(A(state))
-void les_tendency(fs_les* les, const void* state, cf* tend, bool fresh_alpha) {
+// tend = coarse tendency of `state` + P[-i k_j tau_ij^], tau = net(A(state)).
+// Inside a step (step = true) only the kept modes of tend are written and the
+// subgrid term is left to the combine, which reads the stress spectra.
+void les_tendency(fs_les* les, const void* state, cf* tend, bool fresh_alpha, bool step) {
   Plan* p = &les->plan->p;
-  p->ops.tendency(p, state, tend, fresh_alpha);
+  p->ops.tendency(p, state, tend, fresh_alpha, !step);
   if (!les->net) return;
   const int n = p->n;
   const int64_t ns = spec_elems(n), np = phys_elems(n);
   const float kb = (float)(2.0 * M_PI / p->L);
-  hipLaunchKernelGGL(fs::k_grad, dim3(fs::blocks_for(ns)), dim3(fs::kThr), 0, p->launch,
-                     (const cf*)state, les->grad, n, kb);
-  fs::plan_ok(p, "k_grad");
-  p->ops.fft_inv_n(p, les->grad, les->A, 9, les->wa, les->wb);
+  p->ops.fft_inv_n(p, state, les->A, 9, les->wa, les->wb, true);  // the nine gradients
   fs::StressMap sm;
   for (int c = 0; c < 6; c++) sm.scale[c] = les->scale.v[c];
   sm.clip = les->clip;
@@ -475,6 +470,7 @@ void les_tendency(fs_les* les, const void* state, cf* tend, bool fresh_alpha) {
                                 p->launch);
   fs::plan_ok(p, "k_mlp_forward_planar");
   p->ops.fft_fwd_n(p, les->tau, les->th, 6, les->wa, les->wb);
+  if (step) return;
   hipLaunchKernelGGL(fs::k_sgs, dim3(fs::blocks_for(ns)), dim3(fs::kThr), 0, p->launch, tend,
                      (const cf*)les->th, n, kb);
   fs::plan_ok(p, "k_sgs");
@@ -484,22 +480,24 @@ template <int MODE>
 void les_combine(fs_les* les, void* state) {
   Plan* p = &les->plan->p;
   const int n = p->n, K = (n - 1) / 3, M = 2 * K + 1, H = K + 1;
-  hipLaunchKernelGGL((fs::k_lawson<MODE>), dim3(fs::blocks_for((int64_t)M * M * H), 3),
+  hipLaunchKernelGGL((fs::k_lawson<MODE>), dim3(fs::blocks_for((int64_t)M * M * H)),
                      dim3(fs::kThr), 0, p->launch, (cf*)state, les->acc, les->v,
-                     (const cf*)les->k, (const float*)p->e1, (const float*)p->eh1, n, (float)p->dt);
+                     (const cf*)les->k, les->net ? (const cf*)les->th : nullptr,
+                     (const float*)p->e1, (const float*)p->eh1, n,
+                     (float)(2.0 * M_PI / p->L), (float)p->dt);
   fs::plan_ok(p, "k_lawson");
 }
 
 void les_step(fs_les* les, void* state) {
   Plan* p = &les->plan->p;
   if (p->ops.alpha && p->m2max >= 0) p->ops.alpha(p, state);
-  les_tendency(les, state, les->k, false);
+  les_tendency(les, state, les->k, false, true);
   les_combine<fs::kStage1>(les, state);
-  les_tendency(les, les->v, les->k, false);
+  les_tendency(les, les->v, les->k, false, true);
   les_combine<fs::kStage2>(les, state);
-  les_tendency(les, les->v, les->k, false);
+  les_tendency(les, les->v, les->k, false, true);
   les_combine<fs::kStage3>(les, state);
-  les_tendency(les, les->v, les->k, false);
+  les_tendency(les, les->v, les->k, false, true);
   les_combine<fs::kStage4>(les, state);
 }
 
@@ -570,7 +568,7 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
     const int64_t ns = spec_elems(n), np = phys_elems(n);
     Carver cv;
     const size_t o_acc = cv.take(sizeof(cf) * 3 * ns), o_v = cv.take(sizeof(cf) * 3 * ns),
-                 o_k = cv.take(sizeof(cf) * 3 * ns), o_grad = cv.take(sizeof(cf) * 9 * ns),
+                 o_k = cv.take(sizeof(cf) * 3 * ns),
                  o_th = cv.take(sizeof(cf) * 6 * ns), o_A = cv.take(sizeof(float) * 9 * np),
                  o_tau = cv.take(sizeof(float) * 6 * np),
                  o_wa = cv.take(sizeof(cf) * 9 * coarse->p.ops.elems_full),
@@ -584,7 +582,6 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
     les->acc = (cf*)(b + o_acc);
     les->v = (cf*)(b + o_v);
     les->k = (cf*)(b + o_k);
-    les->grad = (cf*)(b + o_grad);
     les->th = (cf*)(b + o_th);
     les->A = (float*)(b + o_A);
     les->tau = (float*)(b + o_tau);
@@ -610,7 +607,7 @@ fs_status fs_les_tendency(fs_les* les, const void* state, void* tend) {
   if (!les->net) return fs_tendency(les->plan, state, tend);
   Plan* p = &les->plan->p;
   if (p->failed) return fail(FS_E_DEVICE, "plan failed earlier");
-  les_tendency(les, state, (cf*)tend, true);
+  les_tendency(les, state, (cf*)tend, true, false);
   return p->failed ? FS_E_DEVICE : FS_OK;
 }
 

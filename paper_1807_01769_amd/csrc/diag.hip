@@ -578,7 +578,7 @@ void launch_structure(Plan* p, const void* state, int nr, const int* r, int pmax
     launched(p, "k_vel_comp");
     p->end(KID_DIAG);
     if (nd == 3)
-      p->ops.fft_inv_n(p, spec, phys, 1, A, B);
+      p->ops.fft_inv_n(p, spec, phys, 1, A, B, false);
     else
       p->ops.fft_inv(p, spec, phys);
     p->begin(KID_DIAG);

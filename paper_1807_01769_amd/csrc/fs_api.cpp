@@ -457,7 +457,7 @@ fs_status fs_tendency(fs_plan* plan, const void* state, void* tend) {
   if (!state || !tend) return fail(FS_E_INVALID, "NULL array");
   if (state == tend) return fail(FS_E_INVALID, "state and tend must not overlap");
   if (fs_status st = check_finite(&plan->p)) return st;
-  plan->p.ops.tendency(&plan->p, state, tend, true);
+  plan->p.ops.tendency(&plan->p, state, tend, true, true);
   return device_status(&plan->p);
 }
 

@@ -33,16 +33,18 @@ struct Ops {
   // one RK4 stage (mode 1..4) after its first pass; do_p1 = 0 skips the next
   // stage's inverse transforms at the end of the last step
   void (*stage)(Plan*, void* state, int mode, int do_p1);
-  // tendency of `state` into `out` (all elements written); with
-  // fresh_alpha the forcing coefficient is recomputed from `state`,
-  // otherwise the one left on the device by the last `alpha` call is used
-  void (*tendency)(Plan*, const void* state, void* out, bool fresh_alpha);
+  // tendency of `state` into `out` on the kept modes (with fill, zeros on
+  // every other element); with fresh_alpha the forcing coefficient is
+  // recomputed from `state`, otherwise the one left on the device by the
+  // last `alpha` call is used
+  void (*tendency)(Plan*, const void* state, void* out, bool fresh_alpha, bool fill);
   void (*fft_fwd)(Plan*, const void* phys, void* spec);
   void (*fft_inv)(Plan*, const void* spec, void* phys);
   // nf stacked fields at once through caller workspaces wa, wb of
-  // nf * elems_full complex elements each (3D only; may be null)
+  // nf * elems_full complex elements each (3D only; may be null); with grad
+  // the input is a velocity state and the nine outputs its gradients
   void (*fft_fwd_n)(Plan*, const void* phys, void* spec, int nf, void* wa, void* wb);
-  void (*fft_inv_n)(Plan*, const void* spec, void* phys, int nf, void* wa, void* wb);
+  void (*fft_inv_n)(Plan*, const void* spec, void* phys, int nf, void* wa, void* wb, bool grad);
   // forcing coefficient from the state (3D only; may be null)
   void (*alpha)(Plan*, const void* state);
   // adaptive step: dt from the velocity maximum of the step, decay tables,

@@ -555,10 +555,13 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
 // z passes take the field from blockIdx.y; the y and x passes treat the F*N
 // z-planes of the stack as rows.
 // ---------------------------------------------------------------------------
-// inverse z: spec -> Wm(FULL)[F][N][XT][N][16]; grid (N * XT * SUB, F)
-template <typename T, int N>
+// inverse z: spec -> Wm(FULL)[F][N][XT][N][16]; grid (N * XT * SUB, F).
+// GRAD: spec is a velocity state [3][N][N][N/2+1] and field f = 3i + j of the
+// output is the gradient d u_i / d x_j, i k_j u_i on the kept modes (kb = 2 pi / L).
+template <typename T, int N, bool GRAD = false>
 __global__ void __launch_bounds__((Strided<T, N>::THREADS))
-    k3f_z_inv(const cx<T>* __restrict__ spec, cx<T>* __restrict__ w, const cx<T>* __restrict__ tw) {
+    k3f_z_inv(const cx<T>* __restrict__ spec, cx<T>* __restrict__ w, const cx<T>* __restrict__ tw,
+              T kb = T(0)) {
   using G = Geo<N, true>;
   using C = Strided<T, N>;
   constexpr int P = G::P, NH = N / 2 + 1;
@@ -570,12 +573,26 @@ __global__ void __launch_bounds__((Strided<T, N>::THREADS))
   blk /= C::SUB;
   const int xt = blk % G::XT, iy = blk / G::XT;
   const int mx = xt * kTile + sub * C::LB + b;
-  spec += (size_t)blockIdx.y * N * N * NH;
+  spec += (size_t)(GRAD ? blockIdx.y / 3 : blockIdx.y) * N * N * NH;
   w += (size_t)blockIdx.y * N * G::XT * N * kTile;
   cx<T> v[1][8];
+  if constexpr (GRAD) {
+    using GK = Geo<N, false>;
+    const int j = blockIdx.y % 3, my = iy <= N / 2 ? iy : iy - N;
+    const bool col = mx <= GK::K && my <= GK::K && my >= -GK::K;
 #pragma unroll
-  for (int e = 0; e < 8; e++)
-    v[0][e] = mx < G::H ? spec[((size_t)(t + e * P) * N + iy) * NH + mx] : cx<T>{0, 0};
+    for (int e = 0; e < 8; e++) {
+      const int iz = t + e * P, mz = iz <= N / 2 ? iz : iz - N;
+      const bool keep = col && mz <= GK::K && mz >= -GK::K;
+      const cx<T> u = keep ? spec[((size_t)iz * N + iy) * NH + mx] : cx<T>{0, 0};
+      const T kj = kb * (T)(j == 0 ? mx : (j == 1 ? my : mz));
+      v[0][e] = mul_i(cscale(u, kj));
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; e++)
+      v[0][e] = mx < G::H ? spec[((size_t)(t + e * P) * N + iy) * NH + mx] : cx<T>{0, 0};
+  }
   fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
   const size_t zstride = (size_t)G::XT * N * kTile;
   cx<T>* dst = w + ((size_t)xt * N + iy) * kTile + sub * C::LB + b;

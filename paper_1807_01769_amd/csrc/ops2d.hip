@@ -82,8 +82,8 @@ struct L2 {
       default: yk<kStage4>(p, state, nullptr, do_p1); break;
     }
   }
-  static void tendency(Plan* p, const void* state, void* out, bool) {
-    launch_fill<T>(p, out, (size_t)NF * N * (N / 2 + 1));
+  static void tendency(Plan* p, const void* state, void* out, bool, bool fill) {
+    if (fill) launch_fill<T>(p, out, (size_t)NF * N * (N / 2 + 1));
     p1(p, state);
     x(p);
     yk<kModeTend>(p, (void*)state, out, 0);

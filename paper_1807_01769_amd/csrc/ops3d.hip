@@ -110,8 +110,8 @@ struct L3 {
       default: zk<kStage4>(p, state, nullptr, do_p1); break;
     }
   }
-  static void tendency(Plan* p, const void* state, void* out, bool fresh_alpha) {
-    launch_fill<T>(p, out, (size_t)NC * N * N * (N / 2 + 1));
+  static void tendency(Plan* p, const void* state, void* out, bool fresh_alpha, bool fill) {
+    if (fill) launch_fill<T>(p, out, (size_t)NC * N * N * (N / 2 + 1));
     if (p->m2max >= 0 && fresh_alpha) launch_alpha<T>(p, state);
     p1(p, state);
     yinv(p);
@@ -119,11 +119,19 @@ struct L3 {
     yfwd(p);
     zk<kModeTend>(p, (void*)state, out, 0);
   }
-  // nf stacked fields through caller workspaces wa, wb (elems_full each per field)
-  static void fft_inv_n(Plan* p, const void* spec, void* phys, int nf, void* wa, void* wb) {
+  // nf stacked fields through caller workspaces wa, wb (elems_full each per
+  // field); grad: spec is a velocity state and the nf = 9 outputs are its
+  // gradients d u_i / d x_j (field 3i + j) on the kept modes
+  static void fft_inv_n(Plan* p, const void* spec, void* phys, int nf, void* wa, void* wb,
+                        bool grad) {
     p->begin(KID_FFT);
-    hipLaunchKernelGGL((k3f_z_inv<T, N>), dim3(N * GF::XT * C::SUB, nf), dim3(C::THREADS), 0,
-                       p->launch, (const cx<T>*)spec, (cx<T>*)wa, TW(p));
+    if (grad)
+      hipLaunchKernelGGL((k3f_z_inv<T, N, true>), dim3(N * GF::XT * C::SUB, 9), dim3(C::THREADS),
+                         0, p->launch, (const cx<T>*)spec, (cx<T>*)wa, TW(p),
+                         (T)(2.0 * M_PI / p->L));
+    else
+      hipLaunchKernelGGL((k3f_z_inv<T, N>), dim3(N * GF::XT * C::SUB, nf), dim3(C::THREADS), 0,
+                         p->launch, (const cx<T>*)spec, (cx<T>*)wa, TW(p), (T)0);
     launched(p, "k3f_z_inv");
     p->end(KID_FFT);
     p->begin(KID_FFT);
@@ -158,7 +166,7 @@ struct L3 {
     p->end(KID_FFT);
   }
   static void fft_inv(Plan* p, const void* spec, void* phys) {
-    fft_inv_n(p, spec, phys, 1, p->bufA, p->bufB);
+    fft_inv_n(p, spec, phys, 1, p->bufA, p->bufB, false);
   }
   static void fft_fwd(Plan* p, const void* phys, void* spec) {
     fft_fwd_n(p, phys, spec, 1, p->bufA, p->bufB);
