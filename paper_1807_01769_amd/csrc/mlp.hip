@@ -40,6 +40,10 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + kHid * kIn, OFF_W2 = OFF_B1 + kHid,
 // lane-ordered BF16 blocks: W1 (4), W2 (4x4), W3 (4), W3^T (4), W2^T (4x4)
 constexpr int BLK_W1 = 0, BLK_W2 = 4, BLK_W3 = 20, BLK_W3T = 24, BLK_W2T = 28, NBLK = 44;
 constexpr int kThreads = 256, kWaves = kThreads / 64;
+// Forward grids stop at one resident round (256 CUs x 3 four-wave blocks at
+// the kernels' 3 waves per SIMD): every wave loads the network into
+// registers once and runs over several point tiles.
+constexpr int kForwardBlocks = 768;
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float x) {
@@ -424,7 +428,7 @@ void mlp_forward_planar_launch(Mlp* net, const float* A, int64_t P, float inv_a,
                                StressMap sm, hipStream_t s) {
   const int64_t tiles = (P + 15) / 16;
   int64_t blocks = (tiles + kWaves - 1) / kWaves;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > kForwardBlocks) blocks = kForwardBlocks;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_mlp_forward_planar, dim3((unsigned)blocks), dim3(kThreads), 0, s, A, P,
                      inv_a, tau, sm, net->packed, net->w);
@@ -434,7 +438,7 @@ void mlp_forward_launch(Mlp* net, const void* x, float* y, int64_t P, const floa
                         hipStream_t s) {
   const int64_t tiles = (P + 15) / 16;
   int64_t blocks = (tiles + kWaves - 1) / kWaves;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > kForwardBlocks) blocks = kForwardBlocks;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)blocks), dim3(kThreads), 0, s, (const short*)x,
                      y, P, net->packed, net->w, out_scale);
