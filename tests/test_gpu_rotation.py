@@ -20,12 +20,13 @@ def fs():
     return _fs
 
 
-@pytest.mark.parametrize("prec,scheme,graphs", [("f32", "rk4", True), ("f32", "rk4", False),
-                                                ("f64", "rk4", True), ("f32", "rk2", True),
-                                                ("f64", "rk2", True)])
-def test_rotating_steps(fs, oracle_mod, prec, scheme, graphs):
-    print(f"case rotation 3d n=32 {prec} {scheme} graphs={graphs}", flush=True)
-    n, nu, dt, f, steps = 32, 2e-3, 4e-3, 3.0, 5
+@pytest.mark.parametrize("n,prec,scheme,graphs", [(32, "f32", "rk4", True), (32, "f32", "rk4", False),
+                                                  (32, "f64", "rk4", True), (32, "f32", "rk2", True),
+                                                  (32, "f64", "rk2", True), (64, "f32", "rk4", True),
+                                                  (64, "f64", "rk4", False)])
+def test_rotating_steps(fs, oracle_mod, n, prec, scheme, graphs):
+    print(f"case rotation 3d n={n} {prec} {scheme} graphs={graphs}", flush=True)
+    nu, dt, f, steps = 2e-3, 4e-3, 3.0, 5 if n == 32 else 2
     cd = np.complex64 if prec == "f32" else np.complex128
     u = I.random_solenoidal_3d(n, seed=111, dtype=cd)
     plan = fs.Plan(n, nu=nu, dt=dt, precision=prec, forcing_power=0.05, rotation=f,
@@ -61,4 +62,31 @@ def test_helical_inertial_wave_fp64(fs):
     k2, T = float(k @ k), dt * steps
     want = u * np.exp(-nu * k2 * T - 1j * f * m[2] / np.sqrt(k2) * T)
     assert np.abs(got - want).max() <= 1e-13
+    plan.close()
+
+
+def test_inertial_wave_512(fs):
+    """The exact inertial wave of one helical mode through the 512^3 FP32
+    kernels (the rotating z pass at full size)."""
+    n, nu, f, dt, steps = 512, 2e-4, 3.0, 1e-3, 4
+    m = (5, -3, 7)
+    k = np.array(m, float)
+    kh = k / np.linalg.norm(k)
+    e1 = np.cross(kh, [0.0, 0.0, 1.0])
+    e1 /= np.linalg.norm(e1)
+    h = (e1 - 1j * np.cross(kh, e1)) / np.sqrt(2)
+    u = np.zeros((3, n, n, n // 2 + 1), np.complex64)
+    u[:, m[2] % n, m[1] % n, m[0]] = 0.4 * h
+    plan = fs.Plan(n, nu=nu, dt=dt, rotation=f)
+    d = torch.from_numpy(u).cuda()
+    plan.step(d, steps)
+    got = d[:, m[2] % n, m[1] % n, m[0]].cpu().numpy().astype(np.complex128)
+    d[:, m[2] % n, m[1] % n, m[0]] = 0
+    rest = torch.view_as_real(d).abs().max().item()  # every other mode stays (rounding-) zero
+    k2, T = float(k @ k), dt * steps
+    want = 0.4 * h * np.exp(-nu * k2 * T - 1j * f * m[2] / np.sqrt(k2) * T)
+    print(f"inertial wave 512^3: err {np.abs(got - want).max():.2e}, other modes {rest:.1e}",
+          flush=True)
+    assert np.abs(got - want).max() <= 2e-6
+    assert rest <= 1e-6
     plan.close()

@@ -53,12 +53,14 @@ def test_strat3d_tendency(fs, oracle_mod, n, prec):
                                                   (64, "f32", "rk4", False),
                                                   (64, "f64", "rk4", True),
                                                   (32, "f32", "rk2", True),
-                                                  (32, "f64", "rk2", False)])
+                                                  (32, "f64", "rk2", False),
+                                                  (128, "f32", "rk4", True)])
 def test_strat3d_steps(fs, oracle_mod, n, prec, scheme, graphs):
     print(f"case boussinesq3d steps n={n} {prec} {scheme} graphs={graphs}", flush=True)
     cd = np.complex64 if prec == "f32" else np.complex128
     s = _state(n, 211, cd)
-    nu, dt, N2, steps, P = 2e-3, 4e-3, 4.0, 3, 0.05
+    nu, dt, N2, P = 2e-3, 4e-3, 4.0, 0.05
+    steps = 3 if n < 128 else 1
     plan = fs.Plan(n, precision=prec, nu=nu, dt=dt, forcing_power=P, boussinesq=True, n2=N2,
                    scheme=scheme, graphs=graphs)
     d = torch.from_numpy(s).cuda()
@@ -97,4 +99,36 @@ def test_plane_gravity_wave_fp64(fs):
     want[:3, m[2], m[1], m[0]] = dec * (A * np.cos(om * T) + B / N * np.sin(om * T)) * ep
     want[3, m[2], m[1], m[0]] = dec * (B * np.cos(om * T) - N * A * np.sin(om * T))
     assert np.abs(got - want).max() <= 1e-13
+    plan.close()
+
+
+def test_plane_gravity_wave_512(fs):
+    """The exact plane internal gravity wave through the 512^3 FP32 stratified
+    kernels (seven-field x and z passes at full size)."""
+    n, nu, N2, dt, steps = 512, 2e-4, 9.0, 1e-3, 4
+    m = (6, 2, -5)
+    k = np.array(m, float)
+    kh = k / np.linalg.norm(k)
+    q = np.array([0.0, 0.0, 1.0]) - kh * kh[2]
+    g = np.linalg.norm(q)
+    ep = q / g
+    A, B = 0.3 - 0.1j, 0.2 + 0.4j
+    s = np.zeros((4, n, n, n // 2 + 1), np.complex64)
+    s[:3, m[2] % n, m[1] % n, m[0]] = A * ep
+    s[3, m[2] % n, m[1] % n, m[0]] = B
+    plan = fs.Plan(n, nu=nu, dt=dt, boussinesq=True, n2=N2)
+    d = torch.from_numpy(s).cuda()
+    del s
+    plan.step(d, steps)
+    got = d[:, m[2] % n, m[1] % n, m[0]].cpu().numpy().astype(np.complex128)
+    d[:, m[2] % n, m[1] % n, m[0]] = 0
+    rest = torch.view_as_real(d).abs().max().item()  # every other mode stays (rounding-) zero
+    T, N = dt * steps, np.sqrt(N2)
+    om, dec = N * g, np.exp(-nu * float(k @ k) * T)
+    want = np.concatenate([dec * (A * np.cos(om * T) + B / N * np.sin(om * T)) * ep,
+                           [dec * (B * np.cos(om * T) - N * A * np.sin(om * T))]])
+    print(f"gravity wave 512^3: err {np.abs(got - want).max():.2e}, other modes {rest:.1e}",
+          flush=True)
+    assert np.abs(got - want).max() <= 2e-6
+    assert rest <= 1e-6
     plan.close()
