@@ -227,6 +227,47 @@ def bench_ensemble(args) -> int:
     return 0
 
 
+# The paper's code comparison times ten RK4 steps of its 2D solver on random
+# initial fields, sequential on a Xeon E5-2695v4 (section "CFD pseudo-spectral
+# code comparisons", bidimensional table: 0.54 s at 512^2, 2.69 s at 1024^2).
+PAPER_2D_TEN_STEPS_S = {512: 0.54, 1024: 2.69}
+
+
+def bench_2d(args) -> int:
+    """Ten RK4 steps of one 2D plan (FP64, the paper's precision) on a random
+    vorticity field: the workload of the paper's 2D code comparison, timed as
+    the mean of repeated ten-step calls after a warm-up."""
+    import numpy as np
+    import torch
+    from paper_1807_01769_amd import fs, inputs as I
+
+    n = args.n
+    w = I.random_vorticity_2d(n, 1000, lambda k: k * np.exp(-(k / 6.0) ** 2))
+    d = torch.from_numpy(w).cuda()
+    plan = fs.Plan(n, ndim=2, precision="f64", nu=ENS_NU, dt=ENS_DT)
+    plan.step(d, 10)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.step(d, 10)
+    torch.cuda.synchronize()
+    ten = (time.perf_counter() - t0) / reps
+    finite = bool(torch.isfinite(torch.view_as_real(d)).all())
+    plan.close()
+    ref = PAPER_2D_TEN_STEPS_S.get(n)
+    out = {"metric": "2D RK4: seconds for ten steps (the paper's code-comparison workload)",
+           "value": ten, "unit": "s / 10 steps", "n_gpus": 1, "steps": 10 * reps,
+           "higher_is_better": False, "dtype": "f64", "data": "synthetic", "finite": finite,
+           "config": {"workload": f"2D NS {n}^2, FP64, random vorticity E(k)~k exp(-(k/6)^2), "
+                                  f"nu={ENS_NU}, dt={ENS_DT}, one plan, ten steps per call"},
+           "paper_context": ({"seconds": ref, "hardware": "Xeon E5-2695v4, sequential, FluidSim"}
+                             if ref else None),
+           "vs_baseline": None}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 MLP_FLOP_PER_POINT = 2 * (9 * 64 + 64 * 64 + 64 * 6)  # forward multiply-adds x 2
 
 
@@ -291,7 +332,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--graphs", action="store_true",
                     help="time graph-launched steps (no per-kernel events)")
-    ap.add_argument("--workload", choices=["3d", "ensemble"], default="3d")
+    ap.add_argument("--workload", choices=["3d", "ensemble", "2d"], default="3d")
     ap.add_argument("--ens-steps", type=int, default=200)
     ap.add_argument("--les-n", type=int, default=64,
                     help="LES grid of the closure speedup measurement (0 = skip)")
@@ -317,6 +358,8 @@ def main() -> int:
         return 1
     if args.workload == "ensemble":
         return bench_ensemble(args)
+    if args.workload == "2d":
+        return bench_2d(args)
     n = args.n
     dev = torch.device("cuda:0")
     if args.calib_copy_gib > 0:
