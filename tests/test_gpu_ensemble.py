@@ -49,3 +49,25 @@ def test_ensemble_matches_single_runs_and_oracle(fs, oracle_mod, graphs, autotun
         print(f"run {r} n={n}: vs alone {e_alone:.2e}, vs oracle {e_ref:.2e}", flush=True)
         assert e_alone <= 1e-6
         assert e_ref <= 1e-5
+
+
+def test_full_ensemble_200_steps(fs, oracle_mod):
+    """The full configuration: 256 runs (128 at 128^2, 96 at 256^2, 32 at
+    512^2), 200 RK4 steps in one graph launch; the first and last run of
+    every size class against the FP64 oracle's 200 steps."""
+    print("case full ensemble 256 runs, 200 steps", flush=True)
+    nu, dt, steps = 1e-4, 5e-4, 200
+    sizes = I.ensemble_sizes()
+    fields = [I.ensemble_vorticity(r, n).astype(np.complex64) for r, n in enumerate(sizes)]
+    with fs.Ensemble(sizes, nu=nu, dt=dt) as ens:
+        st = ens.pack(fields)
+        ens.step(st, steps)
+        torch.cuda.synchronize()
+        picks = [0, 127, 128, 223, 224, 255]
+        got = {r: ens.unpack(st, r).cpu().numpy() for r in picks}
+    for r in picks:
+        n = sizes[r]
+        ref = oracle_mod.step2d(fields[r].astype(np.complex128), nu, dt, steps)
+        e = _rel(got[r].astype(np.complex128), ref, n)
+        print(f"run {r} n={n}: 200 steps vs oracle {e:.2e}", flush=True)
+        assert e <= 1e-5
