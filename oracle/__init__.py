@@ -126,6 +126,7 @@ def lib():
         L.or_strat_propagate.argtypes = [i, d, d, d, d, vp, vp]
         L.or_tendency3d_strat.argtypes = [i, d, vp, d, d, d, vp]
         L.or_step3d_strat.argtypes = [i, d, d, d, d, d, d, d, i, vp, i]
+        L.or_tendency3d_modes.argtypes = [i, d, vp, i, vp, vp]
         L.or_structure.argtypes = [i, i, d, vp, i, vp, i, vp]
         L.or_step2d_strat.argtypes = [i, d, d, d, d, vp, i]
         L.or_spectra1d2d.argtypes = [i, d, vp, vp]
@@ -307,6 +308,16 @@ def structure(state, ndim, r, pmax, L=2 * np.pi):
     lib().or_structure(int(ndim), n, float(L), _p(a), len(rr), rr.ctypes.data, int(pmax), _p(out))
     out = out.reshape(2, len(rr), pmax)
     return out[0], out[1]
+
+
+def tendency3d_modes(uh, modes, L=2 * np.pi):
+    """The 3D tendency (no forcing) at the given modes (mx >= 0, my, mz) by the
+    direct Galerkin triad sum; returns [len(modes)][3] complex."""
+    u = _c128(uh)
+    m = np.ascontiguousarray(np.asarray(modes, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((m.shape[0], 3), np.complex128)
+    lib().or_tendency3d_modes(u.shape[1], float(L), _p(u), m.shape[0], m.ctypes.data, _p(out))
+    return out
 
 
 def step3d_rot(uh, nu, dt, f, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0, scheme=4):

@@ -303,6 +303,64 @@ void or_tendency3d(int n, double L, const cplx *uh, double alpha, double kf_min,
   free(ph);
 }
 
+/* The 3D tendency (no forcing) at single modes by the direct Galerkin sum of
+ * the rotational form: (u x w)^(k) = sum over kept p, q = k - p kept of
+ * u_hat(p) x (i q x u_hat(q)), then the projection and the mean-mode rule.
+ * u_hat at negative kx is the conjugate of the stored mode.  modes: nm
+ * triples (mx >= 0, my, mz); out: nm x 3 complex values. */
+static cplx u_at(int n, const cplx *uh, int c, int mx, int my, int mz) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
+  int conj_ = 0;
+  if (mx < 0) {
+    mx = -mx;
+    my = -my;
+    mz = -mz;
+    conj_ = 1;
+  }
+  const int64_t q = ((int64_t)((mz + n) % n) * n + (my + n) % n) * h + mx;
+  const cplx v = uh[c * ns + q];
+  return conj_ ? conj(v) : v;
+}
+
+void or_tendency3d_modes(int n, double L, const cplx *uh, int nm, const int *modes, cplx *out) {
+  const int K = (n - 1) / 3;
+  const double kb = 2.0 * M_PI / L;
+#pragma omp parallel for schedule(dynamic)
+  for (int t = 0; t < nm; t++) {
+    const int kx = modes[3 * t], ky = modes[3 * t + 1], kz = modes[3 * t + 2];
+    cplx acc[3] = {0, 0, 0};
+    for (int pz = -K; pz <= K; pz++) {
+      const int qz = kz - pz;
+      if (qz < -K || qz > K) continue;
+      for (int py = -K; py <= K; py++) {
+        const int qy = ky - py;
+        if (qy < -K || qy > K) continue;
+        for (int px = -K; px <= K; px++) {
+          const int qx = kx - px;
+          if (qx < -K || qx > K) continue;
+          cplx up[3], uq[3];
+          for (int c = 0; c < 3; c++) {
+            up[c] = u_at(n, uh, c, px, py, pz);
+            uq[c] = u_at(n, uh, c, qx, qy, qz);
+          }
+          const double q3[3] = {kb * qx, kb * qy, kb * qz};
+          /* w(q) = i q x u(q) */
+          const cplx w[3] = {I * (q3[1] * uq[2] - q3[2] * uq[1]), I * (q3[2] * uq[0] - q3[0] * uq[2]),
+                             I * (q3[0] * uq[1] - q3[1] * uq[0])};
+          acc[0] += up[1] * w[2] - up[2] * w[1];
+          acc[1] += up[2] * w[0] - up[0] * w[2];
+          acc[2] += up[0] * w[1] - up[1] * w[0];
+        }
+      }
+    }
+    const double k3[3] = {kb * kx, kb * ky, kb * kz};
+    const double k2 = k3[0] * k3[0] + k3[1] * k3[1] + k3[2] * k3[2];
+    const int keep = abs(kx) <= K && abs(ky) <= K && abs(kz) <= K && k2 > 0;
+    const cplx kp = keep ? (k3[0] * acc[0] + k3[1] * acc[1] + k3[2] * acc[2]) / k2 : 0;
+    for (int c = 0; c < 3; c++) out[3 * t + c] = keep ? acc[c] - k3[c] * kp : 0;
+  }
+}
+
 /* Constant-power forcing coefficient: alpha = P / sum_band w |u_hat|^2, so
  * that the injected power sum w Re(u_hat* . alpha u_hat) equals P; 0 when
  * the band holds no energy or P == 0. */

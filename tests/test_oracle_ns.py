@@ -334,3 +334,18 @@ def test_input_generators(oracle_mod):
     w0 = I.tg_plus_noise_2d(128)
     noise = w0 - I.taylor_green_2d(128)
     assert abs(np.sqrt(np.sum(kept_weight(128, 2) * np.abs(noise) ** 2)) - 1e-2) <= 1e-15
+
+
+def test_tendency3d_modes_direct_sum_equals_fft_form(oracle_mod):
+    """The direct triad sum at single modes (used for full-size sampled checks)
+    equals the pseudo-spectral tendency at every sampled mode, including
+    kx = 0, the mean mode and modes outside the kept cube."""
+    n = 16
+    u = I.random_solenoidal_3d(n, seed=707)
+    full = oracle_mod.tendency3d(u)
+    modes = [(0, 0, 0), (1, 0, 0), (0, 2, -3), (3, -4, 5), (5, 5, -5), (2, -1, 0), (0, -5, 1),
+             (6, 0, 0), (4, 7, -2)]
+    got = oracle_mod.tendency3d_modes(u, modes)
+    for t, (mx, my, mz) in enumerate(modes):
+        want = full[:, mz % n, my % n, mx]
+        assert np.abs(got[t] - want).max() <= 1e-13 * np.abs(full).max(), (mx, my, mz)
