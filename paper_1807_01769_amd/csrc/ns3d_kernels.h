@@ -218,12 +218,13 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
 }
 
 // The fused z passes keep three components plus a transform line in registers
-// (at most 512 threads per block).  In single precision their twiddles come
+// (at most 512 threads per block below N = 1024; at 1024, 1024-thread blocks of
+// eight lines, so a block covers half of each 128-byte row instead of a quarter).  In single precision their twiddles come
 // from a copy of the table in LDS and the compiler is asked for 4 waves per
 // SIMD (two blocks per CU), so the memory phases of one block overlap the
 // transforms of the other; double precision keeps the register budget.
 template <typename T, int N>
-using ZCfg = Strided<T, N, cmin(kTile, cmax(1, 512 / (N / 8)))>;
+using ZCfg = Strided<T, N, cmin(kTile, cmax(1, (N >= 1024 ? 1024 : 512) / (N / 8)))>;
 // linear propagator of a fused z pass
 enum LinearProp : int { kPropVisc = 0, kPropRot = 1, kPropStrat = 2 };
 template <typename T, int PROP = kPropVisc>
