@@ -71,7 +71,8 @@ lib.fs_status_str.restype = C.c_char_p
 lib.fs_last_error.argtypes = []
 lib.fs_last_error.restype = C.c_char_p
 for _f in ("fs_plan_create", "fs_plan_destroy", "fs_plan_set_stream", "fs_state_elems",
-           "fs_workspace_bytes", "fs_plan_workspace_bytes", "fs_spectrum_bins", "fs_fft_forward", "fs_fft_inverse",
+           "fs_workspace_bytes", "fs_plan_workspace_bytes", "fs_spectrum_bins",
+           "fs_fft_forward", "fs_fft_inverse",
            "fs_tendency", "fs_step_rk4", "fs_energy_spectrum", "fs_energy_transfer",
            "fs_energy_spectra_1d", "fs_structure_functions", "fs_plan_time",
            "fs_profile_read"):
