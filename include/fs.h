@@ -297,7 +297,8 @@ fs_status fs_profile_read(fs_plan *plan, double *ms, long *counts, const char **
  *
  * fs_ensemble_create: nruns runs with grid sizes n[r] in {64, 128, 256, 512}
  * sharing L, nu, dt (opts: ndim must be 2, precision FS_F32, no forcing;
- * flags FS_NO_GRAPH, FS_NO_AUTOTUNE).  The packed state is the concatenation
+ * flags FS_NO_GRAPH, FS_NO_AUTOTUNE; fixed-dt RK4, no rotation or buoyancy,
+ * no caller workspace).  The packed state is the concatenation
  * of the runs' 2D states, run r at complex offset offsets[r] (see
  * fs_ensemble_offsets).  Runs of equal size form a class; at creation the
  * block schedule of every class is chosen by timing candidates on the

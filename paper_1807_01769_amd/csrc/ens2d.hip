@@ -314,6 +314,11 @@ fs_status fs_ensemble_create(fs_ensemble** out, int nruns, const int* n, double 
     fs::set_error("unsupported flags for an ensemble");
     return FS_E_INVALID;
   }
+  if (o.scheme != FS_SCHEME_RK4 || o.cfl != 0.0 || o.n2 != 0.0 || o.rotation != 0.0 ||
+      o.workspace) {
+    fs::set_error("ensembles step with fixed-dt RK4 and allocate their own workspace");
+    return FS_E_UNSUPPORTED;
+  }
   for (int r = 0; r < nruns; r++)
     if (!fs::supported_size(n[r])) {
       fs::set_error("run %d: n = %d, ensemble sizes are 64, 128, 256, 512", r, n[r]);

@@ -134,6 +134,11 @@ def test_binding_imports_and_needs_device():
     (1, [64], {"ndim": 3}, -1),
     (1, [64], {"forcing_power": 1.0}, -2),
     (1, [64], {"flags": 0x2}, -1),
+    (1, [64], {"flags": 0x10}, -1),
+    (1, [64], {"scheme": 2}, -2),
+    (1, [64], {"cfl": 0.5}, -2),
+    (1, [64], {"rotation": 1.0}, -2),
+    (1, [64], {"workspace": 1 << 20, "workspace_bytes": 1 << 30}, -2),
 ])
 def test_ensemble_create_validates(lib, nruns, sizes, kw, expect):
     lib.fs_ensemble_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int),
