@@ -189,8 +189,9 @@ fs_status configure(Plan* p, int n, double L, double nu, double dt, const fs_pla
     if (!(isfin(o.forcing_kmin) && isfin(o.forcing_kmax) && o.forcing_kmin >= 0 &&
           o.forcing_kmax >= o.forcing_kmin && o.forcing_kmax > 0))
       return fail(FS_E_INVALID, "forcing band must satisfy 0 <= kmin <= kmax, kmax > 0");
-    bw = (int)std::floor(o.forcing_kmax / kb);
-    if (bw > K) return fail(FS_E_INVALID, "forcing band reaches beyond the dealiased modes");
+    const double bwd = std::floor(o.forcing_kmax / kb);  // checked before the conversion
+    if (!(bwd <= K)) return fail(FS_E_INVALID, "forcing band reaches beyond the dealiased modes");
+    bw = (int)bwd;
     // integer |m|^2 range, evaluated as |k| = kb sqrt(m2) in FP64
     m2min = 1 << 30;
     for (int m2 = 1; m2 <= 3 * bw * bw; m2++) {

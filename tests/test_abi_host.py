@@ -72,6 +72,7 @@ def _create(lib, n, L, nu, dt, **kw):
     ((64, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 3.0, "forcing_kmax": 2.0}, -1),
     ((16, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 2.0, "forcing_kmax": 9.0}, -1),
     ((64, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 1.1, "forcing_kmax": 1.2}, -1),
+    ((64, 6.28, 0.1, 0.01), {"forcing_power": 1.0, "forcing_kmin": 2.0, "forcing_kmax": 1e300}, -1),
     ((64, 6.28, 0.1, 0.01), {"scheme": 2}, -1),
     ((64, 6.28, 0.1, 0.01), {"scheme": -1}, -1),
     ((64, 6.28, 0.1, 0.01), {"cfl": -0.5}, -1),
