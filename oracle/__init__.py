@@ -122,10 +122,10 @@ def lib():
         L.or_umax.restype = d
         L.or_spectra1d3d.argtypes = [i, vp, vp]
         L.or_tendency2d_strat.argtypes = [i, d, d, vp, vp]
-        L.or_step3d_rot.argtypes = [i, d, d, d, d, d, d, d, i, vp, i]
+        L.or_step3d_rot.argtypes = [i, d, d, d, d, d, d, d, i, d, vp, i, vp]
         L.or_strat_propagate.argtypes = [i, d, d, d, d, vp, vp]
         L.or_tendency3d_strat.argtypes = [i, d, vp, d, d, d, vp]
-        L.or_step3d_strat.argtypes = [i, d, d, d, d, d, d, d, i, vp, i]
+        L.or_step3d_strat.argtypes = [i, d, d, d, d, d, d, d, i, d, vp, i, vp]
         L.or_tendency3d_modes.argtypes = [i, d, vp, i, vp, vp]
         L.or_structure.argtypes = [i, i, d, vp, i, vp, i, vp]
         L.or_step2d_strat.argtypes = [i, d, d, d, d, vp, i]
@@ -289,12 +289,15 @@ def tendency3d_strat(s, L=2 * np.pi, alpha=0.0, kf_min=2.0, kf_max=3.0):
 
 
 def step3d_strat(s, nu, dt, N2, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0,
-                 scheme=4):
-    """Lawson RK4 (or RK2) of the 3D Boussinesq system."""
+                 scheme=4, cfl=0.0, return_time=False):
+    """Lawson RK4 (or RK2) of the 3D Boussinesq system; cfl > 0: adaptive
+    steps of at most dt (return_time: also the elapsed time)."""
     a = _c128(s).copy()
+    t = C.c_double(0.0)
     lib().or_step3d_strat(a.shape[1], float(L), float(nu), float(dt), float(N2), float(power),
-                          float(kf_min), float(kf_max), int(scheme), _p(a), int(nsteps))
-    return a
+                          float(kf_min), float(kf_max), int(scheme), float(cfl), _p(a),
+                          int(nsteps), C.byref(t))
+    return (a, t.value) if return_time else a
 
 
 def structure(state, ndim, r, pmax, L=2 * np.pi):
@@ -320,12 +323,16 @@ def tendency3d_modes(uh, modes, L=2 * np.pi):
     return out
 
 
-def step3d_rot(uh, nu, dt, f, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0, scheme=4):
-    """Lawson RK4 (or RK2) in a frame rotating about z (Coriolis -f z x u)."""
+def step3d_rot(uh, nu, dt, f, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0, scheme=4,
+               cfl=0.0, return_time=False):
+    """Lawson RK4 (or RK2) in a frame rotating about z (Coriolis -f z x u);
+    cfl > 0: adaptive steps of at most dt (return_time: also the elapsed time)."""
     u = _c128(uh).copy()
+    t = C.c_double(0.0)
     lib().or_step3d_rot(u.shape[1], float(L), float(nu), float(dt), float(f), float(power),
-                        float(kf_min), float(kf_max), int(scheme), _p(u), int(nsteps))
-    return u
+                        float(kf_min), float(kf_max), int(scheme), float(cfl), _p(u), int(nsteps),
+                        C.byref(t))
+    return (u, t.value) if return_time else u
 
 
 def tendency2d_strat(s, N2, L=2 * np.pi):

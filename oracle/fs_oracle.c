@@ -649,15 +649,27 @@ static void rot_apply(int n, double L, double nu, double f, double t, const cplx
 /* Lawson RK4 (scheme 4) or RK2 (scheme 2) with an operator propagator      */
 /* prop(t, in, out) = E(t) in over `tot` complex values (E = E(dt),           */
 /* Eh = E(dt/2)); hook (if any) runs on u_n before the step's first stage.   */
+/* With cfl > 0 each step takes dt_n = min(dt, cfl (L/n) / max|u_c|) from   */
+/* the velocity (first three fields) of u_n; the elapsed time is added to   */
+/* *t_out (if given).                                                         */
 typedef void (*prop_fn)(double t, const cplx *in, cplx *out, void *ctx);
+static double umax_state(int ndim, int n, double L, const cplx *s);
 
-static void lawson_prop(int64_t tot, double dt, int scheme, cplx *uh, int nsteps, tend_fn tend,
-                        hook_fn hook, prop_fn prop, void *ctx) {
+static void lawson_prop(int64_t tot, double dt_max, int scheme, cplx *uh, int nsteps,
+                        tend_fn tend, hook_fn hook, prop_fn prop, void *ctx, int n, double L,
+                        double cfl, double *t_out) {
   cplx *k1 = malloc(sizeof(cplx) * tot), *k2 = malloc(sizeof(cplx) * tot);
   cplx *k3 = malloc(sizeof(cplx) * tot), *k4 = malloc(sizeof(cplx) * tot);
   cplx *v = malloc(sizeof(cplx) * tot), *w = malloc(sizeof(cplx) * tot);
   cplx *acc = malloc(sizeof(cplx) * tot);
+  double t_el = 0.0;
   for (int s = 0; s < nsteps; s++) {
+    double dt = dt_max;
+    if (cfl > 0) {
+      const double um = umax_state(3, n, L, uh);
+      if (um > 0) dt = fmin(dt_max, cfl * (L / n) / um);
+    }
+    t_el += dt;
     if (hook) hook(uh, ctx);
     tend(uh, k1, ctx);
     /* v = Eh (u + dt/2 k1) */
@@ -686,6 +698,7 @@ static void lawson_prop(int64_t tot, double dt, int scheme, cplx *uh, int nsteps
     prop(0.5 * dt, w, v, ctx);
     for (int64_t i = 0; i < tot; i++) uh[i] = acc[i] + dt / 3.0 * v[i] + dt / 6.0 * k4[i];
   }
+  if (t_out) *t_out += t_el;
   free(k1);
   free(k2);
   free(k3);
@@ -708,10 +721,10 @@ static void rot_tend(const cplx *u, cplx *out, void *ctx) { tend3(u, out, &((str
 static void rot_hook(const cplx *u, void *ctx) { alpha3(u, &((struct rot_ctx *)ctx)->g); }
 
 void or_step3d_rot(int n, double L, double nu, double dt, double f, double power, double kf_min,
-                   double kf_max, int scheme, cplx *uh, int nsteps) {
+                   double kf_max, int scheme, double cfl, cplx *uh, int nsteps, double *t_out) {
   struct rot_ctx c = {{n, L, 0.0, power, kf_min, kf_max}, nu, f};
   lawson_prop(3 * (int64_t)n * n * (n / 2 + 1), dt, scheme, uh, nsteps, rot_tend, rot_hook,
-              rot_prop, &c);
+              rot_prop, &c, n, L, cfl, t_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -809,10 +822,11 @@ static void strat3_hook(const cplx *u, void *ctx) { alpha3(u, &((struct strat3_c
 /* Lawson RK4 / RK2 of the 3D Boussinesq system with the exact propagator of
  * viscosity, buoyancy force and stratification; forcing acts on u only. */
 void or_step3d_strat(int n, double L, double nu, double dt, double N2, double power,
-                     double kf_min, double kf_max, int scheme, cplx *s, int nsteps) {
+                     double kf_min, double kf_max, int scheme, double cfl, cplx *s, int nsteps,
+                     double *t_out) {
   struct strat3_ctx c = {{n, L, 0.0, power, kf_min, kf_max}, nu, N2};
   lawson_prop(4 * (int64_t)n * n * (n / 2 + 1), dt, scheme, s, nsteps, strat3_tend, strat3_hook,
-              strat3_prop, &c);
+              strat3_prop, &c, n, L, cfl, t_out);
 }
 
 /* Largest |u_c| over the grid points and velocity components of a kept-set

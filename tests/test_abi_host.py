@@ -78,12 +78,10 @@ def _create(lib, n, L, nu, dt, **kw):
     ((64, 6.28, 0.1, 0.01), {"cfl": -0.5}, -1),
     ((64, 6.28, 0.1, 0.01), {"cfl": float("nan")}, -1),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "rotation": 1.0}, -2),
-    ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "cfl": 0.5}, -2),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "ndim": 2, "n2": -1.0}, -1),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x20}, -1),
     ((64, 6.28, 0.1, 0.01), {"rotation": float("inf")}, -1),
     ((64, 6.28, 0.1, 0.01), {"rotation": 1.0, "ndim": 2}, -2),
-    ((64, 6.28, 0.1, 0.01), {"rotation": 1.0, "cfl": 0.5}, -2),
     # a caller workspace that is too small or misaligned (checked before any device call)
     ((64, 6.28, 0.1, 0.01), {"workspace": 1 << 20, "workspace_bytes": 4096}, -1),
     ((64, 6.28, 0.1, 0.01), {"workspace": (1 << 40) + 16, "workspace_bytes": 1 << 40}, -1),

@@ -90,3 +90,28 @@ def test_inertial_wave_512(fs):
     assert np.abs(got - want).max() <= 2e-6
     assert rest <= 1e-6
     plan.close()
+
+
+@pytest.mark.parametrize("prec,scheme", [("f32", "rk4"), ("f64", "rk2")])
+def test_rotating_cfl_steps(fs, oracle_mod, prec, scheme):
+    """CFL-adaptive steps in the rotating frame: step sizes from the velocity
+    maximum measured on the GPU, the exact propagator at each step's size."""
+    print(f"case rotation cfl n=32 {prec} {scheme}", flush=True)
+    n, nu, dtmax, f, cfl, steps = 32, 2e-3, 0.05, 3.0, 0.4, 5
+    cd = np.complex64 if prec == "f32" else np.complex128
+    u = I.random_solenoidal_3d(n, seed=121, dtype=cd)
+    plan = fs.Plan(n, nu=nu, dt=dtmax, precision=prec, forcing_power=0.05, rotation=f,
+                   scheme=scheme, cfl=cfl)
+    d = torch.from_numpy(u).cuda()
+    plan.step(d, steps)
+    t = float(plan.time()[0].item())
+    got = d.cpu().numpy().astype(np.complex128)
+    sc = 4 if scheme == "rk4" else 2
+    ref, tr = oracle_mod.step3d_rot(u.astype(np.complex128), nu, dtmax, f, steps, power=0.05,
+                                    scheme=sc, cfl=cfl, return_time=True)
+    err = rel_l2(got, ref, kept_weight(n, 3)[None])
+    print(f"rel err {err:.2e}; time {t:.8f} vs {tr:.8f}", flush=True)
+    assert tr < steps * dtmax * 0.9  # the CFL bound is active
+    tol = 1e-5 if prec == "f32" else 1e-11
+    assert err <= tol and abs(t - tr) <= tol * tr
+    plan.close()

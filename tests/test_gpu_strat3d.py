@@ -132,3 +132,28 @@ def test_plane_gravity_wave_512(fs):
     assert np.abs(got - want).max() <= 2e-6
     assert rest <= 1e-6
     plan.close()
+
+
+@pytest.mark.parametrize("prec,scheme", [("f32", "rk4"), ("f64", "rk2")])
+def test_strat3d_cfl_steps(fs, oracle_mod, prec, scheme):
+    """CFL-adaptive stratified steps: sizes from the velocity part's maximum,
+    the exact buoyancy-stratification propagator at each size."""
+    print(f"case boussinesq3d cfl n=32 {prec} {scheme}", flush=True)
+    n, nu, dtmax, N2, cfl, steps = 32, 2e-3, 0.05, 4.0, 0.4, 5
+    cd = np.complex64 if prec == "f32" else np.complex128
+    s = _state(n, 221, cd)
+    plan = fs.Plan(n, nu=nu, dt=dtmax, precision=prec, forcing_power=0.05, boussinesq=True,
+                   n2=N2, scheme=scheme, cfl=cfl)
+    d = torch.from_numpy(s).cuda()
+    plan.step(d, steps)
+    t = float(plan.time()[0].item())
+    got = d.cpu().numpy().astype(np.complex128)
+    sc = 4 if scheme == "rk4" else 2
+    ref, tr = oracle_mod.step3d_strat(s.astype(np.complex128), nu, dtmax, N2, steps, power=0.05,
+                                      scheme=sc, cfl=cfl, return_time=True)
+    err = rel_l2(got, ref, _w4(n))
+    print(f"rel err {err:.2e}; time {t:.8f} vs {tr:.8f}", flush=True)
+    assert tr < steps * dtmax * 0.9
+    tol = 1e-5 if prec == "f32" else 1e-11
+    assert err <= tol and abs(t - tr) <= tol * tr
+    plan.close()

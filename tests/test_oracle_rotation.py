@@ -89,3 +89,28 @@ def test_rk2_helical_and_f_zero(oracle_mod):
     a = oracle_mod.step3d_rot(r, 0.01, 2e-3, 0.0, 3, scheme=2)
     b, _ = oracle_mod.step3d_ex(r, 0.01, 2e-3, 3, scheme=2)
     assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+
+
+def _numpy_umax(u, n):
+    # numpy's irfftn divides by n^3; the state's inverse is unscaled
+    phys = np.fft.irfftn(u[:3] * kept_mask(n, 3)[None], s=(n, n, n), axes=(1, 2, 3)) * n ** 3
+    return np.abs(phys).max()
+
+
+def test_cfl_steps_rotating(oracle_mod):
+    """Adaptive steps: each step's size from numpy's velocity maximum of the
+    step's initial state, then the fixed-step rotating step with that size."""
+    n, cfl, f = 16, 0.5, 3.0
+    u0 = I.random_solenoidal_3d(n, seed=108)
+    got, t = oracle_mod.step3d_rot(u0, 0.01, 1.0, f, 2, power=0.1, cfl=cfl, return_time=True)
+    u, tt = u0.copy(), 0.0
+    for _ in range(2):
+        dt = cfl * (2 * np.pi / n) / _numpy_umax(u, n)
+        u = oracle_mod.step3d_rot(u, 0.01, dt, f, 1, power=0.1)
+        tt += dt
+    assert abs(t - tt) <= 1e-14 * tt
+    assert np.abs(got - u).max() <= 1e-13 * np.abs(u).max()
+    # a CFL bound above the step: the fixed steps exactly
+    fixed, t3 = oracle_mod.step3d_rot(u0, 0.01, 1e-3, f, 3, cfl=100.0, return_time=True)
+    assert abs(t3 - 3e-3) < 1e-18
+    assert np.array_equal(fixed, oracle_mod.step3d_rot(u0, 0.01, 1e-3, f, 3))

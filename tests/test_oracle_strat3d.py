@@ -158,3 +158,22 @@ def test_linear_terms_written_out_agree(oracle_mod):
     effect = np.abs(plain - s[:3]).max() / np.abs(s).max()
     assert effect > 1e-3
     assert err < 1e-9, (err, effect)
+
+
+def test_cfl_steps_stratified(oracle_mod):
+    """Adaptive steps take their size from the velocity part only (numpy's
+    maximum of the first three fields), then the fixed-step Boussinesq step."""
+    n, cfl, N2 = 16, 0.5, 4.0
+    s0 = _state(n, 81)
+    got, t = oracle_mod.step3d_strat(s0, 0.01, 1.0, N2, 2, scheme=2, cfl=cfl, return_time=True)
+    s, tt = s0.copy(), 0.0
+    for _ in range(2):
+        phys = np.fft.irfftn(s[:3] * kept_mask(n, 3)[None], s=(n, n, n), axes=(1, 2, 3)) * n ** 3
+        dt = cfl * (2 * np.pi / n) / np.abs(phys).max()
+        s = oracle_mod.step3d_strat(s, 0.01, dt, N2, 1, scheme=2)
+        tt += dt
+    assert abs(t - tt) <= 1e-14 * tt
+    assert np.abs(got - s).max() <= 1e-13 * np.abs(s).max()
+    fixed, t3 = oracle_mod.step3d_strat(s0, 0.01, 1e-3, N2, 3, cfl=100.0, return_time=True)
+    assert abs(t3 - 3e-3) < 1e-18
+    assert np.array_equal(fixed, oracle_mod.step3d_strat(s0, 0.01, 1e-3, N2, 3))
