@@ -125,7 +125,8 @@ def lib():
         L.or_step3d_rot.argtypes = [i, d, d, d, d, d, d, d, i, d, vp, i, vp]
         L.or_strat_propagate.argtypes = [i, d, d, d, d, vp, vp]
         L.or_tendency3d_strat.argtypes = [i, d, vp, d, d, d, vp]
-        L.or_step3d_strat.argtypes = [i, d, d, d, d, d, d, d, i, d, vp, i, vp]
+        L.or_step3d_strat.argtypes = [i, d, d, d, d, d, d, d, d, i, d, vp, i, vp]
+        L.or_stratrot_propagate.argtypes = [i, d, d, d, d, d, vp, vp]
         L.or_tendency3d_modes.argtypes = [i, d, vp, i, vp, vp]
         L.or_structure.argtypes = [i, i, d, vp, i, vp, i, vp]
         L.or_step2d_strat.argtypes = [i, d, d, d, d, vp, i]
@@ -288,13 +289,26 @@ def tendency3d_strat(s, L=2 * np.pi, alpha=0.0, kf_min=2.0, kf_max=3.0):
     return out
 
 
+def stratrot_propagate(s, nu, N2, f, t, L=2 * np.pi):
+    """Exact propagator of viscosity, buoyancy, stratification and rotation
+    (Coriolis parameter f about z) on a [4][n][n][n/2+1] state with
+    solenoidal velocity."""
+    a = _c128(s)
+    out = np.empty_like(a)
+    lib().or_stratrot_propagate(a.shape[1], float(L), float(nu), float(N2), float(f), float(t),
+                                _p(a), _p(out))
+    return out
+
+
 def step3d_strat(s, nu, dt, N2, nsteps, L=2 * np.pi, power=0.0, kf_min=2.0, kf_max=3.0,
-                 scheme=4, cfl=0.0, return_time=False):
-    """Lawson RK4 (or RK2) of the 3D Boussinesq system; cfl > 0: adaptive
-    steps of at most dt (return_time: also the elapsed time)."""
+                 scheme=4, cfl=0.0, return_time=False, f=0.0):
+    """Lawson RK4 (or RK2) of the 3D Boussinesq system (f != 0: in a frame
+    rotating about z); cfl > 0: adaptive steps of at most dt (return_time:
+    also the elapsed time)."""
     a = _c128(s).copy()
     t = C.c_double(0.0)
-    lib().or_step3d_strat(a.shape[1], float(L), float(nu), float(dt), float(N2), float(power),
+    lib().or_step3d_strat(a.shape[1], float(L), float(nu), float(dt), float(N2), float(f),
+                          float(power),
                           float(kf_min), float(kf_max), int(scheme), float(cfl), _p(a),
                           int(nsteps), C.byref(t))
     return (a, t.value) if return_time else a

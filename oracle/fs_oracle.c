@@ -770,6 +770,65 @@ void or_strat_propagate(int n, double L, double nu, double N2, double t, const c
   }
 }
 
+/* Rotating and stratified (frame rotating about z with Coriolis parameter f,
+ * buoyancy as above).  On a solenoidal mode write u = a1 e1 + a2 e2 with
+ * e1 = khat x z / g, e2 = khat x e1 (g = |k_h| / |k|; for k_h = 0, e1 = x,
+ * e2 = khat x x).  Then q = z - khat khat_z = -g e2, u_z = -g a2 and
+ *   a1' = sf a2,  a2' = -sf a1 - g b,  b' = N2 g a2,   sf = f khat_z;
+ * in (a1, a2, b / N) this is the skew-symmetric K = [[0, sf, 0], [-sf, 0, -sN],
+ * [0, sN, 0]], sN = N g, whose exponential is I + s K + c K^2 (Rodrigues),
+ * s = sin(w t) / w, c = (1 - cos(w t)) / w^2, w^2 = sf^2 + sN^2.  Back in
+ * (a1, a2, b), finite at N2 = 0:
+ *   a1' = (1 - c sf^2) a1 + s sf a2 - c sf g b
+ *   a2' = -s sf a1 + (1 - c w^2) a2 - s g b
+ *   b'  = -c sf g N2 a1 + s g N2 a2 + (1 - c N2 g^2) b,
+ * times exp(-nu k^2 t); the khat component of the velocity is left as it is
+ * (the propagator acts on solenoidal fields). */
+void or_stratrot_propagate(int n, double L, double nu, double N2, double f, double t,
+                           const cplx *in, cplx *out) {
+  const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h;
+  const double kb = 2.0 * M_PI / L;
+  for (int64_t i = 0; i < ns; i++) {
+    int iz = (int)(i / (n * h)), iy = (int)((i / h) % n), ix = (int)(i % h);
+    int m[3] = {ix, mode_full(iy, n), mode_full(iz, n)};
+    const int keep = keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n);
+    const double k[3] = {kb * m[0], kb * m[1], kb * m[2]};
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    if (!keep || k2 == 0) {
+      for (int c = 0; c < 4; c++) out[c * ns + i] = 0;
+      continue;
+    }
+    const double kn = sqrt(k2), kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
+    const double g = sqrt(kh[0] * kh[0] + kh[1] * kh[1]);
+    double e1[3], e2[3];
+    if (g > 0) {
+      e1[0] = kh[1] / g;
+      e1[1] = -kh[0] / g;
+      e1[2] = 0;
+    } else {
+      e1[0] = 1;
+      e1[1] = 0;
+      e1[2] = 0;
+    }
+    e2[0] = kh[1] * e1[2] - kh[2] * e1[1];
+    e2[1] = kh[2] * e1[0] - kh[0] * e1[2];
+    e2[2] = kh[0] * e1[1] - kh[1] * e1[0];
+    const double sf = f * kh[2], w2 = sf * sf + N2 * g * g, w = sqrt(w2);
+    const double sn = w > 0 ? sin(w * t) / w : t;
+    const double cc = w > 0 ? 2.0 * pow(sin(0.5 * w * t), 2) / w2 : 0.5 * t * t;
+    const double d = exp(-nu * k2 * t);
+    const cplx u[3] = {in[i], in[ns + i], in[2 * ns + i]}, b = in[3 * ns + i];
+    const cplx a0 = u[0] * kh[0] + u[1] * kh[1] + u[2] * kh[2];
+    const cplx a1 = u[0] * e1[0] + u[1] * e1[1] + u[2] * e1[2];
+    const cplx a2 = u[0] * e2[0] + u[1] * e2[1] + u[2] * e2[2];
+    const cplx n1 = (1 - cc * sf * sf) * a1 + sn * sf * a2 - cc * sf * g * b;
+    const cplx n2 = -sn * sf * a1 + (1 - cc * w2) * a2 - sn * g * b;
+    const cplx nb = -cc * sf * g * N2 * a1 + sn * g * N2 * a2 + (1 - cc * N2 * g * g) * b;
+    for (int c = 0; c < 3; c++) out[c * ns + i] = d * (a0 * kh[c] + n1 * e1[c] + n2 * e2[c]);
+    out[3 * ns + i] = d * nb;
+  }
+}
+
 void or_tendency3d_strat(int n, double L, const cplx *s, double alpha, double kf_min,
                          double kf_max, cplx *out) {
   const int64_t h = n / 2 + 1, ns = (int64_t)n * n * h, np = (int64_t)n * n * n;
@@ -806,12 +865,15 @@ void or_tendency3d_strat(int n, double L, const cplx *s, double alpha, double kf
 
 struct strat3_ctx {
   struct grid_ctx g;
-  double nu, N2;
+  double nu, N2, f;
 };
 
 static void strat3_prop(double t, const cplx *in, cplx *out, void *ctx) {
   struct strat3_ctx *c = ctx;
-  or_strat_propagate(c->g.n, c->g.L, c->nu, c->N2, t, in, out);
+  if (c->f != 0.0)
+    or_stratrot_propagate(c->g.n, c->g.L, c->nu, c->N2, c->f, t, in, out);
+  else
+    or_strat_propagate(c->g.n, c->g.L, c->nu, c->N2, t, in, out);
 }
 static void strat3_tend(const cplx *u, cplx *out, void *ctx) {
   struct grid_ctx *g = &((struct strat3_ctx *)ctx)->g;
@@ -820,11 +882,12 @@ static void strat3_tend(const cplx *u, cplx *out, void *ctx) {
 static void strat3_hook(const cplx *u, void *ctx) { alpha3(u, &((struct strat3_ctx *)ctx)->g); }
 
 /* Lawson RK4 / RK2 of the 3D Boussinesq system with the exact propagator of
- * viscosity, buoyancy force and stratification; forcing acts on u only. */
-void or_step3d_strat(int n, double L, double nu, double dt, double N2, double power,
+ * viscosity, buoyancy force and stratification (and, with f != 0, rotation);
+ * forcing acts on u only. */
+void or_step3d_strat(int n, double L, double nu, double dt, double N2, double f, double power,
                      double kf_min, double kf_max, int scheme, double cfl, cplx *s, int nsteps,
                      double *t_out) {
-  struct strat3_ctx c = {{n, L, 0.0, power, kf_min, kf_max}, nu, N2};
+  struct strat3_ctx c = {{n, L, 0.0, power, kf_min, kf_max}, nu, N2, f};
   lawson_prop(4 * (int64_t)n * n * (n / 2 + 1), dt, scheme, s, nsteps, strat3_tend, strat3_hook,
               strat3_prop, &c, n, L, cfl, t_out);
 }

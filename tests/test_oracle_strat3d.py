@@ -177,3 +177,109 @@ def test_cfl_steps_stratified(oracle_mod):
     fixed, t3 = oracle_mod.step3d_strat(s0, 0.01, 1e-3, N2, 3, cfl=100.0, return_time=True)
     assert abs(t3 - 3e-3) < 1e-18
     assert np.array_equal(fixed, oracle_mod.step3d_strat(s0, 0.01, 1e-3, N2, 3))
+
+
+def _solenoidal_random(n, seed):
+    """Random half-spectrum (u, b) with u projected to be solenoidal per mode."""
+    rng = np.random.default_rng(seed)
+    sh = (4, n, n, n // 2 + 1)
+    s = (rng.standard_normal(sh) + 1j * rng.standard_normal(sh)) * kept_mask(n, 3)[None]
+    kx, ky, kz = kmesh(n, 3)
+    k2 = kx ** 2 + ky ** 2 + kz ** 2
+    k2[k2 == 0] = 1.0
+    kd = (kx * s[0] + ky * s[1] + kz * s[2]) / k2
+    s[0] -= kx * kd
+    s[1] -= ky * kd
+    s[2] -= kz * kd
+    return s
+
+
+@pytest.mark.parametrize("N2,f", [(2.5, 3.0), (0.0, 2.0), (40.0, 0.7)])
+def test_rotating_stratified_propagator_is_matrix_exponential(oracle_mod, N2, f):
+    """(u, b) -> (-f P(z x u) + P(b z) - nu k^2 u, -N^2 uz - nu k^2 b) on
+    solenoidal velocities, exponentiated by scipy at every kept mode."""
+    n, nu, t = 8, 0.01, 0.7
+    s = _solenoidal_random(n, 11)
+    got = oracle_mod.stratrot_propagate(s, nu, N2, f, t)
+    kx, ky, kz = kmesh(n, 3)
+    Z = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 0.0]])  # z x u
+    worst, scale = 0.0, 0.0
+    for idx in zip(*np.nonzero(kept_mask(n, 3))):
+        k = np.array([kx[idx], ky[idx], kz[idx]])
+        k2 = k @ k
+        if k2 == 0:
+            continue
+        P = np.eye(3) - np.outer(k, k) / k2
+        A = np.zeros((4, 4))
+        A[:3, :3] = -f * P @ Z
+        A[:3, 3] = P @ np.array([0.0, 0.0, 1.0])
+        A[3, 2] = -N2
+        A -= nu * k2 * np.eye(4)
+        want = expm(t * A) @ s[(slice(None),) + idx]
+        worst = max(worst, np.abs(got[(slice(None),) + idx] - want).max())
+        scale = max(scale, np.abs(want).max())
+    assert worst <= 1e-13 * scale, (worst, scale)
+
+
+def test_rotating_stratified_reductions(oracle_mod):
+    n = 16
+    s = _solenoidal_random(n, 13)
+    # f = 0: the stratified propagator
+    a = oracle_mod.stratrot_propagate(s, 0.01, 2.5, 0.0, 0.3)
+    b = oracle_mod.strat_propagate(s, 0.01, 2.5, 0.3)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+    # N^2 = 0 and b = 0: the rotating step
+    u = _state(n, 91)
+    u[3] = 0
+    got = oracle_mod.step3d_strat(u, 0.01, 2e-3, 0.0, 3, f=2.0, power=0.05)
+    ref = oracle_mod.step3d_rot(u[:3], 0.01, 2e-3, 2.0, 3, power=0.05)
+    assert np.abs(got[3]).max() == 0.0
+    assert np.abs(got[:3] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_plane_inertia_gravity_wave_is_exact(oracle_mod):
+    """A single solenoidal plane mode keeps the nonlinear terms zero, so the
+    step is its propagator over the whole time (pinned above by expm)."""
+    n, nu, N2, f, dt, steps = 16, 0.01, 6.0, 2.5, 0.05, 20
+    m = (2, 1, 3)
+    s0, ep, _ = _wave(n, m, 0.3 - 0.1j, 0.2 + 0.4j)
+    k = np.array(m, float)
+    e1 = np.cross(k / np.linalg.norm(k), [0.0, 0.0, 1.0])
+    s0[:3, m[2], m[1], m[0]] += 0.25j * e1 / np.linalg.norm(e1)  # a toroidal part too
+    assert np.abs(oracle_mod.tendency3d_strat(s0)).max() <= 1e-15
+    got = oracle_mod.step3d_strat(s0, nu, dt, N2, steps, f=f)
+    want = oracle_mod.stratrot_propagate(s0, nu, N2, f, dt * steps)
+    assert np.abs(got - want).max() <= 1e-14
+
+
+def test_rotating_stratified_written_out_agrees(oracle_mod):
+    n, N2, f, dt, steps = 16, 4.0, 3.0, 1e-3, 10
+    s0 = _state(n, 73)
+    kx, ky, kz = kmesh(n, 3)
+    k2 = kx ** 2 + ky ** 2 + kz ** 2
+    k2[k2 == 0] = 1.0
+    mask = kept_mask(n, 3)[None]
+
+    def proj(v):
+        kv = (kx * v[0] + ky * v[1] + kz * v[2]) / k2
+        return v - np.stack([kx, ky, kz]) * kv
+
+    def rhs(s):
+        cor = np.stack([-s[1], s[0], np.zeros_like(s[0])])  # z x u
+        buoy = np.stack([np.zeros_like(s[3]), np.zeros_like(s[3]), s[3]])
+        lin = np.concatenate([proj(buoy - f * cor), (-N2 * s[2])[None]])
+        return (oracle_mod.tendency3d_strat(s) + lin) * mask
+
+    s = s0.copy()
+    for _ in range(steps):
+        a1 = rhs(s)
+        a2 = rhs(s + 0.5 * dt * a1)
+        a3 = rhs(s + 0.5 * dt * a2)
+        a4 = rhs(s + dt * a3)
+        s = s + dt / 6 * (a1 + 2 * a2 + 2 * a3 + a4)
+    got = oracle_mod.step3d_strat(s0, 0.0, dt, N2, steps, f=f)
+    nof = oracle_mod.step3d_strat(s0, 0.0, dt, N2, steps)
+    err = np.abs(got - s).max() / np.abs(s).max()
+    effect = np.abs(nof - s).max() / np.abs(s).max()
+    assert effect > 1e-3
+    assert err < 1e-9, (err, effect)
