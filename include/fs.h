@@ -86,8 +86,10 @@ enum { FS_SCHEME_RK4 = 0, FS_SCHEME_RK2 = 1 };
  *   q = z - khat khat_z, g2 = |k_h|^2/|k|^2, s = sqrt(n2 g2), c = cos(s t),
  *   S = sin(s t)/s (t when s = 0),
  *   E(t)(u, b) = exp(-nu k^2 t) (u + [(c-1) uz/g2 + S b] q,  c b - n2 S uz);
- *   fs_tendency returns the nonlinear terms (-i k.(u b)^ for b).  No
- *   rotation; forcing acts on u; adaptive steps take their size from u.
+ *   fs_tendency returns the nonlinear terms (-i k.(u b)^ for b).  With a
+ *   rotation as well, the Coriolis force joins the exactly integrated terms
+ *   (see fs_plan_opts.rotation); forcing acts on u; adaptive steps take their
+ *   size from u.
  * Diagnostics, transfer and 1D spectra describe the velocity (2D: vorticity)
  * part. */
 #define FS_BOUSSINESQ 0x8u
@@ -121,8 +123,14 @@ typedef struct {
                            (acceleration -f z x u); 0 (default): none.  Folded into
                            the exact linear propagator: for solenoidal fields
                            E(t) u = exp(-nu k^2 t)(cos(s t) u - sin(s t) khat x u),
-                           s = f kz / |k|; fs_tendency excludes it; not with
-                           FS_BOUSSINESQ */
+                           s = f kz / |k|; fs_tendency excludes it.  With
+                           FS_BOUSSINESQ, u = a1 e1 + a2 e2 (e1 = khat x z / g,
+                           e2 = khat x e1, g = |k_h|/|k|) and (a1, a2, b) obey
+                           a1' = sf a2, a2' = -sf a1 - g b, b' = n2 g a2
+                           (sf = f khat_z), integrated exactly as the rotation
+                           exp(t K) = I + s K + c K^2 in (a1, a2, b/N):
+                           w^2 = sf^2 + n2 g^2, s = sin(w t)/w,
+                           c = (1 - cos(w t))/w^2 */
   void *workspace;      /* optional caller-owned device workspace (e.g. a torch
                            tensor), 256-byte aligned, of at least
                            fs_plan_workspace_bytes bytes; the plan uses it instead

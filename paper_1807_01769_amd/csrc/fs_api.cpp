@@ -172,8 +172,6 @@ fs_status configure(Plan* p, int n, double L, double nu, double dt, const fs_pla
   if (!isfin(o.rotation)) return fail(FS_E_INVALID, "rotation must be finite");
   if (o.rotation != 0.0 && o.ndim != 3)
     return fail(FS_E_UNSUPPORTED, "rotation is implemented for ndim = 3");
-  if (o.rotation != 0.0 && (o.flags & FS_BOUSSINESQ))
-    return fail(FS_E_UNSUPPORTED, "rotation and FS_BOUSSINESQ together are not implemented");
   if (!(isfin(o.forcing_power) && o.forcing_power >= 0))
     return fail(FS_E_INVALID, "forcing_power must be finite and >= 0");
   if (o.scheme != FS_SCHEME_RK4 && o.scheme != FS_SCHEME_RK2)

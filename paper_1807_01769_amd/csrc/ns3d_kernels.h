@@ -226,10 +226,12 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
 template <typename T, int N>
 using ZCfg = Strided<T, N, cmin(kTile, cmax(1, (N >= 1024 ? 1024 : 512) / (N / 8)))>;
 // linear propagator of a fused z pass
-enum LinearProp : int { kPropVisc = 0, kPropRot = 1, kPropStrat = 2 };
+enum LinearProp : int { kPropVisc = 0, kPropRot = 1, kPropStrat = 2, kPropStratRot = 3 };
+// the propagators of Boussinesq flow, whose state carries the buoyancy too
+constexpr bool prop_boussinesq(int prop) { return prop >= kPropStrat; }
 template <typename T, int PROP = kPropVisc>
 constexpr int zpass_waves() {
-  return sizeof(T) == 4 ? (PROP == kPropStrat ? 2 : 4) : 1;
+  return sizeof(T) == 4 ? (prop_boussinesq(PROP) ? 2 : 4) : 1;
 }
 // twiddle table of a z pass: the LDS copy `twl` (filled by the block) in single
 // precision, the global table otherwise
@@ -374,7 +376,8 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
 // (do_p1) the next stage's six inverse z transforms into w1.
 // MODE kModeTend writes the tendency to a.tend instead.  PROP selects the
 // linear propagator of the combine: viscosity, + rotation (about z), or
-// + buoyancy force and stratification (kPropStrat: products Wm[6], the
+// + buoyancy force and stratification (kPropStrat, and with rotation too
+// kPropStratRot: products Wm[6], the
 // flux u b giving the buoyancy tendency -i k.(u b)^, four state components,
 // seven inverse transforms).  Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
@@ -385,7 +388,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
   using C = ZCfg<T, N>;
   constexpr int P = G::P;
   constexpr int NH = N / 2 + 1;
-  constexpr int NC = PROP == kPropStrat ? 4 : 3;
+  constexpr int NC = prop_boussinesq(PROP) ? 4 : 3;
   __shared__ cx<T> lds[C::LB * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
   __shared__ cx<T> twl[sizeof(T) == 4 ? N : 1];
@@ -412,7 +415,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
   for (int c = 0; c < 3; c++)
     fft_lines<T, N, -1, 1>(reinterpret_cast<cx<T>(&)[1][8]>(v[c]), t, lds, lidx, twr);
   const T kx = a.kb * (T)mx, ky = a.kb * (T)my;
-  if constexpr (PROP == kPropStrat) {
+  if constexpr (prop_boussinesq(PROP)) {
     // buoyancy tendency -i k.(u b)^, one flux component at a time
 #pragma unroll
     for (int e = 0; e < 8; e++) v[3][e] = {0, 0};
@@ -506,9 +509,13 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
           R.s2 = sin(sg * dt * (T)0.5);
           R.c2 = cos(sg * dt * (T)0.5);
           prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
-        } else {
+        } else if constexpr (PROP == kPropStrat) {
           StratProp<T> R;
           R.set(kx, ky, kz, a.n2, dt);
+          prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+        } else {
+          StratRotProp<T> R;
+          R.set(kx, ky, kz, a.n2, a.rotf, dt);
           prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
         }
 #pragma unroll

@@ -249,6 +249,77 @@ struct StratProp {
   }
 };
 
+// Rotating and stratified flow, w = (u, b): on a solenoidal mode write
+// u = a1 e1 + a2 e2 with e1 = khat x z / g, e2 = khat x e1 (g = |k_h| / |k|;
+// e1 = x when k_h = 0).  Coriolis force, buoyancy force and stratification
+// couple (a1, a2, b) as
+//   a1' = sf a2,  a2' = -sf a1 - g b,  b' = N^2 g a2,   sf = f khat_z,
+// a rotation in (a1, a2, b / N) at rate w, w^2 = sf^2 + N^2 g^2, so
+// E(t) = I + s K + c K^2 with s = sin(w t) / w, c = (1 - cos(w t)) / w^2
+// (t and t^2 / 2 when w = 0), times exp(-nu k^2 t); the khat component of u
+// is carried along unchanged.
+template <typename T>
+struct StratRotProp {
+  static constexpr int NC = 4;
+  T kh[3], e1[2], e2[3];
+  T g, sf, n2;
+  T snf, ccf, snh, cch;  // s and c of the full and the half step
+  __device__ __forceinline__ void set(T kx, T ky, T kz, T N2, T f, T dt) {
+    const T k2 = kx * kx + ky * ky + kz * kz;
+    const T ikn = k2 > (T)0 ? (T)1 / sqrt(k2) : (T)0;
+    kh[0] = kx * ikn;
+    kh[1] = ky * ikn;
+    kh[2] = kz * ikn;
+    g = sqrt(kh[0] * kh[0] + kh[1] * kh[1]);
+    if (g > (T)0) {
+      const T ig = (T)1 / g;
+      e1[0] = kh[1] * ig;
+      e1[1] = -kh[0] * ig;
+      e2[0] = kh[0] * kh[2] * ig;
+      e2[1] = kh[1] * kh[2] * ig;
+      e2[2] = -g;
+    } else {
+      e1[0] = (T)1;
+      e1[1] = (T)0;
+      e2[0] = (T)0;
+      e2[1] = kh[2];
+      e2[2] = (T)0;
+    }
+    n2 = N2;
+    sf = f * kh[2];
+    const T w2 = sf * sf + N2 * g * g, w = sqrt(w2);
+    // sines and cosines of w dt / 4 give both steps by double angles
+    const T s4 = sin(w * dt * (T)0.25), c4 = cos(w * dt * (T)0.25);
+    const T s2 = (T)2 * s4 * c4, c2 = (T)1 - (T)2 * s4 * s4;  // of w dt / 2
+    if (w > (T)0) {
+      const T iw = (T)1 / w, iw2 = (T)1 / w2;
+      snh = s2 * iw;
+      snf = (T)2 * s2 * c2 * iw;
+      cch = (T)2 * s4 * s4 * iw2;
+      ccf = (T)2 * s2 * s2 * iw2;
+    } else {
+      snh = dt * (T)0.5;
+      snf = dt;
+      cch = dt * dt * (T)0.125;
+      ccf = dt * dt * (T)0.5;
+    }
+  }
+  __device__ __forceinline__ void apply(const cx<T> (&w)[4], T d, bool half, cx<T> (&o)[4]) const {
+    const T s = half ? snh : snf, c = half ? cch : ccf;
+    const cx<T> a0 = cscale(w[0], kh[0]) + cscale(w[1], kh[1]) + cscale(w[2], kh[2]);
+    const cx<T> a1 = cscale(w[0], e1[0]) + cscale(w[1], e1[1]);
+    const cx<T> a2 = cscale(w[0], e2[0]) + cscale(w[1], e2[1]) + cscale(w[2], e2[2]);
+    const T sg = sf * g, ng2 = n2 * g * g;
+    const cx<T> m1 = cscale(a1, (T)1 - c * sf * sf) + cscale(a2, s * sf) - cscale(w[3], c * sg);
+    const cx<T> m2 = cscale(a2, (T)1 - c * (sf * sf + ng2)) - cscale(a1, s * sf) - cscale(w[3], s * g);
+    const cx<T> mb = cscale(w[3], (T)1 - c * ng2) + cscale(a2, s * g * n2) - cscale(a1, c * sg * n2);
+    o[0] = cscale(cscale(a0, kh[0]) + cscale(m1, e1[0]) + cscale(m2, e2[0]), d);
+    o[1] = cscale(cscale(a0, kh[1]) + cscale(m1, e1[1]) + cscale(m2, e2[1]), d);
+    o[2] = cscale(cscale(a0, kh[2]) + cscale(m2, e2[2]), d);
+    o[3] = cscale(mb, d);
+  }
+};
+
 // The Lawson stage combinations of rk4_combine with a propagator acting on
 // the NC components of one mode.
 template <int MODE, class Prop, typename T, int NC>

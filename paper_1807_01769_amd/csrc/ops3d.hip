@@ -83,10 +83,14 @@ struct L3 {
   static void zk(Plan* p, void* state, void* tend, int do_p1) {
     p->begin(KID_Z);
     const dim3 grid(xcd_grid(G::M, G::XT * ZC::SUB));
-    if constexpr (STRAT)
-      hipLaunchKernelGGL((k3_z<T, N, MODE, kPropStrat>), grid, dim3(ZC::THREADS), 0, p->launch,
-                         (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend), do_p1);
-    else if (MODE != kModeTend && p->rotf != 0.0)
+    if constexpr (STRAT) {
+      if (MODE != kModeTend && p->rotf != 0.0)
+        hipLaunchKernelGGL((k3_z<T, N, MODE, kPropStratRot>), grid, dim3(ZC::THREADS), 0,
+                           p->launch, (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend), do_p1);
+      else
+        hipLaunchKernelGGL((k3_z<T, N, MODE, kPropStrat>), grid, dim3(ZC::THREADS), 0, p->launch,
+                           (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend), do_p1);
+    } else if (MODE != kModeTend && p->rotf != 0.0)
       hipLaunchKernelGGL((k3_z<T, N, MODE, kPropRot>), grid, dim3(ZC::THREADS), 0, p->launch,
                          (const cx<T>*)B(p), A(p), stage_args<T>(p, state, tend), do_p1);
     else

@@ -77,7 +77,7 @@ def _create(lib, n, L, nu, dt, **kw):
     ((64, 6.28, 0.1, 0.01), {"scheme": -1}, -1),
     ((64, 6.28, 0.1, 0.01), {"cfl": -0.5}, -1),
     ((64, 6.28, 0.1, 0.01), {"cfl": float("nan")}, -1),
-    ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "rotation": 1.0}, -2),
+    ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "rotation": 1.0, "ndim": 2}, -2),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x8, "ndim": 2, "n2": -1.0}, -1),
     ((64, 6.28, 0.1, 0.01), {"flags": 0x20}, -1),
     ((64, 6.28, 0.1, 0.01), {"rotation": float("inf")}, -1),
