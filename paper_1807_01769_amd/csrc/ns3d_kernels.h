@@ -411,9 +411,22 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
   for (int c = 0; c < 3; c++)
 #pragma unroll
     for (int e = 0; e < 8; e++) v[c][e] = src0[c * fstride + (size_t)(t + e * P) * zstride];
+  // single precision up to 512: the first component's transformed lines wait
+  // in an LDS stash (each lane reads back only what it wrote, so no barrier)
+  // while the other two are transformed; held in registers they spilled to
+  // scratch at the two-blocks-per-CU register budget
+  constexpr bool kStash = sizeof(T) == 4 && N <= 512 && !prop_boussinesq(PROP);
+  __shared__ cx<T> stash[kStash ? C::LB * N : 1];
 #pragma unroll
-  for (int c = 0; c < 3; c++)
+  for (int c = 0; c < 3; c++) {
     fft_lines<T, N, -1, 1>(reinterpret_cast<cx<T>(&)[1][8]>(v[c]), t, lds, lidx, twr);
+    if constexpr (kStash) {
+      if (c == 0) {
+#pragma unroll
+        for (int e = 0; e < 8; e++) stash[lidx(0, t + e * P)] = v[0][e];
+      }
+    }
+  }
   const T kx = a.kb * (T)mx, ky = a.kb * (T)my;
   if constexpr (prop_boussinesq(PROP)) {
     // buoyancy tendency -i k.(u b)^, one flux component at a time
@@ -459,6 +472,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
     const T kz = a.kb * (T)mz;
     const T k2 = kx * kx + ky * ky + kz * kz;
     cx<T> nl[NC];
+    if constexpr (kStash) v[0][e] = stash[lidx(0, t + e * P)];
     if (k2 > (T)0) {
       const T ik2 = recip(k2);
       const cx<T> kp = cscale(cscale(v[0][e], kx) + cscale(v[1][e], ky) + cscale(v[2][e], kz), ik2);
