@@ -411,11 +411,11 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
   for (int c = 0; c < 3; c++)
 #pragma unroll
     for (int e = 0; e < 8; e++) v[c][e] = src0[c * fstride + (size_t)(t + e * P) * zstride];
-  // single precision up to 512: the first component's transformed lines wait
-  // in an LDS stash (each lane reads back only what it wrote, so no barrier)
-  // while the other two are transformed; held in registers they spilled to
-  // scratch at the two-blocks-per-CU register budget
-  constexpr bool kStash = sizeof(T) == 4 && N <= 512 && !prop_boussinesq(PROP);
+  // up to 512: the first component's transformed lines wait in an LDS stash
+  // (each lane reads back only what it wrote, so no barrier) while the other
+  // two are transformed; held in registers they spilled to scratch (single
+  // precision at two blocks per CU, double precision at one)
+  constexpr bool kStash = N <= 512 && !prop_boussinesq(PROP);
   __shared__ cx<T> stash[kStash ? C::LB * N : 1];
 #pragma unroll
   for (int c = 0; c < 3; c++) {
