@@ -3,7 +3,10 @@ one shell |k| = k0 with positive helicity (i k x u = k0 u for every mode) has
 vorticity k0 u, so u x w = 0 and the nonlinear term vanishes: an unforced step
 multiplies every mode by exp(-nu k0^2 t) exactly.  This checks the fused passes
 of 256^3 and 512^3 plans, FP64 (and FP32 at 512^3), at every mode against a
-closed form, where a whole oracle step would be too costly."""
+closed form, where a whole oracle step would be too costly.  In a frame
+rotating about z each positive-helicity mode is an inertial wave (khat x h =
+-i h, so the propagator multiplies it by exp(i f kz t / |k|)) and the field
+stays Beltrami, so the rotating step is exact too."""
 import numpy as np
 import pytest
 
@@ -66,22 +69,26 @@ def test_beltrami_field_is_exact_eigenfield():
     assert np.abs(np.einsum("ij,ij->i", ms, h)).max() < 1e-14
 
 
-@pytest.mark.parametrize("n,k0sq,prec", [(256, 6254, "f64"), (512, 150 * 150, "f64"),
-                                         (512, 150 * 150, "f32")])
-def test_beltrami_decay_full_size(fs, n, k0sq, prec):
-    print(f"case beltrami decay n={n} |m|^2={k0sq} {prec}", flush=True)
+@pytest.mark.parametrize("n,k0sq,prec,f", [(256, 6254, "f64", 0.0), (512, 150 * 150, "f64", 0.0),
+                                           (512, 150 * 150, "f32", 0.0),
+                                           (256, 6254, "f64", 40.0), (512, 150 * 150, "f32", 40.0)])
+def test_beltrami_decay_full_size(fs, n, k0sq, prec, f):
+    print(f"case beltrami decay n={n} |m|^2={k0sq} {prec} rotation {f}", flush=True)
     nu, dt, steps = 2e-4, 1e-3, 5
     cd = np.complex128 if prec == "f64" else np.complex64
     u, idx, h = beltrami_field(n, k0sq, 7, cd)
     nmodes = len(idx[0])
-    plan = fs.Plan(n, precision=prec, nu=nu, dt=dt)
+    plan = fs.Plan(n, precision=prec, nu=nu, dt=dt, rotation=f)
     d = torch.from_numpy(u).cuda()
     del u
     plan.step(d, steps)
     got = d[:, idx[0], idx[1], idx[2]].cpu().numpy().T.astype(np.complex128)  # [modes][3]
     d[:, idx[0], idx[1], idx[2]] = 0
     rest = torch.view_as_real(d).abs().max().item()
-    want = h.astype(cd).astype(np.complex128) * np.exp(-nu * k0sq * dt * steps)
+    t = dt * steps
+    kz = shell_modes(k0sq)[:, 2].astype(np.float64)
+    phase = np.exp(1j * f * kz / np.sqrt(k0sq) * t)[:, None]
+    want = h.astype(cd).astype(np.complex128) * np.exp(-nu * k0sq * t) * phase
     err = np.abs(got - want).max() / np.abs(want).max()
     print(f"{nmodes} shell modes: rel err {err:.2e}; other modes {rest:.1e}", flush=True)
     # u x w vanishes only in exact arithmetic: its rounding, of order
