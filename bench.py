@@ -56,24 +56,27 @@ def read_traffic():
     return None
 
 
-def algorithmic_bytes(n: int, steps: int, elem: int = 8) -> dict:
+def algorithmic_bytes(n: int, steps: int, elem: int = 8, nc: int = 3) -> dict:
     """Bytes each kernel class must move in `steps` steps if only kept modes
     travel (the dealias-pruned model): per field, Us = M*M*H (state), Uzm =
     N*M*H (after the z pass), Uzn = N*N*H (after the y pass) complex values,
-    with K = (N-1)//3, M = 2K+1, H = K+1."""
+    with K = (N-1)//3, M = 2K+1, H = K+1.  nc = 4: Boussinesq flow (u, b),
+    seven inverse fields (u, w, b) and six forward ones (u x w, u b)."""
     K = (n - 1) // 3
     M, H = 2 * K + 1, K + 1
     Us, Uzm, Uzn = M * M * H * elem, n * M * H * elem, n * n * H * elem
+    fi, ff = (6, 3) if nc == 3 else (7, 6)
     launches = {"y_inverse": 4 * steps, "x_c2r_product_r2c": 4 * steps,
                 "y_forward": 4 * steps, "z_stage": 4 * steps, "p1": 1}
     total = {
-        "y_inverse": 4 * steps * (6 * Uzm + 6 * Uzn),
-        "x_c2r_product_r2c": 4 * steps * (6 * Uzn + 3 * Uzn),
-        "y_forward": 4 * steps * (3 * Uzn + 3 * Uzm),
-        # read the products, write the next stage's six fields (not after the
-        # last stage), RK4 state/accumulator traffic 30 Us per step
-        "z_stage": 4 * steps * 3 * Uzm + (4 * steps - 1) * 6 * Uzm + steps * 30 * Us,
-        "p1": 3 * Us + 6 * Uzm,
+        "y_inverse": 4 * steps * (fi * Uzm + fi * Uzn),
+        "x_c2r_product_r2c": 4 * steps * (fi * Uzn + ff * Uzn),
+        "y_forward": 4 * steps * (ff * Uzn + ff * Uzm),
+        # read the products, write the next stage's inverse fields (not after
+        # the last stage), RK4 state/accumulator traffic 10 Us per component
+        # and step
+        "z_stage": 4 * steps * ff * Uzm + (4 * steps - 1) * fi * Uzm + steps * 10 * nc * Us,
+        "p1": nc * Us + fi * Uzm,
     }
     return {k: (total[k], launches[k]) for k in total}
 
@@ -341,6 +344,12 @@ def main() -> int:
                     help="skip the copy ceiling, network and ensemble measurements")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--boussinesq", action="store_true",
+                    help="3D Boussinesq flow (a buoyancy field b beside u), squared "
+                         "buoyancy frequency --n2; no LES or CPU leg")
+    ap.add_argument("--n2", type=float, default=4.0)
+    ap.add_argument("--rotation", type=float, default=0.0,
+                    help="Coriolis parameter f of a frame rotating about z; no LES or CPU leg")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -373,11 +382,19 @@ def main() -> int:
     log(f"generating the {n}^3 initial field")
     t0 = time.perf_counter()
     u0 = I.random_solenoidal_3d(n, seed=SEED, dtype=np.complex64)
+    if args.boussinesq:
+        # b: one solenoidal component of a second draw (same spectrum)
+        b0 = I.random_solenoidal_3d(n, seed=SEED + 1, dtype=np.complex64)[2]
+        u0 = np.concatenate([u0, b0[None]])
+        del b0
     state = torch.from_numpy(u0).to(dev)
     del u0
     log(f"initial field ready ({time.perf_counter() - t0:.1f} s)")
+    plain = not args.boussinesq and args.rotation == 0.0
     plan = fs.Plan(n, nu=NU, dt=DT, ndim=3, precision="f32", forcing_power=POWER,
-                   forcing_kmin=KMIN, forcing_kmax=KMAX, profile=not args.graphs)
+                   forcing_kmin=KMIN, forcing_kmax=KMAX, profile=not args.graphs,
+                   boussinesq=args.boussinesq, n2=args.n2 if args.boussinesq else 0.0,
+                   rotation=args.rotation)
     plan.step(state, args.warmup)
     torch.cuda.synchronize()
     if not args.graphs:
@@ -402,7 +419,7 @@ def main() -> int:
     tr = read_traffic()
     if not args.graphs:
         prof = plan.profile_read()
-        alg = algorithmic_bytes(n, args.steps)
+        alg = algorithmic_bytes(n, args.steps, nc=4 if args.boussinesq else 3)
         for name, (ms, cnt) in prof.items():
             rec = {"ms_total": ms, "launches": cnt, "ms_avg": ms / cnt}
             if name in alg and alg[name][1] == cnt:
@@ -412,7 +429,7 @@ def main() -> int:
             kernels[name] = rec
         dom = max((k for k in kernels if "alg_GBps" in kernels[k]), key=lambda k: kernels[k]["ms_total"])
         traffic = None
-        if tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
+        if plain and tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
             traffic = tr.get("bytes_per_launch", {}).get(dom)
         ach = kernels[dom]["alg_GBps"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -422,7 +439,7 @@ def main() -> int:
         step_alg = sum(v[0] for k, v in alg.items() if k != "p1") / args.steps
         roofline["step_alg_GBps"] = round(step_alg / (ms_per_step * 1e-3) / 1e9, 1)
 
-    if roofline is not None and tr and tr.get("source_hash") == kernel_source_hash() \
+    if plain and roofline is not None and tr and tr.get("source_hash") == kernel_source_hash() \
             and tr.get("n") == n:
         bpl = tr.get("bytes_per_launch", {})
         names = [k for k in ("z_stage", "x_c2r_product_r2c", "y_inverse", "y_forward")
@@ -432,7 +449,7 @@ def main() -> int:
         roofline["step_measured_frac"] = round(roofline["step_measured_GBps"] / HBM_PEAK_GBS, 4)
 
     les = None
-    if args.les_n > 0 and args.les_n < n:
+    if plain and args.les_n > 0 and args.les_n < n:
         les = closure_les_speed(fs, torch, plan, state, args.les_n, args.les_steps, ms_per_step)
     extras = {}
     if not args.no_extras:
@@ -448,7 +465,7 @@ def main() -> int:
         log(f"ensemble: {ens['gridpoint_steps_per_s']:.3e} gridpoint-steps/s")
 
     cpu = None
-    if not args.no_cpu:
+    if plain and not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
         cpu = cpu_baseline(args.cpu_seconds)
 
@@ -468,7 +485,10 @@ def main() -> int:
         "config": {"workload": f"3D forced isotropic turbulence {n}^3, velocity form, FP32, "
                                "nu=2e-4, dt=1e-3, random solenoidal E(k)~k^4 exp(-2(k/4)^2) unit "
                                "energy seed 1, constant-power forcing 5e-3 on 2<=|k|<=3, "
-                               "2/3 dealiasing, Lawson IF-RK4",
+                               "2/3 dealiasing, Lawson IF-RK4"
+                               + (f", Boussinesq N^2={args.n2} (b: second draw, seed 2)"
+                                  if args.boussinesq else "")
+                               + (f", rotating frame f={args.rotation}" if args.rotation else ""),
                    "n": n, "timing": "graph" if args.graphs else "per-kernel events"},
         "roofline": roofline,
         "cpu_baseline": cpu,
