@@ -617,6 +617,35 @@ void or_step2d(int n, double L, double nu, double dt, cplx *wh, int nsteps) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* The mean mode (k = 0) under the linear terms.  A periodic pressure has no */
+/* mean gradient, so nothing projects the mean: with Coriolis acceleration   */
+/* -f z x u the mean velocity obeys dux/dt = f uy, duy/dt = -f ux (an        */
+/* inertial oscillation, uz unchanged), and with buoyancy b z and the        */
+/* stratification -N2 uz the vertical mean and the mean buoyancy obey        */
+/* duz/dt = b, db/dt = -N2 uz.  Exactly, over a time t:                       */
+/*   ux' = cos(f t) ux + sin(f t) uy,   uy' = cos(f t) uy - sin(f t) ux,      */
+/*   uz' = cos(N t) uz + S b,           b'  = cos(N t) b - N2 S uz,           */
+/* with S = sin(N t) / N (t when N = 0).  Viscosity does not act at k = 0.    */
+/* in/out point at the mode of the first component; components ns apart;    */
+/* nc = 3 (velocity only) or 4 (velocity, buoyancy).                          */
+/* ------------------------------------------------------------------------ */
+static void mean_propagate(double f, double N2, double t, const cplx *in, int64_t ns, int nc,
+                           cplx *out) {
+  const cplx ux = in[0], uy = in[ns], uz = in[2 * ns];
+  const double cf = cos(f * t), sf = sin(f * t);
+  out[0] = cf * ux + sf * uy;
+  out[ns] = cf * uy - sf * ux;
+  if (nc == 3) {
+    out[2 * ns] = uz;
+    return;
+  }
+  const cplx b = in[3 * ns];
+  const double Nb = sqrt(N2), cn = cos(Nb * t), S = Nb > 0 ? sin(Nb * t) / Nb : t;
+  out[2 * ns] = cn * uz + S * b;
+  out[3 * ns] = cn * b - N2 * S * uz;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Rotating frame (3D): Coriolis acceleration -f z x u.  On solenoidal fields */
 /* its projection is -sigma khat x u with sigma = f kz / |k|, a rotation about */
 /* khat, so the linear part (viscosity + rotation) has the exact propagator   */
@@ -632,8 +661,12 @@ static void rot_apply(int n, double L, double nu, double f, double t, const cplx
     const int keep = keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n);
     const double k[3] = {kb * m[0], kb * m[1], kb * m[2]};
     const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    if (!keep || k2 == 0) {
+    if (!keep) {
       for (int c = 0; c < 3; c++) out[c * ns + i] = 0;
+      continue;
+    }
+    if (k2 == 0) {
+      mean_propagate(f, 0.0, t, in + i, ns, 3, out + i);
       continue;
     }
     const double kn = sqrt(k2), kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};
@@ -753,8 +786,12 @@ void or_strat_propagate(int n, double L, double nu, double N2, double t, const c
     const int keep = keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n);
     const double k[3] = {kb * m[0], kb * m[1], kb * m[2]};
     const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    if (!keep || k2 == 0) {
+    if (!keep) {
       for (int c = 0; c < 4; c++) out[c * ns + i] = 0;
+      continue;
+    }
+    if (k2 == 0) {
+      mean_propagate(0.0, N2, t, in + i, ns, 4, out + i);
       continue;
     }
     const double g2 = (k[0] * k[0] + k[1] * k[1]) / k2;
@@ -794,8 +831,12 @@ void or_stratrot_propagate(int n, double L, double nu, double N2, double f, doub
     const int keep = keep1(m[0], n) && keep1(m[1], n) && keep1(m[2], n);
     const double k[3] = {kb * m[0], kb * m[1], kb * m[2]};
     const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    if (!keep || k2 == 0) {
+    if (!keep) {
       for (int c = 0; c < 4; c++) out[c * ns + i] = 0;
+      continue;
+    }
+    if (k2 == 0) {
+      mean_propagate(f, N2, t, in + i, ns, 4, out + i);
       continue;
     }
     const double kn = sqrt(k2), kh[3] = {k[0] / kn, k[1] / kn, k[2] / kn};

@@ -50,6 +50,7 @@ def test_f_zero_is_the_plain_step(oracle_mod):
 def test_coriolis_written_out_agrees(oracle_mod):
     n, f, dt, steps = 16, 2.0, 1e-3, 10
     u0 = I.random_solenoidal_3d(n, seed=102) * kept_mask(n, 3)[None]
+    u0[:, 0, 0, 0] = [0.3, -0.2, 0.25]  # a mean flow (k2 := 1 below: P = I on it)
     kx, ky, kz = kmesh(n, 3)
     k2 = kx ** 2 + ky ** 2 + kz ** 2
     k2[k2 == 0] = 1.0
