@@ -90,6 +90,15 @@ enum { FS_SCHEME_RK4 = 0, FS_SCHEME_RK2 = 1 };
  *   rotation as well, the Coriolis force joins the exactly integrated terms
  *   (see fs_plan_opts.rotation); forcing acts on u; adaptive steps take their
  *   size from u.
+ * The mean mode (k = 0, 3D): a periodic pressure has no mean gradient, so the
+ *   linear terms act on the mean unprojected.  Over a time t the mean
+ *   velocity U and mean buoyancy B become
+ *     Ux' = cos(f t) Ux + sin(f t) Uy,  Uy' = cos(f t) Uy - sin(f t) Ux,
+ *     Uz' = cos(N t) Uz + S B,          B'  = cos(N t) B - n2 S Uz,
+ *   S = sin(N t)/N (t when N = 0), f = opts.rotation (0 without rotation),
+ *   N^2 = opts.n2 (Boussinesq plans; without buoyancy Uz is unchanged); the
+ *   nonlinear terms never change the mean (their mean is zero), so without
+ *   rotation or buoyancy the mean velocity is carried unchanged.
  * Diagnostics, transfer and 1D spectra describe the velocity (2D: vorticity)
  * part. */
 #define FS_BOUSSINESQ 0x8u

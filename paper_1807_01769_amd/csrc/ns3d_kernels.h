@@ -511,7 +511,13 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()
           if constexpr (mode_reads_state(MODE)) u[c] = a.state[c * cstride + so];
           if constexpr (mode_reads_acc(MODE)) acc[c] = a.acc[c * acstride + ao];
         }
-        if constexpr (PROP == kPropRot) {
+        if (k2 == (T)0) {
+          // the mean mode: the unprojected linear terms (rotation of the
+          // horizontal mean, buoyancy oscillation of the vertical mean)
+          MeanProp<T, NC> R;
+          R.set(a.rotf, prop_boussinesq(PROP) ? a.n2 : (T)0, dt);
+          prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+        } else if constexpr (PROP == kPropRot) {
           RotProp<T> R;
           const T ikn = k2 > (T)0 ? (T)1 / sqrt(k2) : (T)0;
           R.kh[0] = kx * ikn;

@@ -320,6 +320,54 @@ struct StratRotProp {
   }
 };
 
+// The mean mode (k = 0).  A periodic pressure has no mean gradient, so the
+// linear terms act on the mean unprojected: with Coriolis acceleration
+// -f z x u the horizontal mean turns (dux/dt = f uy, duy/dt = -f ux), and
+// with buoyancy the vertical mean and the mean buoyancy oscillate at N
+// (duz/dt = b, db/dt = -N^2 uz):
+//   ux' = c ux + s uy,  uy' = c uy - s ux         (c, s of f t),
+//   uz' = cn uz + sn b, b' = cn b - N^2 sn uz    (cn = cos N t, sn = sin(N t) / N,
+//                                                 t when N = 0).
+// NC = 3: velocity only (uz is carried unchanged).  Viscosity does not act at
+// k = 0 (the factor d passed in is 1 there).
+template <typename T, int NC_>
+struct MeanProp {
+  static constexpr int NC = NC_;
+  T cf, sf, ch, sh;      // Coriolis: cos and sin of f dt and of f dt / 2
+  T cnf, snf, cnh, snh;  // buoyancy: cos(N t) and sin(N t) / N at dt and dt / 2
+  T n2;
+  __device__ __forceinline__ void set(T f, T N2, T dt) {
+    cf = cos(f * dt);
+    sf = sin(f * dt);
+    ch = cos(f * dt * (T)0.5);
+    sh = sin(f * dt * (T)0.5);
+    n2 = N2;
+    const T nb = sqrt(N2);
+    cnf = cos(nb * dt);
+    cnh = cos(nb * dt * (T)0.5);
+    if (nb > (T)0) {
+      snf = sin(nb * dt) / nb;
+      snh = sin(nb * dt * (T)0.5) / nb;
+    } else {
+      snf = dt;
+      snh = dt * (T)0.5;
+    }
+  }
+  __device__ __forceinline__ void apply(const cx<T> (&w)[NC], T d, bool half,
+                                        cx<T> (&o)[NC]) const {
+    const T c = half ? ch : cf, s = half ? sh : sf;
+    o[0] = cscale(cscale(w[0], c) + cscale(w[1], s), d);
+    o[1] = cscale(cscale(w[1], c) - cscale(w[0], s), d);
+    if constexpr (NC == 4) {
+      const T cn = half ? cnh : cnf, sn = half ? snh : snf;
+      o[2] = cscale(cscale(w[2], cn) + cscale(w[3], sn), d);
+      o[3] = cscale(cscale(w[3], cn) - cscale(w[2], n2 * sn), d);
+    } else {
+      o[2] = cscale(w[2], d);
+    }
+  }
+};
+
 // The Lawson stage combinations of rk4_combine with a propagator acting on
 // the NC components of one mode.
 template <int MODE, class Prop, typename T, int NC>
