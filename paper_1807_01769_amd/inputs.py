@@ -37,6 +37,8 @@ __all__ = [
     "random_vorticity_2d",
     "tg_plus_noise_2d",
     "random_solenoidal_3d",
+    "broadband_solenoidal_3d",
+    "broadband_vorticity_2d",
     "ensemble_sizes",
     "ensemble_vorticity",
 ]
@@ -263,6 +265,76 @@ def random_solenoidal_3d(n: int, seed: int = 1, energy: float = 1.0,
         s = np.floor(np.sqrt(k2) + 0.5).astype(np.int64)
         out[:, iz] = u[:, iz] * scale[s][None]
     return out
+
+
+def _broadband_rms(kmag, n):
+    """Per-mode rms amplitude exp(-|m| / K) (K the largest kept mode): every
+    kept mode carries signal, from 1 at the origin to exp(-sqrt(3)) at the
+    corner of the kept cube (exp(-sqrt(2)) in 2D)."""
+    return np.exp(-kmag / float((n - 1) // 3))
+
+
+def broadband_solenoidal_3d(n: int, seed: int, energy: float = 1.0,
+                            dtype=np.complex128) -> np.ndarray:
+    """Random solenoidal velocity that fills the whole kept cube.
+
+    Unlike the turbulence recipe (whose spectrum peaks at |k| ~ 4 and is
+    negligible beyond |k| ~ 20), every kept mode gets two complex Gaussians on
+    the two unit vectors orthogonal to k, scaled by a per-mode rms that decays
+    only by exp(-|m| / K).  For checks that must see every tile of the kept
+    cube, its faces, edges and corner.  Draw order as in the other
+    generators; total energy 0.5*<|u|^2> = ``energy``."""
+    rng = np.random.default_rng(seed)
+    h = n // 2 + 1
+    full, half = mode_numbers(n)
+    kept_full = 3 * np.abs(full) < n
+    ky, kx = np.meshgrid(full.astype(np.float64), half.astype(np.float64), indexing="ij")
+    keep_plane = kept_full[:, None] & (3 * half < n)[None, :]
+    kp = np.sqrt(kx * kx + ky * ky)
+    on_axis = kp == 0
+    kps = np.where(on_axis, 1.0, kp)
+    e1x = np.where(on_axis, 1.0, ky / kps)
+    e1y = np.where(on_axis, 0.0, -kx / kps)
+    u = np.zeros((3, n, n, h), np.complex128)
+    ur = u.view(np.float64).reshape(3, n, n, h, 2)
+    for iz in range(n):
+        g = rng.standard_normal((n, h, 2, 2))
+        if not kept_full[iz]:
+            continue
+        kz = float(full[iz])
+        kmag = np.sqrt(kp * kp + kz * kz)
+        sup = keep_plane & (kmag > 0)
+        ik = np.where(sup, 1.0 / np.where(kmag > 0, kmag, 1.0), 0.0)
+        amp = _broadband_rms(kmag, n) * sup
+        e2x = np.where(on_axis, 0.0, kz * kx / kps) * ik
+        e2y = np.where(on_axis, kz, kz * ky / kps) * ik
+        e2z = np.where(on_axis, 0.0, -kp) * ik
+        for ri in range(2):
+            ga, gb = g[..., 0, ri] * amp, g[..., 1, ri] * amp
+            ur[0, iz, :, :, ri] = ga * e1x + gb * e2x
+            ur[1, iz, :, :, ri] = ga * e1y + gb * e2y
+            ur[2, iz, :, :, ri] = gb * e2z
+    _hermitian_kx0(u, 3)
+    w = _half_weight(kx)
+    e = 0.0
+    for iz in range(n):
+        e += 0.5 * float(np.sum(w * np.sum(np.abs(u[:, iz]) ** 2, axis=0)))
+    return (u * np.sqrt(energy / e)).astype(dtype)
+
+
+def broadband_vorticity_2d(n: int, seed: int, energy: float = 1.0) -> np.ndarray:
+    """Random vorticity that fills the whole kept square: complex Gaussian
+    coefficients with per-mode rms exp(-|m| / K) (K the largest kept mode),
+    total energy 0.5*<|u|^2> = ``energy``."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n, n // 2 + 1, 2))
+    kx, ky = _grids(n, 2)
+    kmag = np.sqrt(kx * kx + ky * ky)
+    sup = kept_cube(n, 2) & (kmag > 0)
+    w = np.where(sup, (g[..., 0] + 1j * g[..., 1]) * _broadband_rms(kmag, n), 0.0)
+    _hermitian_kx0(w, 2)
+    e = 0.5 * np.sum(_half_weight(kx) * np.abs(w) ** 2 / np.where(kmag > 0, kmag * kmag, 1.0))
+    return w * np.sqrt(energy / e)
 
 
 def ensemble_sizes(counts=((128, 128), (96, 256), (32, 512))):

@@ -40,9 +40,10 @@ def shell_modes(k0sq):
     return np.array(out)
 
 
-def beltrami_field(n, k0sq, seed, dtype):
+def beltrami_field(n, k0sq, seed, dtype, device=False):
     """Positive-helicity modes h = e1 + i e2 (e1 ⟂ k, e2 = khat x e1), random
-    complex amplitudes, on the shell |m|^2 = k0sq."""
+    complex amplitudes, on the shell |m|^2 = k0sq (device: the field is built
+    as a device tensor, for sizes whose host copy would be slow)."""
     rng = np.random.default_rng(seed)
     ms = shell_modes(k0sq)
     k = ms.astype(np.float64)
@@ -53,8 +54,15 @@ def beltrami_field(n, k0sq, seed, dtype):
     e2 = np.cross(kh, e1)
     amp = (rng.standard_normal(len(ms)) + 1j * rng.standard_normal(len(ms))) / np.sqrt(len(ms))
     h = (e1 + 1j * e2) * amp[:, None]
-    u = np.zeros((3, n, n, n // 2 + 1), dtype)
     iz, iy, ix = ms[:, 2] % n, ms[:, 1] % n, ms[:, 0]
+    if device:
+        u = torch.zeros((3, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+        hd = torch.from_numpy(h.astype(np.complex64)).cuda()
+        ti, tj, tk = (torch.from_numpy(a).cuda() for a in (iz, iy, ix))
+        for c in range(3):
+            u[c, ti, tj, tk] = hd[:, c]
+        return u, (iz, iy, ix), h
+    u = np.zeros((3, n, n, n // 2 + 1), dtype)
     for c in range(3):
         u[c, iz, iy, ix] = h[:, c]
     return u, (iz, iy, ix), h
@@ -71,17 +79,19 @@ def test_beltrami_field_is_exact_eigenfield():
 
 @pytest.mark.parametrize("n,k0sq,prec,f", [(256, 6254, "f64", 0.0), (512, 150 * 150, "f64", 0.0),
                                            (512, 150 * 150, "f32", 0.0),
-                                           (256, 6254, "f64", 40.0), (512, 150 * 150, "f32", 40.0)])
+                                           (256, 6254, "f64", 40.0), (512, 150 * 150, "f32", 40.0),
+                                           (1024, 300 * 300, "f32", 40.0)])
 def test_beltrami_decay_full_size(fs, n, k0sq, prec, f):
     print(f"case beltrami decay n={n} |m|^2={k0sq} {prec} rotation {f}", flush=True)
     nu, dt, steps = 2e-4, 1e-3, 5
     cd = np.complex128 if prec == "f64" else np.complex64
-    u, idx, h = beltrami_field(n, k0sq, 7, cd)
+    u, idx, h = beltrami_field(n, k0sq, 7, cd, device=n > 512)
     nmodes = len(idx[0])
     plan = fs.Plan(n, precision=prec, nu=nu, dt=dt, rotation=f)
-    d = torch.from_numpy(u).cuda()
+    d = u if n > 512 else torch.from_numpy(u).cuda()
     del u
     plan.step(d, steps)
+    torch.cuda.synchronize()
     got = d[:, idx[0], idx[1], idx[2]].cpu().numpy().T.astype(np.complex128)  # [modes][3]
     d[:, idx[0], idx[1], idx[2]] = 0
     rest = torch.view_as_real(d).abs().max().item()
@@ -92,10 +102,11 @@ def test_beltrami_decay_full_size(fs, n, k0sq, prec, f):
     err = np.abs(got - want).max() / np.abs(want).max()
     print(f"{nmodes} shell modes: rel err {err:.2e}; other modes {rest:.1e}", flush=True)
     # u x w vanishes only in exact arithmetic: its rounding, of order
-    # eps k0 |u|^2 with |w| = k0 |u| (k0 = 150 at 512^3), leaks into the modes
-    # off the shell at a few 1e-6 of the largest amplitude in FP32 (a few
-    # 1e-14 in FP64); the FP32 bound is the parity tolerance used elsewhere
+    # eps k0 |u|^2 with |w| = k0 |u|, leaks into the modes off the shell at a
+    # few 1e-6 of the largest amplitude in FP32 at k0 = 150 (a few 1e-14 in
+    # FP64); the bound on that leak is the parity tolerance used elsewhere at
+    # k0 = 150 and grows in proportion to k0 (k0 = 300 at 1024^3)
     tol = 1e-12 if prec == "f64" else 1e-5
     assert err <= tol
-    assert rest <= tol * np.abs(want).max()
+    assert rest <= tol * max(1.0, np.sqrt(k0sq) / 150.0) * np.abs(want).max()
     plan.close()

@@ -140,22 +140,25 @@ def test_plane_inertia_gravity_wave_fp64(fs):
     plan.close()
 
 
-def test_plane_inertia_gravity_wave_512(fs):
-    """The plane inertia-gravity wave through the 512^3 FP32 kernels."""
-    n, nu, N2, f, dt, steps = 512, 2e-4, 9.0, 4.0, 1e-3, 4
+@pytest.mark.parametrize("n,f", [(512, 4.0), (1024, 4.0), (1024, 0.0)])
+def test_plane_inertia_gravity_wave_full_size(fs, n, f):
+    """The plane inertia-gravity wave through the 512^3 and 1024^3 FP32
+    kernels (f = 0: the stratified propagator alone, at 1024^3 the
+    1024-thread z pass without the stash)."""
+    print(f"case plane inertia-gravity wave n={n} f={f}", flush=True)
+    nu, N2, dt, steps = 2e-4, 9.0, 1e-3, 4
     m = (6, 2, -5)
     w0 = _plane_mode(m)
-    s = np.zeros((4, n, n, n // 2 + 1), np.complex64)
-    s[:, m[2] % n, m[1] % n, m[0]] = w0
+    d = torch.zeros((4, n, n, n // 2 + 1), dtype=torch.complex64, device="cuda")
+    d[:, m[2] % n, m[1] % n, m[0]] = torch.from_numpy(w0.astype(np.complex64)).cuda()
     plan = fs.Plan(n, nu=nu, dt=dt, boussinesq=True, n2=N2, rotation=f)
-    d = torch.from_numpy(s).cuda()
-    del s
     plan.step(d, steps)
+    torch.cuda.synchronize()
     got = d[:, m[2] % n, m[1] % n, m[0]].cpu().numpy().astype(np.complex128)
     d[:, m[2] % n, m[1] % n, m[0]] = 0
     rest = torch.view_as_real(d).abs().max().item()
     want = expm(dt * steps * _mode_operator(m, nu, N2, f)) @ w0
-    print(f"inertia-gravity wave 512^3: err {np.abs(got - want).max():.2e}, "
+    print(f"inertia-gravity wave {n}^3 f={f}: err {np.abs(got - want).max():.2e}, "
           f"other modes {rest:.1e}", flush=True)
     assert np.abs(got - want).max() <= 2e-6
     assert rest <= 1e-6
