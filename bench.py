@@ -92,32 +92,47 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(seconds: float, n: int = 128) -> dict:
-    """The oracle's RK4 steps of the forced recipe on all host threads for
-    about `seconds`, then one step on a single thread."""
+def cpu_baseline(n: int = 512) -> dict:
+    """The oracle as it stands (plain FP64 C, OpenMP over transform lines, all
+    host threads), wall time: one RK4 step of the forced recipe at n^3 (the
+    headline size: no warm-up step, which would double the time), then the
+    two small reference workloads: 10 steps of the 3D Taylor-Green vortex at
+    128^3 and 100 FP64 steps of the 2D Taylor-Green + noise case at 128^2, and
+    one 128^3 step on a single thread."""
     import numpy as np
     import oracle
     from paper_1807_01769_amd import inputs as I
 
-    u = I.random_solenoidal_3d(n, seed=SEED).astype(np.complex64).astype(np.complex128)
     cores = oracle.get_threads()
-    steps, t = 0, 0.0
-    while t < seconds:
-        t0 = time.perf_counter()
-        u = oracle.step3d(u, NU, DT, 1, power=POWER, kf_min=KMIN, kf_max=KMAX)
-        t += time.perf_counter() - t0
-        steps += 1
-    ns = t / steps / n ** 3 * 1e9
-    oracle.set_threads(1)
+    u = I.random_solenoidal_3d(n, seed=SEED).astype(np.complex64).astype(np.complex128)
     t0 = time.perf_counter()
     oracle.step3d(u, NU, DT, 1, power=POWER, kf_min=KMIN, kf_max=KMAX)
-    t1 = time.perf_counter() - t0
+    t_head = time.perf_counter() - t0
+    del u
+    log(f"oracle: one {n}^3 step {t_head:.1f} s on {cores} threads")
+    tg = I.taylor_green_3d(128)
+    oracle.step3d(tg, 1.0 / 1600, 2e-3, 1)
+    t0 = time.perf_counter()
+    oracle.step3d(tg, 1.0 / 1600, 2e-3, 10)
+    t_m1 = time.perf_counter() - t0
+    w = I.tg_plus_noise_2d(128, seed=0)
+    t0 = time.perf_counter()
+    oracle.step2d(w, 1e-3, 1e-3, 100)
+    t_m0 = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.step3d(tg, 1.0 / 1600, 2e-3, 1)
+    t_1 = time.perf_counter() - t0
     oracle.set_threads(cores)
-    return {"value": ns, "unit": "ns/gridpoint/step", "cores": cores, "kind": "oracle",
-            "cpu": cpu_model(), "single_thread_value": t1 / n ** 3 * 1e9,
-            "sample": f"{steps} FP64 RK4 step(s) of the same forced-turbulence recipe at {n}^3 "
-                      f"on {cores} threads ({t:.1f} s), then 1 step on one thread ({t1:.1f} s); "
-                      f"per-point FFT work at {n}^3 is log2({n})/9 of 512^3's"}
+    return {"value": t_head / n ** 3 * 1e9, "unit": "ns/gridpoint/step", "cores": cores,
+            "kind": "oracle", "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"1 FP64 RK4 step of the same forced-turbulence recipe at {n}^3 on {cores} "
+                      f"threads ({t_head:.1f} s, no warm-up)",
+            "taylor_green_3d_128_10_steps": {"seconds": t_m1,
+                                             "ns_per_gridpoint_step": t_m1 / 10 / 128 ** 3 * 1e9},
+            "tg_noise_2d_128_fp64_100_steps": {"seconds": t_m0,
+                                               "ns_per_gridpoint_step": t_m0 / 100 / 128 ** 2 * 1e9},
+            "single_thread_128_ns_per_gridpoint_step": t_1 / 128 ** 3 * 1e9}
 
 
 LES_DT_FACTOR = 8  # LES step = 8 DNS steps (grid ratio 512 / 64)
@@ -213,7 +228,7 @@ def bench_ensemble(args) -> int:
         w = fields[0].astype(np.complex128)
         t = time.perf_counter()
         k = 0
-        while time.perf_counter() - t < args.cpu_seconds / 2:
+        while time.perf_counter() - t < 8.0:
             w = oracle.step2d(w, nu, dt, 1)
             k += 1
         el = time.perf_counter() - t
@@ -226,47 +241,6 @@ def bench_ensemble(args) -> int:
                                   "FP32, nu=1e-4, dt=5e-4, E(k)~k exp(-(k/6)^2), seeds 1000+r",
                       "gridpoints": pts},
            "alg_GBps": res["alg_GBps"], "schedule": res["schedule"], "cpu_baseline": cpu}
-    print(json.dumps(out), flush=True)
-    return 0
-
-
-# The paper's code comparison times ten RK4 steps of its 2D solver on random
-# initial fields, sequential on a Xeon E5-2695v4 (section "CFD pseudo-spectral
-# code comparisons", bidimensional table: 0.54 s at 512^2, 2.69 s at 1024^2).
-PAPER_2D_TEN_STEPS_S = {512: 0.54, 1024: 2.69}
-
-
-def bench_2d(args) -> int:
-    """Ten RK4 steps of one 2D plan (FP64, the paper's precision) on a random
-    vorticity field: the workload of the paper's 2D code comparison, timed as
-    the mean of repeated ten-step calls after a warm-up."""
-    import numpy as np
-    import torch
-    from paper_1807_01769_amd import fs, inputs as I
-
-    n = args.n
-    w = I.random_vorticity_2d(n, 1000, lambda k: k * np.exp(-(k / 6.0) ** 2))
-    d = torch.from_numpy(w).cuda()
-    plan = fs.Plan(n, ndim=2, precision="f64", nu=ENS_NU, dt=ENS_DT)
-    plan.step(d, 10)
-    torch.cuda.synchronize()
-    reps = max(1, args.steps)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        plan.step(d, 10)
-    torch.cuda.synchronize()
-    ten = (time.perf_counter() - t0) / reps
-    finite = bool(torch.isfinite(torch.view_as_real(d)).all())
-    plan.close()
-    ref = PAPER_2D_TEN_STEPS_S.get(n)
-    out = {"metric": "2D RK4: seconds for ten steps (the paper's code-comparison workload)",
-           "value": ten, "unit": "s / 10 steps", "n_gpus": 1, "steps": 10 * reps,
-           "higher_is_better": False, "dtype": "f64", "data": "synthetic", "finite": finite,
-           "config": {"workload": f"2D NS {n}^2, FP64, random vorticity E(k)~k exp(-(k/6)^2), "
-                                  f"nu={ENS_NU}, dt={ENS_DT}, one plan, ten steps per call"},
-           "paper_context": ({"seconds": ref, "hardware": "Xeon E5-2695v4, sequential, FluidSim"}
-                             if ref else None),
-           "vs_baseline": None}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -328,14 +302,18 @@ def copy_ceiling(torch, gib=2.0, reps=10):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50,
+                    help="timed graph-launched steps, split into --reps repetitions")
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=5,
+                    help="repetitions of the timed steps; ms_per_step is their median")
+    ap.add_argument("--breakdown-steps", type=int, default=10,
+                    help="steps of the per-kernel event pass after the timed region (0 = skip)")
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-n", type=int, default=512,
+                    help="grid of the oracle's timed step (the CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--graphs", action="store_true",
-                    help="time graph-launched steps (no per-kernel events)")
-    ap.add_argument("--workload", choices=["3d", "ensemble", "2d"], default="3d")
+    ap.add_argument("--workload", choices=["3d", "ensemble"], default="3d")
     ap.add_argument("--ens-steps", type=int, default=200)
     ap.add_argument("--les-n", type=int, default=64,
                     help="LES grid of the closure speedup measurement (0 = skip)")
@@ -367,8 +345,6 @@ def main() -> int:
         return 1
     if args.workload == "ensemble":
         return bench_ensemble(args)
-    if args.workload == "2d":
-        return bench_2d(args)
     n = args.n
     dev = torch.device("cuda:0")
     if args.calib_copy_gib > 0:
@@ -391,23 +367,35 @@ def main() -> int:
     del u0
     log(f"initial field ready ({time.perf_counter() - t0:.1f} s)")
     plain = not args.boussinesq and args.rotation == 0.0
+    variant_opts = dict(boussinesq=args.boussinesq, n2=args.n2 if args.boussinesq else 0.0,
+                        rotation=args.rotation)
     plan = fs.Plan(n, nu=NU, dt=DT, ndim=3, precision="f32", forcing_power=POWER,
-                   forcing_kmin=KMIN, forcing_kmax=KMAX, profile=not args.graphs,
-                   boussinesq=args.boussinesq, n2=args.n2 if args.boussinesq else 0.0,
-                   rotation=args.rotation)
+                   forcing_kmin=KMIN, forcing_kmax=KMAX, **variant_opts)
     plan.step(state, args.warmup)
     torch.cuda.synchronize()
-    if not args.graphs:
-        plan.profile_read()
     log(f"warmup done ({args.warmup} steps)")
 
+    # Timed region: exactly K graph-launched steps, in R repetitions of about
+    # K / R steps, each bracketed by HIP events on the plan's stream (torch's
+    # current stream, on which the plan was created); ms_per_step is the
+    # median over the repetitions of their time per step.
+    reps = max(1, min(args.reps, args.steps))
+    chunks = [args.steps // reps + (1 if r < args.steps % reps else 0) for r in range(reps)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in chunks]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan.step(state, args.steps)
+    for (e0, e1), c in zip(evs, chunks):
+        e0.record()
+        plan.step(state, c)
+        e1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step")
+    rep_ms = [e0.elapsed_time(e1) / c for (e0, e1), c in zip(evs, chunks)]
+    ms_per_step = float(np.median(rep_ms))
+    host_ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"timed {args.steps} steps in {reps} repetitions: median {ms_per_step:.3f} ms/step "
+        f"(repetitions {', '.join(f'{v:.3f}' for v in rep_ms)}; host clock {host_ms_per_step:.3f})")
 
     _, e, z = plan.energy_spectrum(state)
     energy, enstrophy = float(e.cpu()), float(z.cpu())
@@ -415,11 +403,26 @@ def main() -> int:
         print("non-finite state after the timed steps", file=sys.stderr)
         return 1
 
+    # Per-kernel breakdown: the same step on a plan that launches its kernels
+    # directly and brackets each with HIP events on the plan's stream, for
+    # `--breakdown-steps` steps right after the timed region; the roofline of
+    # the dominant kernel uses these per-launch averages.
     kernels, roofline = {}, None
     tr = read_traffic()
-    if not args.graphs:
+    bsteps = args.breakdown_steps
+    if bsteps > 0:
+        plan.close()
+        plan = fs.Plan(n, nu=NU, dt=DT, ndim=3, precision="f32", forcing_power=POWER,
+                       forcing_kmin=KMIN, forcing_kmax=KMAX, profile=True, **variant_opts)
+        plan.step(state, 1)
+        torch.cuda.synchronize()
+        plan.profile_read()
+        tb0 = time.perf_counter()
+        plan.step(state, bsteps)
+        torch.cuda.synchronize()
+        prof_ms_per_step = (time.perf_counter() - tb0) * 1e3 / bsteps
         prof = plan.profile_read()
-        alg = algorithmic_bytes(n, args.steps, nc=4 if args.boussinesq else 3)
+        alg = algorithmic_bytes(n, bsteps, nc=4 if args.boussinesq else 3)
         for name, (ms, cnt) in prof.items():
             rec = {"ms_total": ms, "launches": cnt, "ms_avg": ms / cnt}
             if name in alg and alg[name][1] == cnt:
@@ -435,18 +438,21 @@ def main() -> int:
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "alg_bytes_per_launch": kernels[dom]["alg_bytes_per_launch"],
-                    "ms_avg": kernels[dom]["ms_avg"]}
-        step_alg = sum(v[0] for k, v in alg.items() if k != "p1") / args.steps
+                    "ms_avg": kernels[dom]["ms_avg"],
+                    "kernel_timing": f"HIP events around every launch on the plan's stream, "
+                                     f"{bsteps} directly launched steps after the timed region "
+                                     f"({prof_ms_per_step:.3f} ms/step on the host clock)"}
+        step_alg = sum(v[0] for k, v in alg.items() if k != "p1") / bsteps
         roofline["step_alg_GBps"] = round(step_alg / (ms_per_step * 1e-3) / 1e9, 1)
+        roofline["step_alg_frac"] = round(roofline["step_alg_GBps"] / HBM_PEAK_GBS, 4)
 
-    if plain and roofline is not None and tr and tr.get("source_hash") == kernel_source_hash() \
-            and tr.get("n") == n:
-        bpl = tr.get("bytes_per_launch", {})
-        names = [k for k in ("z_stage", "x_c2r_product_r2c", "y_inverse", "y_forward")
-                 if k in bpl and k in kernels]
-        step_bytes = sum(bpl[k] * kernels[k]["launches"] for k in names) / args.steps
-        roofline["step_measured_GBps"] = round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1)
-        roofline["step_measured_frac"] = round(roofline["step_measured_GBps"] / HBM_PEAK_GBS, 4)
+        if plain and tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
+            bpl = tr.get("bytes_per_launch", {})
+            names = [k for k in ("z_stage", "x_c2r_product_r2c", "y_inverse", "y_forward")
+                     if k in bpl and k in kernels]
+            step_bytes = sum(bpl[k] * kernels[k]["launches"] for k in names) / bsteps
+            roofline["step_measured_GBps"] = round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1)
+            roofline["step_measured_frac"] = round(roofline["step_measured_GBps"] / HBM_PEAK_GBS, 4)
 
     les = None
     if plain and args.les_n > 0 and args.les_n < n:
@@ -467,16 +473,27 @@ def main() -> int:
     cpu = None
     if plain and not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
-        cpu = cpu_baseline(args.cpu_seconds)
+        cpu = cpu_baseline(args.cpu_n)
 
+    # the stratified and rotating variants are other workloads: their own metric
+    # name and a structured variant, so that no collector mixes them with the
+    # headline forced-turbulence step
+    variant = None if plain else {"boussinesq": bool(args.boussinesq),
+                                  "n2": args.n2 if args.boussinesq else 0.0,
+                                  "rotation_f": args.rotation}
+    metric = METRIC if plain else (
+        "RK4 step ns/gridpoint, 3D " + ("rotating " if args.rotation else "")
+        + ("Boussinesq (stratified) " if args.boussinesq else "") + f"flow {n}^3 FP32")
     out = {
-        "metric": METRIC,
+        "metric": metric,
         "value": ms_per_step * 1e6 / n ** 3,
         "unit": "ns/gridpoint/step",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_repetitions": rep_ms,
+        "host_ms_per_step": host_ms_per_step,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -489,7 +506,10 @@ def main() -> int:
                                + (f", Boussinesq N^2={args.n2} (b: second draw, seed 2)"
                                   if args.boussinesq else "")
                                + (f", rotating frame f={args.rotation}" if args.rotation else ""),
-                   "n": n, "timing": "graph" if args.graphs else "per-kernel events"},
+                   "n": n,
+                   "timing": f"graph-launched steps, median of {reps} repetitions of "
+                             f"{'/'.join(str(c) for c in chunks)} steps (HIP events)",
+                   "variant": variant},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "closure_les": les,
