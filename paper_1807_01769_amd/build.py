@@ -11,7 +11,7 @@ SRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libfs.so")
-SOURCES = ["ops3d.hip", "ops2d.hip", "ens2d.hip", "mlp.hip", "closure.hip", "diag.hip", "fs_api.cpp"]
+SOURCES = ["ops3d_f32.hip", "ops3d_f32_strat.hip", "ops3d_f64.hip", "ops3d_f64_strat.hip", "ops3d.hip", "ops2d.hip", "ens2d.hip", "mlp.hip", "closure.hip", "diag.hip", "fs_api.cpp"]
 ARCH = os.environ.get("FS_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
