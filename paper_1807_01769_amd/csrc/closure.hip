@@ -314,7 +314,7 @@ fs_status fs_closure_create(fs_closure** out, fs_plan* fine, fs_plan* coarse) {
   const size_t wfull = sizeof(cf) * 9 * coarse->p.ops.elems_full;
   const size_t o_wa = cv.take(wfull), o_wb = cv.take(wfull);
   fs_closure* c = new fs_closure;
-  if (hipMalloc(&c->base, cv.total) != hipSuccess) {
+  if (fs::dev_malloc(&c->base, cv.total) != hipSuccess) {
     hipGetLastError();
     delete c;
     return fail(FS_E_NOMEM, "hipMalloc of %zu bytes failed", cv.total);
@@ -573,7 +573,7 @@ fs_status fs_les_create(fs_les** out, fs_plan* coarse, fs_mlp* model, float a_sc
                  o_tau = cv.take(sizeof(float) * 6 * np),
                  o_wa = cv.take(sizeof(cf) * 9 * coarse->p.ops.elems_full),
                  o_wb = cv.take(sizeof(cf) * 9 * coarse->p.ops.elems_full);
-    if (hipMalloc(&les->base, cv.total) != hipSuccess) {
+    if (fs::dev_malloc(&les->base, cv.total) != hipSuccess) {
       hipGetLastError();
       delete les;
       return fail(FS_E_NOMEM, "hipMalloc of %zu bytes failed", cv.total);

@@ -367,7 +367,7 @@ fs_status fs_ensemble_create(fs_ensemble** out, int nruns, const int* n, double 
   }
   const size_t scratch_off = total;
   total += fs::a256(scratch);
-  if (hipMalloc(&e->base, total) != hipSuccess) {
+  if (fs::dev_malloc(&e->base, total) != hipSuccess) {
     hipGetLastError();
     delete h;
     fs::set_error("hipMalloc of %zu bytes failed", total);

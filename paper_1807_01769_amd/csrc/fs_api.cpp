@@ -7,7 +7,9 @@
 #include <cstdint>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +28,42 @@ void set_error(const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
+}
+
+namespace {
+std::mutex g_alloc_mu;
+std::string g_alloc_hook;  // last value of FS_TEST_FAIL_ALLOC seen
+long g_alloc_count = 0;    // allocations since it took that value
+
+bool injected_failure() {
+  const char* v = std::getenv("FS_TEST_FAIL_ALLOC");
+  std::lock_guard<std::mutex> lock(g_alloc_mu);
+  if (!v || !*v) {
+    g_alloc_hook.clear();
+    return false;
+  }
+  if (g_alloc_hook != v) {
+    g_alloc_hook = v;
+    g_alloc_count = 0;
+  }
+  return ++g_alloc_count == std::atol(v);
+}
+}  // namespace
+
+hipError_t dev_malloc(void** ptr, size_t bytes) {
+  if (injected_failure()) {
+    *ptr = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(ptr, bytes);
+}
+
+hipError_t pinned_malloc(void** ptr, size_t bytes) {
+  if (injected_failure()) {
+    *ptr = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipHostMalloc(ptr, bytes, hipHostMallocDefault);
 }
 
 bool Plan::ok(hipError_t e, const char* what) {
@@ -320,7 +358,7 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   if (o.workspace) {
     p->base = o.workspace;
     p->owns_base = false;
-  } else if (hipMalloc(&p->base, total) != hipSuccess) {
+  } else if (fs::dev_malloc(&p->base, total) != hipSuccess) {
     hipGetLastError();
     delete h;
     return fail(FS_E_NOMEM, "hipMalloc of %zu bytes failed", total);
@@ -343,13 +381,14 @@ fs_status fs_plan_create(fs_plan** out, int n, double L, double nu, double dt,
   p->nonfin = (unsigned*)(b + off[9] + 24);
   p->dpart_blocks = fs::kDiagMaxBlocks;
   if ((o.flags & FS_CHECK_FINITE) &&
-      (!p->ok(hipHostMalloc((void**)&p->nonfin_host, sizeof(unsigned), hipHostMallocDefault),
-              "pinned flag") ||
+      (!p->ok(fs::pinned_malloc((void**)&p->nonfin_host, sizeof(unsigned)), "pinned flag") ||
        !p->ok(hipEventCreateWithFlags(&p->nonfin_ev, hipEventDisableTiming), "flag event"))) {
     std::string msg = fs::g_err;
+    const bool nomem = p->nonfin_host == nullptr;
+    hipGetLastError();
     release(p);
     delete h;
-    return fail(FS_E_DEVICE, "%s", msg.c_str());
+    return fail(nomem ? FS_E_NOMEM : FS_E_DEVICE, "%s", msg.c_str());
   }
   if (p->nonfin_host) *p->nonfin_host = 0;
 

@@ -121,6 +121,14 @@ struct Plan {
 };
 
 void set_error(const char* fmt, ...);
+
+// Every device and pinned-host allocation of the library goes through these.
+// Test hook: while the environment variable FS_TEST_FAIL_ALLOC holds "k"
+// (optionally followed by a tag, "2#plan"), the k-th allocation counted from
+// the moment the variable took its current value fails as if the device were
+// out of memory, so that the FS_E_NOMEM paths can be exercised.
+hipError_t dev_malloc(void** ptr, size_t bytes);
+hipError_t pinned_malloc(void** ptr, size_t bytes);
 // check the launch just made; marks the plan failed on error
 bool launched(Plan* p, const char* what);
 

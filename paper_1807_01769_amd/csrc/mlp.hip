@@ -473,7 +473,7 @@ fs_status fs_mlp_create(fs_mlp** out, uint64_t seed, void* stream) {
   const size_t bytes = 4 * (4 * np + 64) + sizeof(fs::s4) * fs::NBLK * 64 +
                        4 * (size_t)n->nwaves * (np + 1) + 8 * (size_t)fs::kMaxGroups * (np + 1) +
                        2048;
-  if (hipMalloc(&n->base, bytes) != hipSuccess) {
+  if (fs::dev_malloc(&n->base, bytes) != hipSuccess) {
     hipGetLastError();
     delete h;
     fs::set_error("hipMalloc failed");
