@@ -136,6 +136,13 @@ class Plan:
         self.real_dtype = {"f32": torch.float32, "f64": torch.float64}[precision]
         self.complex_dtype = {"f32": torch.complex64, "f64": torch.complex128}[precision]
         self.stream = stream
+        # the physics options, as given (what a checkpoint needs to rebuild the plan)
+        self.options = {"n": self.n, "L": self.L, "nu": self.nu, "dt": self.dt,
+                        "ndim": self.ndim, "precision": precision,
+                        "forcing_power": float(forcing_power),
+                        "forcing_kmin": float(forcing_kmin), "forcing_kmax": float(forcing_kmax),
+                        "scheme": scheme, "cfl": float(cfl), "boussinesq": bool(boussinesq),
+                        "n2": float(n2), "rotation": float(rotation)}
         o = _opts(ndim, precision, forcing_power, forcing_kmin, forcing_kmax, graphs, profile,
                   scheme, cfl, boussinesq, n2, rotation, check_finite)
         o.stream = _stream_ptr(stream)
