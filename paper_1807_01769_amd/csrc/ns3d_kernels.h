@@ -25,7 +25,7 @@ namespace fs {
 
 // ---------------------------------------------------------------------------
 // X pass: for each row pair (y0, y0+1) at height z, inverse-transform
-// (ux,uy) (uz,wx) (wy,wz) of each row, form p = (u x w) * scale, forward
+// (ux,uy) (uz,wz) (wx,wy) of each row, form p = (u x w) * scale, forward
 // transform (px + i py) of each row and (pz(y0) + i pz(y1)), store kept kx.
 // One transform line is in flight at a time and the cross product is built
 // as its factors arrive (u kept, partial products accumulated).  The kept
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
       stage_rows(1);
       __syncthreads();
     }
-    T ux[8], uy[8], uz[8], qy[8], qz[8];
+    T ux[8], uy[8], uz[8], qx[8], qy[8];
     cx<T> v[1][8];
     inverse_pair(0, r, v);
 #pragma unroll
@@ -180,9 +180,9 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
       uz[e] = v[0][e].re;
       if (umax)
         um = fmax(um, (double)fmax(fmax(fabs(ux[e]), fabs(uy[e])), fabs(uz[e])));
-      const T wx = v[0][e].im;
-      qy[e] = uz[e] * wx;   // py = uz wx - ux wz
-      qz[e] = -uy[e] * wx;  // pz = ux wy - uy wx
+      const T wz = v[0][e].im;
+      qx[e] = uy[e] * wz;   // px = uy wz - uz wy
+      qy[e] = -ux[e] * wz;  // py = uz wx - ux wz
     }
     if constexpr (STRAT) {
       // buoyancy flux u b (b carries the scale): (fx + i fy) now, fz paired
@@ -201,16 +201,16 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
     inverse_pair(2, r, v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
-      const T wy = v[0][e].re, wz = v[0][e].im;
-      const T pz = (qz[e] + ux[e] * wy) * scale;
-      v[0][e] = {(uy[e] * wz - uz[e] * wy) * scale, (qy[e] - ux[e] * wz) * scale};
+      const T wx = v[0][e].re, wy = v[0][e].im;
+      const T pz = (ux[e] * wy - uy[e] * wx) * scale;
+      v[0][e] = {(qx[e] - uz[e] * wy) * scale, (qy[e] + uz[e] * wx) * scale};
       if (r == 0) pz0[e] = pz;
-      else qz[e] = pz;
+      else qx[e] = pz;
     }
     forward_store(v, 0, y0 + r, 1, y0 + r);
     if (r == 1) {
 #pragma unroll
-      for (int e = 0; e < 8; e++) v[0][e] = {pz0[e], qz[e]};
+      for (int e = 0; e < 8; e++) v[0][e] = {pz0[e], qx[e]};
       forward_store(v, 2, y0, 2, y0 + 1);
     }
   }
@@ -249,8 +249,12 @@ __device__ __forceinline__ const cx<T>* zpass_twiddles(const cx<T>* __restrict__
 // ---------------------------------------------------------------------------
 // Inverse z transforms of the six fields (u, w = i k x v) of a stage input v
 // held in registers as v[c][e] at z-position t + e*P of line b; writes
-// Wm[6][N][XT][M][16] (fields ordered ux uy uz wx wy wz).  NC = 4 adds the
-// buoyancy v[3] as field 6.
+// Wm[6][N][XT][M][16] with the fields ordered ux uy uz wz wx wy, so that the
+// x pass's complex lines (fields 2g, 2g+1) pair (ux, uy), (uz, wz), (wx, wy):
+// no component of u x w multiplies the real and imaginary parts of one line
+// (the rounding of a complex transform couples its two parts, and a product
+// of the two would carry that coupling as a bias into the mean over rows).
+// NC = 4 adds the buoyancy v[3] as field 6.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NC, class TW>
 __device__ __forceinline__ void z_inverse_six(cx<T> (&v)[NC][8], int t, int b, int jy, int xt,
@@ -280,7 +284,7 @@ __device__ __forceinline__ void z_inverse_six(cx<T> (&v)[NC][8], int t, int b, i
       w[0][e] = r;
     }
     fft_lines<T, N, +1, 1>(w, t, lds, lidx, tw);
-    cx<T>* dst = dst0 + (3 + c) * fstride;
+    cx<T>* dst = dst0 + (3 + (c + 1) % 3) * fstride;  // wz, wx, wy in fields 3, 4, 5
 #pragma unroll
     for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = w[0][e];
   }
