@@ -351,6 +351,8 @@ fs_status fs_ensemble_destroy(fs_ensemble *ens); /* NULL is a no-op */
  * Features: BF16 [npts][16], the 9 inputs in slots 0..8, slots 9..15 zero.
  * Targets and outputs: FP32 [npts][6].  All arrays are device memory.
  * The network owns its parameters, moments and scratch (allocated once).
+ * The architecture is fixed: the matrix-core kernels chain the three layers
+ * in registers with lane layouts specific to these widths.
  */
 typedef struct fs_mlp fs_mlp;
 /* Xavier-uniform weights from a counter-based hash of (seed, index), zero
