@@ -249,6 +249,27 @@ fs_status fs_energy_spectrum(fs_plan *plan, const void *state, double *spectrum,
                              double *energy, double *enstrophy);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * diagnostics of fs_energy_spectrum without a plan and without any
+ * allocation.  The state is described by (ndim, n, precision, L) as a plan
+ * with those values would describe it (same layout and supported sizes); the
+ * results are bit for bit those of fs_energy_spectrum.  The block partial
+ * sums live in a static device array of 8 MiB, one copy per device, held
+ * until the process ends: a call needing more, blocks * (nbins + 2) doubles
+ * with blocks = min(rows / 4, 1024), rows = M^2 in 3D and M in 2D,
+ * M = 2 floor((n-1)/3) + 1 (nbins > 1022 at the largest grids), is rejected
+ * with FS_E_INVALID.
+ * Enqueued on `stream` (a hipStream_t; NULL = null stream) with no
+ * synchronisation; calls that overlap on one device share the array and race.
+ * Errors: FS_E_INVALID / FS_E_UNSUPPORTED before anything is enqueued,
+ * FS_E_DEVICE if the device or the launch fails.
+ */
+fs_status fs_energy_spectrum_static(int ndim, int n, int precision, double L, const void *state,
+                                    double *spectrum, int nbins, double *energy,
+                                    double *enstrophy, void *stream);
+
+/*
  * 1D spectra ("spectra as functions of ... a component of the wavenumber",
  * section "Implementation and architecture"): the energy of each velocity
  * component binned by the modulus of one wavenumber component,

@@ -7,6 +7,7 @@
 // then a second kernel summing block partials in block order), so a rerun on
 // the same input gives the same bits.
 #include <cmath>
+#include <mutex>
 
 #include "fft_core.h"
 #include "fs_internal.h"
@@ -635,6 +636,49 @@ void launch_fill(Plan* p, void* ptr, size_t n_complex) {
   p->end(KID_FILL);
 }
 
+// ---------------------------------------------------------------------------
+// Diagnostics without a plan and without allocation.  The block partial sums
+// of k_diag1 go to a file-scope device array instead of a plan's workspace;
+// every device the library runs on holds its own copy until the process ends.
+// Each call writes every partial it later reads (nbins + 2 values per block),
+// so nothing needs clearing between calls; calls that overlap on one device
+// share the array and race.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticDiagDoubles = (size_t)1 << 20;  // 8 MiB
+static __device__ __align__(256) double scratch[kStaticDiagDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// the address of this device's copy of `scratch` (the host-side name is only
+// a stand-in for it); looked up once per device, with that device current
+double* scratch_on(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[dev] = (double*)ptr;
+  }
+  return g_scratch[dev];
+}
+
+template <typename T>
+void diag_static(int ndim, int n, double L, const void* state, double* spectrum, int nbins,
+                 double* energy, double* enstrophy, double* part, int blocks, hipStream_t s) {
+  const int K = (n - 1) / 3;
+  hipLaunchKernelGGL((k_diag1<T, false>), dim3(blocks), dim3(kDiagThreads), 0, s,
+                     (const cx<T>*)state, (const cx<T>*)nullptr, ndim, n, K, 2.0 * M_PI / L, nbins,
+                     part);
+  hipLaunchKernelGGL(k_diag2, dim3(1), dim3(kDiagThreads), 0, s, (const double*)part, blocks,
+                     nbins, spectrum, energy, enstrophy);
+}
+}  // namespace
+
 template void launch_diag<float>(Plan*, const void*, double*, int, double*, double*);
 template void launch_diag<double>(Plan*, const void*, double*, int, double*, double*);
 template void launch_transfer<float>(Plan*, const void*, const void*, double*, double*, int,
@@ -653,3 +697,68 @@ template void launch_fill<float>(Plan*, void*, size_t);
 template void launch_fill<double>(Plan*, void*, size_t);
 
 }  // namespace fs
+
+extern "C" fs_status fs_energy_spectrum_static(int ndim, int n, int precision, double L,
+                                               const void* state, double* spectrum, int nbins,
+                                               double* energy, double* enstrophy, void* stream) {
+  using namespace fs;
+  if (ndim != 2 && ndim != 3) {
+    set_error("ndim = %d must be 2 or 3", ndim);
+    return FS_E_INVALID;
+  }
+  if (precision != FS_F32 && precision != FS_F64) {
+    set_error("precision = %d must be FS_F32 or FS_F64", precision);
+    return FS_E_INVALID;
+  }
+  if (n < 16 || n > 1024 || (n & (n - 1)) || (ndim == 3 && precision == FS_F64 && n > 512)) {
+    set_error("n = %d: supported sizes are the plans' (powers of two 16..1024, 3D FP64 <= 512)", n);
+    return FS_E_UNSUPPORTED;
+  }
+  if (!(std::isfinite(L) && L > 0)) {
+    set_error("L must be finite and > 0");
+    return FS_E_INVALID;
+  }
+  if (!state || !spectrum) {
+    set_error("NULL array");
+    return FS_E_INVALID;
+  }
+  if (nbins < 1 || nbins > kDiagMaxBins) {
+    set_error("nbins = %d must be in 1..%d", nbins, kDiagMaxBins);
+    return FS_E_INVALID;
+  }
+  // the same partial-sum grid as the plan's reduction, so the results agree bit for bit
+  const int K = (n - 1) / 3, M = 2 * K + 1;
+  const int rows = ndim == 3 ? M * M : M;
+  int blocks = (rows + kWaves - 1) / kWaves;
+  if (blocks > kDiagMaxBlocks) blocks = kDiagMaxBlocks;
+  const size_t need = (size_t)blocks * (size_t)(nbins + 2);
+  if (need > kStaticDiagDoubles) {
+    set_error("nbins = %d at n = %d needs %zu bytes of partial sums; the static scratch holds "
+              "%zu (fs_energy_spectrum with a plan has no such limit)",
+              nbins, n, need * sizeof(double), kStaticDiagDoubles * sizeof(double));
+    return FS_E_INVALID;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    hipGetLastError();
+    set_error("no usable HIP device");
+    return FS_E_DEVICE;
+  }
+  double* part = scratch_on(dev);
+  if (!part) {
+    set_error("hipGetSymbolAddress of the static scratch failed");
+    return FS_E_DEVICE;
+  }
+  if (precision == FS_F32)
+    diag_static<float>(ndim, n, L, state, spectrum, nbins, energy, enstrophy, part, blocks,
+                       (hipStream_t)stream);
+  else
+    diag_static<double>(ndim, n, L, state, spectrum, nbins, energy, enstrophy, part, blocks,
+                        (hipStream_t)stream);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("diagnostics launch: %s", hipGetErrorString(e));
+    return FS_E_DEVICE;
+  }
+  return FS_OK;
+}

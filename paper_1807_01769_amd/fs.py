@@ -61,6 +61,7 @@ lib.fs_fft_inverse.argtypes = [_vp, _vp, _vp]
 lib.fs_tendency.argtypes = [_vp, _vp, _vp]
 lib.fs_step_rk4.argtypes = [_vp, _vp, _i]
 lib.fs_energy_spectrum.argtypes = [_vp, _vp, _vp, _i, _vp, _vp]
+lib.fs_energy_spectrum_static.argtypes = [_i, _i, _i, _d, _vp, _vp, _i, _vp, _vp, _vp]
 lib.fs_energy_transfer.argtypes = [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp]
 lib.fs_energy_spectra_1d.argtypes = [_vp, _vp, _vp]
 lib.fs_structure_functions.argtypes = [_vp, _vp, _i, _vp, _i, _vp]
@@ -114,6 +115,29 @@ def _opts(ndim=3, precision="f32", forcing_power=0.0, forcing_kmin=2.0, forcing_
     o.scheme = {"rk4": FS_SCHEME_RK4, "rk2": FS_SCHEME_RK2}[scheme]
     o.cfl = float(cfl)
     return o
+
+
+def energy_spectrum_static(state: torch.Tensor, ndim: int, n: int, precision: str = "f32",
+                           nbins: int | None = None, L: float = 2 * math.pi, stream=None):
+    """fs_energy_spectrum_static: the plan-free, allocation-free diagnostics of
+    a state (device tensors spectrum[nbins], energy[1], enstrophy[1], float64;
+    the caller allocates them here, the library allocates nothing)."""
+    cdt = {"f32": torch.complex64, "f64": torch.complex128}[precision]
+    h = n // 2 + 1
+    shape = (3, n, n, h) if ndim == 3 else (n, h)
+    if tuple(state.shape) != shape or state.dtype != cdt or not state.is_cuda \
+            or not state.is_contiguous():
+        raise ValueError(f"state must be a contiguous {cdt} device tensor of shape {shape}")
+    if nbins is None:
+        K = (n - 1) // 3
+        nbins = int(math.floor(math.sqrt(ndim) * K + 0.5)) + 1  # as fs_spectrum_bins
+    spec = torch.empty(int(nbins), dtype=torch.float64, device=state.device)
+    ez = torch.empty(2, dtype=torch.float64, device=state.device)
+    _check(lib.fs_energy_spectrum_static(int(ndim), int(n), FS_F32 if precision == "f32" else FS_F64,
+                                         float(L), state.data_ptr(), spec.data_ptr(), int(nbins),
+                                         ez.data_ptr(), ez.data_ptr() + 8, _stream_ptr(stream)),
+           "fs_energy_spectrum_static")
+    return spec, ez[0:1], ez[1:2]
 
 
 class Plan:
