@@ -217,14 +217,23 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
   if (umax) umax_wave(umax, um);
 }
 
-// The fused z passes keep three components plus a transform line in registers
-// (at most 512 threads per block below N = 1024; at 1024, 1024-thread blocks of
-// eight lines, so a block covers half of each 128-byte row instead of a quarter).  In single precision their twiddles come
-// from a copy of the table in LDS and the compiler is asked for 4 waves per
-// SIMD (two blocks per CU), so the memory phases of one block overlap the
-// transforms of the other; double precision keeps the register budget.
-template <typename T, int N>
-using ZCfg = Strided<T, N, cmin(kTile, cmax(1, (N >= 1024 ? 1024 : 512) / (N / 8)))>;
+// The fused z passes keep three components plus a transform line in registers.
+// Lines per block: a block of 1024 threads covers a whole 128-byte row of the
+// tile-blocked layout (16 lines) at N = 512 in single precision (velocity
+// only: one block per CU, 132 KB of LDS with the stash, 4 waves per SIMD);
+// otherwise at most 512 threads below N = 1024 (two blocks per CU, each
+// covering part of each row, merged in L2), and 1024-thread blocks of eight
+// lines at N = 1024.  Full-row blocks measured 913 -> 840 us per 512^3 launch.
+// In single precision their twiddles come from a copy of the table in LDS and
+// the compiler is asked for 4 waves per SIMD (2 with buoyancy, whose pass
+// needs twice the registers); double precision keeps the register budget.
+// NC: state components (4 with buoyancy).
+template <typename T, int N, int NC = 3>
+using ZCfg = Strided<T, N, cmin(kTile, cmax(1, ((N >= 1024 || (N == 512 && sizeof(T) == 4 &&
+                                                                  NC == 3))
+                                                     ? 1024
+                                                     : 512) /
+                                                    (N / 8)))>;
 // linear propagator of a fused z pass
 enum LinearProp : int { kPropVisc = 0, kPropRot = 1, kPropStrat = 2, kPropStratRot = 3 };
 // the propagators of Boussinesq flow, whose state carries the buoyancy too
@@ -262,7 +271,7 @@ __device__ __forceinline__ void z_inverse_six(cx<T> (&v)[NC][8], int t, int b, i
                                               cx<T>* __restrict__ w1, cx<T>* lds,
                                               const TW& tw) {
   using G = Geo<N, false>;
-  using C = ZCfg<T, N>;
+  using C = ZCfg<T, N, NC>;
   constexpr int P = G::P;
   const size_t fstride = (size_t)N * G::XT * G::M * kTile;
   cx<T>* dst0 = w1 + (size_t)xt * G::M * kTile + (size_t)jy * kTile + sub * C::LB + b;
@@ -335,10 +344,10 @@ __device__ __forceinline__ T recip(T x) {
 // Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NC = 3>
-__global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
+__global__ void __launch_bounds__((ZCfg<T, N, NC>::THREADS))
     k3_p1(const cx<T>* __restrict__ state, cx<T>* __restrict__ w1, StageArgs<T> a) {
   using G = Geo<N, false>;
-  using C = ZCfg<T, N>;
+  using C = ZCfg<T, N, NC>;
   constexpr int P = G::P;
   constexpr int NH = N / 2 + 1;
   __shared__ cx<T> lds[C::LB * N];
@@ -386,10 +395,11 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
 // seven inverse transforms).  Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE, int PROP = kPropVisc>
-__global__ void __launch_bounds__((ZCfg<T, N>::THREADS), (zpass_waves<T, PROP>()))
+__global__ void __launch_bounds__((ZCfg<T, N, prop_boussinesq(PROP) ? 4 : 3>::THREADS),
+                                  (zpass_waves<T, PROP>()))
     k3_z(const cx<T>* __restrict__ w4, cx<T>* __restrict__ w1, StageArgs<T> a, int do_p1) {
   using G = Geo<N, false>;
-  using C = ZCfg<T, N>;
+  using C = ZCfg<T, N, prop_boussinesq(PROP) ? 4 : 3>;
   constexpr int P = G::P;
   constexpr int NH = N / 2 + 1;
   constexpr int NC = prop_boussinesq(PROP) ? 4 : 3;

@@ -45,7 +45,7 @@ struct L3 {
   using GF = Geo<N, true>;
   using C = Strided<T, N>;
   using YC = Strided<T, N, kYLines>;
-  using ZC = ZCfg<T, N>;
+  using ZC = ZCfg<T, N, NC>;
   using R = RowPairs<N>;
   static cx<T>* A(Plan* p) { return (cx<T>*)p->bufA; }
   static cx<T>* B(Plan* p) { return (cx<T>*)p->bufB; }
