@@ -29,7 +29,7 @@ METRIC = "RK4 step ns/gridpoint at 512³ FP32, % HBM roofline; closure-LES vs DN
 HBM_PEAK_GBS = 8000.0
 NU, DT, POWER, KMIN, KMAX, SEED = 2e-4, 1e-3, 5e-3, 2.0, 3.0, 1
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3d_512.txt")
-KERNEL_SOURCES = ["fft_core.h", "ns_common.h", "ns3d_kernels.h", "ops3d.hip"]
+KERNEL_SOURCES = ["fft_core.h", "ns_common.h", "ns3d_kernels.h", "ops3d_impl.h"]
 
 
 def log(*a):

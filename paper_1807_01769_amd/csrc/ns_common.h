@@ -433,57 +433,122 @@ __device__ __forceinline__ void umax_wave(unsigned long long* umax, double m) {
 
 // ---------------------------------------------------------------------------
 // Strided passes along y: blocks of [XT][M][16] <-> [XT][N][16].
-// rows = fields * z extent; grid xcd_grid(rows, XT * SUB).
+// rows = fields * z extent; grid xcd_grid(rows, XT * YCfg::SUB).
+//
+// A block transforms whole 128-byte tile rows (16 lines) where it can.  Up to
+// N = 512 that is 16 lanes groups of N/8 threads; at N = 1024 in single
+// precision 16 groups would need 2048 threads, so each lane carries two
+// adjacent lines (F = 2), read and written as one 16-byte access: eight lanes
+// then cover a 128-byte row in one instruction (128 KB of LDS per block).
+// Elsewhere the block holds LB < 16 lines (LDS and thread limits).
 // ---------------------------------------------------------------------------
-template <typename T, int N, bool FULL>
-__global__ void __launch_bounds__((Strided<T, N, kYLines>::THREADS))
-    k_y_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-            const cx<T>* __restrict__ tw, int rows) {
-  using G = Geo<N, FULL>;
-  using C = Strided<T, N, kYLines>;
-  __shared__ cx<T> lds[C::LB * N];
-  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
-  const Twiddles<T, N, false> twr(tw, t);
-  int row, rem;
-  if (!xcd_row_block(rows, G::XT * C::SUB, row, rem)) return;  // whole block
-  const int sub = rem % C::SUB;
-  const size_t tile = (size_t)row * G::XT + rem / C::SUB;  // row = field*nz + z
-  const cx<T>* src = in + tile * G::M * kTile + sub * C::LB + b;
-  cx<T> v[1][8];
-#pragma unroll
-  for (int e = 0; e < 8; e++) {
-    const int j = G::i2j(t + e * G::P);
-    v[0][e] = j >= 0 ? ld_nt(&src[j * kTile]) : cx<T>{0, 0};
+template <typename T, int N>
+struct YCfg {
+  static constexpr int P = N / 8;
+  static constexpr bool kPair =
+      sizeof(T) == 4 && kTile * P > 1024 && (size_t)kTile * N * sizeof(cx<T>) <= 163840;
+  static constexpr int F = kPair ? 2 : 1;                              // lines per lane
+  static constexpr int LB = kPair ? kTile / 2 : Strided<T, N, kYLines>::LB;  // lane groups
+  static constexpr int LINES = LB * F;                                 // lines per block
+  static constexpr int SUB = kTile / LINES;
+  static constexpr int THREADS = LB * P;
+};
+
+// F lines of lane group b at one position: F = 1 one value, F = 2 the two
+// adjacent lines 2b, 2b + 1 as one 16-byte access (non-temporal)
+template <typename T, int F>
+__device__ __forceinline__ void ld_lines(const cx<T>* p, cx<T> (&v)[F][8], int e) {
+  if constexpr (F == 1) {
+    v[0][e] = ld_nt(p);
+  } else {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    const v4 x = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p));
+    v[0][e] = cx<T>{x.x, x.y};
+    v[1][e] = cx<T>{x.z, x.w};
   }
-  fft_lines<T, N, +1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
-  cx<T>* dst = out + tile * N * kTile + sub * C::LB + b;
-#pragma unroll
-  for (int e = 0; e < 8; e++) st_nt(&dst[(t + e * G::P) * kTile], v[0][e]);
+}
+template <typename T, int F>
+__device__ __forceinline__ void st_lines(cx<T>* p, const cx<T> (&v)[F][8], int e) {
+  if constexpr (F == 1) {
+    st_nt(p, v[0][e]);
+  } else {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    v4 x;
+    x.x = v[0][e].re;
+    x.y = v[0][e].im;
+    x.z = v[1][e].re;
+    x.w = v[1][e].im;
+    __builtin_nontemporal_store(x, reinterpret_cast<v4*>(p));
+  }
 }
 
 template <typename T, int N, bool FULL>
-__global__ void __launch_bounds__((Strided<T, N, kYLines>::THREADS))
-    k_y_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+__global__ void __launch_bounds__((YCfg<T, N>::THREADS))
+    k_y_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
             const cx<T>* __restrict__ tw, int rows) {
   using G = Geo<N, FULL>;
-  using C = Strided<T, N, kYLines>;
-  __shared__ cx<T> lds[C::LB * N];
+  using C = YCfg<T, N>;
+  constexpr int F = C::F;
+  __shared__ cx<T> lds[C::LINES * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
   const Twiddles<T, N, false> twr(tw, t);
   int row, rem;
   if (!xcd_row_block(rows, G::XT * C::SUB, row, rem)) return;  // whole block
   const int sub = rem % C::SUB;
   const size_t tile = (size_t)row * G::XT + rem / C::SUB;  // row = field*nz + z
-  const cx<T>* src = in + tile * N * kTile + sub * C::LB + b;
-  cx<T> v[1][8];
-#pragma unroll
-  for (int e = 0; e < 8; e++) v[0][e] = src[(t + e * G::P) * kTile];
-  fft_lines<T, N, -1, 1>(v, t, lds, [=](int, int pos) { return pos * C::LB + b; }, twr);
-  cx<T>* dst = out + tile * G::M * kTile + sub * C::LB + b;
+  const cx<T>* src = in + tile * G::M * kTile + sub * C::LINES + F * b;
+  cx<T> v[F][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int j = G::i2j(t + e * G::P);
-    if (j >= 0) st_nt(&dst[j * kTile], v[0][e]);
+    if (j >= 0) {
+      ld_lines<T, F>(&src[j * kTile], v, e);
+    } else {
+#pragma unroll
+      for (int f = 0; f < F; f++) v[f][e] = cx<T>{0, 0};
+    }
+  }
+  fft_lines<T, N, +1, F>(v, t, lds, [=](int f, int pos) { return pos * C::LINES + F * b + f; },
+                         twr);
+  cx<T>* dst = out + tile * N * kTile + sub * C::LINES + F * b;
+#pragma unroll
+  for (int e = 0; e < 8; e++) st_lines<T, F>(&dst[(t + e * G::P) * kTile], v, e);
+}
+
+template <typename T, int N, bool FULL>
+__global__ void __launch_bounds__((YCfg<T, N>::THREADS))
+    k_y_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+            const cx<T>* __restrict__ tw, int rows) {
+  using G = Geo<N, FULL>;
+  using C = YCfg<T, N>;
+  constexpr int F = C::F;
+  __shared__ cx<T> lds[C::LINES * N];
+  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  const Twiddles<T, N, false> twr(tw, t);
+  int row, rem;
+  if (!xcd_row_block(rows, G::XT * C::SUB, row, rem)) return;  // whole block
+  const int sub = rem % C::SUB;
+  const size_t tile = (size_t)row * G::XT + rem / C::SUB;  // row = field*nz + z
+  const cx<T>* src = in + tile * N * kTile + sub * C::LINES + F * b;
+  cx<T> v[F][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    if constexpr (F == 1) {
+      v[0][e] = src[(t + e * G::P) * kTile];
+    } else {
+      typedef T v4 __attribute__((ext_vector_type(4)));
+      const v4 x = *reinterpret_cast<const v4*>(&src[(t + e * G::P) * kTile]);
+      v[0][e] = cx<T>{x.x, x.y};
+      v[1][e] = cx<T>{x.z, x.w};
+    }
+  }
+  fft_lines<T, N, -1, F>(v, t, lds, [=](int f, int pos) { return pos * C::LINES + F * b + f; },
+                         twr);
+  cx<T>* dst = out + tile * G::M * kTile + sub * C::LINES + F * b;
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int j = G::i2j(t + e * G::P);
+    if (j >= 0) st_lines<T, F>(&dst[j * kTile], v, e);
   }
 }
 

@@ -44,7 +44,7 @@ struct L3 {
   using G = Geo<N, false>;
   using GF = Geo<N, true>;
   using C = Strided<T, N>;
-  using YC = Strided<T, N, kYLines>;
+  using YC = YCfg<T, N>;
   using ZC = ZCfg<T, N, NC>;
   using R = RowPairs<N>;
   static cx<T>* A(Plan* p) { return (cx<T>*)p->bufA; }
