@@ -6,8 +6,8 @@
 // chains; fs_ensemble_step_rk4 captures all of them, for all requested steps,
 // as parallel branches of one hipGraph and launches it once.
 //
-// Schedules: the y passes can use 16, 8 or 4 kx lines per block and the x
-// pass one or two times the default row pairs per block.  At creation an
+// Schedules: the y passes can use 16, 8, 4 or 2 kx lines per block and the
+// x pass one, two or four times the default row pairs per block.  At creation an
 // autotuner times every candidate of every class on the class's own
 // workspace (a measured plan choice in the manner of FFTW's MEASURE
 // planning) and keeps the fastest; choices are cached per (size, runs,
@@ -31,8 +31,8 @@ namespace fs {
 namespace {
 
 constexpr int kEnsSizes[] = {64, 128, 256, 512};
-constexpr int kYCand[] = {16, 8, 4};  // lines per y-pass block
-constexpr int kXCand[] = {1, 2};      // multiples of the default row pairs
+constexpr int kYCand[] = {16, 8, 4, 2};  // lines per y-pass block
+constexpr int kXCand[] = {1, 2, 4};   // multiples of the default row pairs
 
 struct EnsClass {
   int n = 0, nruns = 0;
@@ -132,7 +132,8 @@ void dispatch_p1(const Ensemble* e, const EnsClass& c, void* st, hipStream_t s) 
   switch (c.ylines) {
     case 16: launch_p1<N, 16>(e, c, st, s); break;
     case 8: launch_p1<N, 8>(e, c, st, s); break;
-    default: launch_p1<N, 4>(e, c, st, s); break;
+    case 4: launch_p1<N, 4>(e, c, st, s); break;
+    default: launch_p1<N, 2>(e, c, st, s); break;
   }
 }
 template <int N>
@@ -140,16 +141,29 @@ void dispatch_y(const Ensemble* e, const EnsClass& c, void* st, int mode, int do
   switch (c.ylines) {
     case 16: launch_y<N, 16>(e, c, st, mode, do_p1, s); break;
     case 8: launch_y<N, 8>(e, c, st, mode, do_p1, s); break;
-    default: launch_y<N, 4>(e, c, st, mode, do_p1, s); break;
+    case 4: launch_y<N, 4>(e, c, st, mode, do_p1, s); break;
+    default: launch_y<N, 2>(e, c, st, mode, do_p1, s); break;
   }
+}
+// row pairs per x-pass block: xmul times the default, as long as the block
+// stays within the run's row pairs (and so within 64 KiB of LDS)
+template <int N>
+constexpr int x_rowpairs(int xmul) {
+  constexpr int RP0 = RowPairs<N>::RP;
+  return (xmul >= 4 && 4 * RP0 <= N / 2) ? 4 * RP0 : (xmul >= 2 && 2 * RP0 <= N / 2) ? 2 * RP0 : RP0;
 }
 template <int N>
 void dispatch_x(const Ensemble* e, const EnsClass& c, hipStream_t s) {
   constexpr int RP0 = RowPairs<N>::RP;
-  if (c.xmul == 2 && 2 * RP0 <= N / 2)
-    launch_x<N, 2 * RP0>(e, c, s);
-  else
-    launch_x<N, RP0>(e, c, s);
+  switch (x_rowpairs<N>(c.xmul) / RP0) {
+    case 4:
+      if constexpr (4 * RP0 <= N / 2) launch_x<N, 4 * RP0>(e, c, s);
+      break;
+    case 2:
+      if constexpr (2 * RP0 <= N / 2) launch_x<N, 2 * RP0>(e, c, s);
+      break;
+    default: launch_x<N, RP0>(e, c, s); break;
+  }
 }
 
 void class_p1(const Ensemble* e, const EnsClass& c, void* st, hipStream_t s) {
@@ -467,14 +481,14 @@ fs_status fs_ensemble_schedule(const fs_ensemble* ens, int cls, int* n, int* nru
   if (n) *n = c.n;
   if (nruns) *nruns = c.nruns;
   if (y_lines) *y_lines = c.ylines;
-  int rp0 = 1;
+  int rp = 1;
   switch (c.n) {
-    case 64: rp0 = fs::RowPairs<64>::RP; break;
-    case 128: rp0 = fs::RowPairs<128>::RP; break;
-    case 256: rp0 = fs::RowPairs<256>::RP; break;
-    default: rp0 = fs::RowPairs<512>::RP; break;
+    case 64: rp = fs::x_rowpairs<64>(c.xmul); break;
+    case 128: rp = fs::x_rowpairs<128>(c.xmul); break;
+    case 256: rp = fs::x_rowpairs<256>(c.xmul); break;
+    default: rp = fs::x_rowpairs<512>(c.xmul); break;
   }
-  if (x_rowpairs) *x_rowpairs = (c.xmul == 2 && 2 * rp0 <= c.n / 2) ? 2 * rp0 : rp0;
+  if (x_rowpairs) *x_rowpairs = rp;
   if (us_y) *us_y = c.us_y;
   if (us_x) *us_x = c.us_x;
   return FS_OK;
