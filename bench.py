@@ -60,25 +60,41 @@ def algorithmic_bytes(n: int, steps: int, elem: int = 8, nc: int = 3) -> dict:
     """Bytes each kernel class must move in `steps` steps if only kept modes
     travel (the dealias-pruned model): per field, Us = M*M*H (state), Uzm =
     N*M*H (after the z pass), Uzn = N*N*H (after the y pass) complex values,
-    with K = (N-1)//3, M = 2K+1, H = K+1.  nc = 4: Boussinesq flow (u, b),
-    seven inverse fields (u, w, b) and six forward ones (u x w, u b)."""
+    with K = (N-1)//3, M = 2K+1, H = K+1.  The x pass reads six fields (u,
+    w) and writes three (u x w); the z pass writes five of the six (the
+    vertical vorticity, which needs no kz, is formed by the inverse y pass
+    from ux, uy).  nc = 4: Boussinesq flow (u, b), one more inverse field and
+    three more forward ones (u b)."""
     K = (n - 1) // 3
     M, H = 2 * K + 1, K + 1
     Us, Uzm, Uzn = M * M * H * elem, n * M * H * elem, n * n * H * elem
     fi, ff = (6, 3) if nc == 3 else (7, 6)
+    fz = fi - 1
     launches = {"y_inverse": 4 * steps, "x_c2r_product_r2c": 4 * steps,
                 "y_forward": 4 * steps, "z_stage": 4 * steps, "p1": 1}
     total = {
-        "y_inverse": 4 * steps * (fi * Uzm + fi * Uzn),
+        "y_inverse": 4 * steps * (fz * Uzm + fi * Uzn),
         "x_c2r_product_r2c": 4 * steps * (fi * Uzn + ff * Uzn),
         "y_forward": 4 * steps * (ff * Uzn + ff * Uzm),
         # read the products, write the next stage's inverse fields (not after
         # the last stage), RK4 state/accumulator traffic 10 Us per component
         # and step
-        "z_stage": 4 * steps * ff * Uzm + (4 * steps - 1) * fi * Uzm + steps * 10 * nc * Us,
-        "p1": nc * Us + fi * Uzm,
+        "z_stage": 4 * steps * ff * Uzm + (4 * steps - 1) * fz * Uzm + steps * 10 * nc * Us,
+        "p1": nc * Us + fz * Uzm,
     }
     return {k: (total[k], launches[k]) for k in total}
+
+
+def unfused_model_bytes(n: int) -> float:
+    """Bytes per step of the unfused pruned schedule (separate passes per
+    stage: z inverse reads 3 and writes 6 kept-column fields, y inverse 6/6,
+    x 6/3, y forward 3/3, z forward reads 3; the RK4 epilogue 42 field
+    traffics per step), with f = M/N the kept fraction per full axis and C
+    the bytes of one real single-precision field, 4 N^3:
+    (4 (3 f^3 + 18 f^2 + 18 f) + 42 f^3) C, about 385 B per grid point."""
+    K = (n - 1) // 3
+    f = (2 * K + 1) / n
+    return (4 * (3 * f ** 3 + 18 * f ** 2 + 18 * f) + 42 * f ** 3) * 4.0 * n ** 3
 
 
 def cpu_model() -> str:
@@ -445,6 +461,9 @@ def main() -> int:
         step_alg = sum(v[0] for k, v in alg.items() if k != "p1") / bsteps
         roofline["step_alg_GBps"] = round(step_alg / (ms_per_step * 1e-3) / 1e9, 1)
         roofline["step_alg_frac"] = round(roofline["step_alg_GBps"] / HBM_PEAK_GBS, 4)
+        if not args.boussinesq:
+            roofline["step_unfused_model_frac"] = round(
+                unfused_model_bytes(n) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
         if plain and tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
             bpl = tr.get("bytes_per_launch", {})

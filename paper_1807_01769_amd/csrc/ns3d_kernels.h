@@ -6,8 +6,9 @@
 //
 //   Z  (z, fwd + inv)  previous stage's products -> forward z transform ->
 //                      projection, forcing, Lawson RK4 combine -> next stage
-//                      input -> curl -> six inverse z transforms   [k3_z]
-//   Yi (y, inverse)    six fields                                 [k_y_inv]
+//                      input -> curl -> five inverse z transforms
+//                      (u, wx, wy)                                [k3_z]
+//   Yi (y, inverse)    five fields in, wz formed, six out         [k_y_inv_step]
 //   X  (x, c2r / r2c)  six C2R, u x w, three R2C                  [k3_x]
 //   Yf (y, forward)    three fields                               [k_y_fwd]
 //
@@ -16,7 +17,7 @@
 // and writes the H kept kx values of every row.
 //
 // Stratified (Boussinesq) flow carries a buoyancy field b as a fourth state
-// component: the inverse passes move seven fields (u, w, b), the x pass also
+// component: the inverse passes move six and seven fields (u, w, b), the x pass also
 // forms the buoyancy flux u b, and the forward passes move six (u x w, u b).
 #pragma once
 #include "ns_common.h"
@@ -256,20 +257,16 @@ __device__ __forceinline__ const cx<T>* zpass_twiddles(const cx<T>* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Inverse z transforms of the six fields (u, w = i k x v) of a stage input v
-// held in registers as v[c][e] at z-position t + e*P of line b; writes
-// Wm[6][N][XT][M][16] with the fields ordered ux uy uz wz wx wy, so that the
-// x pass's complex lines (fields 2g, 2g+1) pair (ux, uy), (uz, wz), (wx, wy):
-// no component of u x w multiplies the real and imaginary parts of one line
-// (the rounding of a complex transform couples its two parts, and a product
-// of the two would carry that coupling as a bias into the mean over rows).
-// NC = 4 adds the buoyancy v[3] as field 6.
+// Inverse z transforms of a stage input v held in registers as v[c][e] at
+// z-position t + e*P of line b: the velocity and the horizontal vorticity
+// (wx, wy; w = i k x v), written to Wm[5][N][XT][M][16] as ux uy uz wx wy.
+// The vertical vorticity needs no kz and is formed by the inverse y pass.
+// NC = 4 adds the buoyancy v[3] as field 5.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NC, class TW>
-__device__ __forceinline__ void z_inverse_six(cx<T> (&v)[NC][8], int t, int b, int jy, int xt,
-                                              int sub, int mx, int my, T kb,
-                                              cx<T>* __restrict__ w1, cx<T>* lds,
-                                              const TW& tw) {
+__device__ __forceinline__ void z_inverse(cx<T> (&v)[NC][8], int t, int b, int jy, int xt,
+                                          int sub, int mx, int my, T kb,
+                                          cx<T>* __restrict__ w1, cx<T>* lds, const TW& tw) {
   using G = Geo<N, false>;
   using C = ZCfg<T, N, NC>;
   constexpr int P = G::P;
@@ -280,20 +277,17 @@ __device__ __forceinline__ void z_inverse_six(cx<T> (&v)[NC][8], int t, int b, i
   const T kx = kb * (T)mx, ky = kb * (T)my;
   // vorticity first (needs v), then velocity in place
 #pragma unroll
-  for (int c = 0; c < 3; c++) {
+  for (int c = 0; c < 2; c++) {
     cx<T> w[1][8];
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       const int iz = t + e * P;
       const T kz = kb * (T)(iz <= N / 2 ? iz : iz - N);
-      cx<T> r;
-      if (c == 0) r = mul_i(cscale(v[2][e], ky) - cscale(v[1][e], kz));
-      else if (c == 1) r = mul_i(cscale(v[0][e], kz) - cscale(v[2][e], kx));
-      else r = mul_i(cscale(v[1][e], kx) - cscale(v[0][e], ky));
-      w[0][e] = r;
+      w[0][e] = c == 0 ? mul_i(cscale(v[2][e], ky) - cscale(v[1][e], kz))
+                       : mul_i(cscale(v[0][e], kz) - cscale(v[2][e], kx));
     }
     fft_lines<T, N, +1, 1>(w, t, lds, lidx, tw);
-    cx<T>* dst = dst0 + (3 + (c + 1) % 3) * fstride;  // wz, wx, wy in fields 3, 4, 5
+    cx<T>* dst = dst0 + (3 + c) * fstride;  // wx, wy in fields 3, 4
 #pragma unroll
     for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = w[0][e];
   }
@@ -303,7 +297,7 @@ __device__ __forceinline__ void z_inverse_six(cx<T> (&v)[NC][8], int t, int b, i
 #pragma unroll
     for (int e = 0; e < 8; e++) w[0][e] = v[c][e];
     fft_lines<T, N, +1, 1>(w, t, lds, lidx, tw);
-    cx<T>* dst = dst0 + (c < 3 ? c : 6) * fstride;
+    cx<T>* dst = dst0 + (c < 3 ? c : 5) * fstride;
 #pragma unroll
     for (int e = 0; e < 8; e++) dst[(size_t)(t + e * P) * zstride] = w[0][e];
   }
@@ -340,7 +334,7 @@ __device__ __forceinline__ T recip(T x) {
 // ---------------------------------------------------------------------------
 // First inverse pass of a stage, from the caller's state (ABI layout
 // [NC][N][N][N/2+1]): masks to the kept set, records the band values, and
-// writes the six (NC = 4: seven) inverse-z-transformed fields.
+// writes the five (NC = 4: six) inverse-z-transformed fields.
 // Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NC = 3>
@@ -380,19 +374,19 @@ __global__ void __launch_bounds__((ZCfg<T, N, NC>::THREADS))
       }
     }
   }
-  z_inverse_six<T, N, NC>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
+  z_inverse<T, N, NC>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
 }
 
 // ---------------------------------------------------------------------------
 // Z pass: forward z transforms of the stage's products (Wm[3][N][XT][M][16]),
 // projection + forcing -> tendency of this stage, Lawson RK4 combine, and
-// (do_p1) the next stage's six inverse z transforms into w1.
+// (do_p1) the next stage's five (six) inverse z transforms into w1.
 // MODE kModeTend writes the tendency to a.tend instead.  PROP selects the
 // linear propagator of the combine: viscosity, + rotation (about z), or
 // + buoyancy force and stratification (kPropStrat, and with rotation too
 // kPropStratRot: products Wm[6], the
 // flux u b giving the buoyancy tendency -i k.(u b)^, four state components,
-// seven inverse transforms).  Grid: M * XT * SUB.
+// six inverse transforms).  Grid: M * XT * SUB.
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MODE, int PROP = kPropVisc>
 __global__ void __launch_bounds__((ZCfg<T, N, prop_boussinesq(PROP) ? 4 : 3>::THREADS),
@@ -587,7 +581,7 @@ __global__ void __launch_bounds__((ZCfg<T, N, prop_boussinesq(PROP) ? 4 : 3>::TH
     if (a.nonfin) flag_wave(a.nonfin, bad);
   }
   if constexpr (MODE != kModeTend) {
-    if (do_p1) z_inverse_six<T, N, NC>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
+    if (do_p1) z_inverse<T, N, NC>(v, t, b, jy, xt, sub, mx, my, a.kb, w1, lds, twr);
   }
 }
 

@@ -440,13 +440,18 @@ __device__ __forceinline__ void umax_wave(unsigned long long* umax, double m) {
 // precision 16 groups would need 2048 threads, so each lane carries two
 // adjacent lines (F = 2), read and written as one 16-byte access: eight lanes
 // then cover a 128-byte row in one instruction (128 KB of LDS per block).
+// The inverse pass of a stage (STEP), whose (ux, uy, wz) unit holds two
+// lines per lane at once and so runs at 4 waves per SIMD, pairs lines from
+// N = 256 on: at N = 512, 512-thread blocks of 16 lines, two per CU, keep as
+// many lines in flight per CU as the 8-wave single-line blocks would.
 // Elsewhere the block holds LB < 16 lines (LDS and thread limits).
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+template <typename T, int N, bool STEP = false>
 struct YCfg {
   static constexpr int P = N / 8;
-  static constexpr bool kPair =
-      sizeof(T) == 4 && kTile * P > 1024 && (size_t)kTile * N * sizeof(cx<T>) <= 163840;
+  static constexpr bool kPair = sizeof(T) == 4 &&
+                                (STEP ? N >= 256 : kTile * P > 1024) &&
+                                (size_t)kTile * N * sizeof(cx<T>) <= 163840;
   static constexpr int F = kPair ? 2 : 1;                              // lines per lane
   static constexpr int LB = kPair ? kTile / 2 : Strided<T, N, kYLines>::LB;  // lane groups
   static constexpr int LINES = LB * F;                                 // lines per block
@@ -513,6 +518,115 @@ __global__ void __launch_bounds__((YCfg<T, N>::THREADS))
   cx<T>* dst = out + tile * N * kTile + sub * C::LINES + F * b;
 #pragma unroll
   for (int e = 0; e < 8; e++) st_lines<T, F>(&dst[(t + e * G::P) * kTile], v, e);
+}
+
+// The pointer as a value the compiler cannot see through: loads from it
+// stay below this point (loads through a read-only kernel argument may
+// otherwise be scheduled anywhere, barriers included).
+template <typename P>
+__device__ __forceinline__ P* opaque_ptr(P* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Inverse y pass of a stage: Wm (fields ux uy uz wx wy [b]) -> Wn (fields ux
+// uy uz wz wx wy [b]).  The vertical vorticity wz = i (kx uy - ky ux) needs
+// no kz, so it is formed here from the ux, uy lines the pass reads anyway
+// rather than transformed and stored by the z pass: one field fewer written
+// there and read here.  Each z plane has `units` row units: unit 0 reads ux,
+// uy and writes ux, uy, wz; unit u >= 1 carries Wm field u + 1 to Wn field
+// u + 2 (uz to field 2).  rows = units * N; grid xcd_grid(rows, XT * SUB).
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__((YCfg<T, N, true>::THREADS), 4)
+    k_y_inv_step(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                 const cx<T>* __restrict__ tw, T kb, int rows) {
+  using G = Geo<N, false>;
+  using C = YCfg<T, N, true>;
+  constexpr int F = C::F;
+  constexpr int P = G::P;
+  __shared__ cx<T> lds[C::LINES * N];
+  const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;
+  int row, rem;
+  if (!xcd_row_block(rows, G::XT * C::SUB, row, rem)) return;  // whole block
+  const int unit = row / N, z = row % N;
+  const int xt = rem / C::SUB;
+  const int lane = (rem % C::SUB) * C::LINES + F * b;  // first line of the lane in its tile
+  auto lidx = [=](int f, int pos) { return pos * C::LINES + F * b + f; };
+  const size_t zoff = (size_t)z * G::XT + xt;
+  const int fin = unit == 0 ? 0 : unit + 1;
+  const int fout = unit == 0 ? 0 : (unit == 1 ? 2 : unit + 2);
+  const cx<T>* src = in + (zoff + (size_t)fin * N * G::XT) * G::M * kTile + lane;
+  cx<T>* dst = out + (zoff + (size_t)fout * N * G::XT) * N * kTile + lane;
+  cx<T> v[F][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int j = G::i2j(t + e * P);
+    if (j >= 0) {
+      ld_lines<T, F>(&src[j * kTile], v, e);
+    } else {
+#pragma unroll
+      for (int f = 0; f < F; f++) v[f][e] = cx<T>{0, 0};
+    }
+  }
+  if (unit != 0) {
+    const Twiddles<T, N, false> twr(tw, t);
+    fft_lines<T, N, +1, F>(v, t, lds, lidx, twr);
+#pragma unroll
+    for (int e = 0; e < 8; e++) st_lines<T, F>(&dst[(t + e * P) * kTile], v, e);
+    return;
+  }
+  // unit 0: wz = i (kx uy - ky ux), its ky part from ux first
+  cx<T> w[F][8];
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int j = G::i2j(t + e * P);
+    const T ky = j >= 0 ? kb * (T)G::jmode(j) : (T)0;
+#pragma unroll
+    for (int f = 0; f < F; f++) w[f][e] = mul_i(cscale(v[f][e], -ky));
+  }
+  {
+    // twiddles read afresh for every transform: shared by the block's
+    // transforms, their values would stay in registers across all of them
+    const Twiddles<T, N, false> twr(opaque_ptr(tw), t);
+    fft_lines<T, N, +1, F>(v, t, lds, lidx, twr);
+  }
+#pragma unroll
+  for (int e = 0; e < 8; e++) st_lines<T, F>(&dst[(t + e * P) * kTile], v, e);
+  // uy is loaded only now: hoisted above the ux transform, its loads would
+  // hold a third line of registers through it
+  const cx<T>* src1 = opaque_ptr(in) + (zoff + (size_t)N * G::XT) * G::M * kTile + lane;
+#pragma unroll
+  for (int e = 0; e < 8; e++) {
+    const int j = G::i2j(t + e * P);
+    if (j >= 0) {
+      ld_lines<T, F>(&src1[j * kTile], v, e);
+    } else {
+#pragma unroll
+      for (int f = 0; f < F; f++) v[f][e] = cx<T>{0, 0};
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < F; f++) {
+    const T kx = kb * (T)(xt * kTile + lane + f);
+#pragma unroll
+    for (int e = 0; e < 8; e++) w[f][e] = w[f][e] + mul_i(cscale(v[f][e], kx));
+  }
+  {
+    const Twiddles<T, N, false> twr(opaque_ptr(tw), t);
+    fft_lines<T, N, +1, F>(v, t, lds, lidx, twr);
+  }
+  cx<T>* dst1 = dst + (size_t)N * G::XT * N * kTile;
+#pragma unroll
+  for (int e = 0; e < 8; e++) st_lines<T, F>(&dst1[(t + e * P) * kTile], v, e);
+  {
+    const Twiddles<T, N, false> twr(opaque_ptr(tw), t);
+    fft_lines<T, N, +1, F>(w, t, lds, lidx, twr);
+  }
+  cx<T>* dst3 = dst + (size_t)3 * N * G::XT * N * kTile;
+#pragma unroll
+  for (int e = 0; e < 8; e++) st_lines<T, F>(&dst3[(t + e * P) * kTile], w, e);
 }
 
 template <typename T, int N, bool FULL>

@@ -39,7 +39,8 @@ StageArgs<T> stage_args(Plan* p, void* state, void* tend) {
 template <typename T, int N, bool STRAT>
 struct L3 {
   static constexpr int NC = STRAT ? 4 : 3;    // state components
-  static constexpr int FINV = STRAT ? 7 : 6;  // fields of the inverse passes
+  static constexpr int FINV = STRAT ? 7 : 6;  // fields of the x pass's input
+  static constexpr int FZ = FINV - 1;         // fields of the z pass's output (no wz)
   static constexpr int FFWD = STRAT ? 6 : 3;  // fields of the forward passes
   using G = Geo<N, false>;
   using GF = Geo<N, true>;
@@ -61,9 +62,13 @@ struct L3 {
   }
   static void yinv(Plan* p) {
     p->begin(KID_YINV);
-    hipLaunchKernelGGL((k_y_inv<T, N, false>), dim3(xcd_grid(FINV * N, G::XT * YC::SUB)),
-                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), FINV * N);
-    launched(p, "k_y_inv");
+    // row units per z plane: (ux, uy -> ux, uy, wz) and one per other field
+    constexpr int units = FINV - 2;
+    using YS = YCfg<T, N, true>;
+    hipLaunchKernelGGL((k_y_inv_step<T, N>), dim3(xcd_grid(units * N, G::XT * YS::SUB)),
+                       dim3(YS::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p),
+                       (T)(2.0 * M_PI / p->L), units * N);
+    launched(p, "k_y_inv_step");
     p->end(KID_YINV);
   }
   static void x(Plan* p, bool umax = false) {
@@ -193,14 +198,14 @@ struct L3 {
     o.transfer = launch_transfer<T>;
     o.spectra1d = launch_spectra1d<T>;
     o.structure = launch_structure<T>;
-    // A: z-pass output Wm[FINV], later the x-pass output Wn[FFWD];
+    // A: z-pass output Wm[FZ], later the x-pass output Wn[FFWD];
     // B: y-inverse output Wn[FINV], later the y-forward output Wm[FFWD].
     // Diagnostics also keep one undealiased field plus one physical field
     // (N^3 reals) in A.
     const size_t wm = (size_t)N * G::XT * G::M * kTile, wn = (size_t)N * G::XT * N * kTile;
     const size_t wfull = (size_t)N * GF::XT * N * kTile;
     const size_t phys = ((size_t)N * N * N * sizeof(T) + sizeof(cx<T>) - 1) / sizeof(cx<T>);
-    o.elems_a = std::max({FINV * wm, FFWD * wn, wfull + phys});
+    o.elems_a = std::max({FZ * wm, FFWD * wn, wfull + phys});
     o.elems_b = std::max({FINV * wn, FFWD * wm, wfull});
     o.elems_acc = (size_t)NC * G::XT * G::M * G::M * kTile;
     o.elems_full = wfull;
