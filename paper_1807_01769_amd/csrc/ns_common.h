@@ -629,12 +629,13 @@ __global__ void __launch_bounds__((YCfg<T, N, true>::THREADS), 4)
   for (int e = 0; e < 8; e++) st_lines<T, F>(&dst3[(t + e * P) * kTile], w, e);
 }
 
+// (the forward pass of a stage, !FULL, pairs lines as the inverse one does)
 template <typename T, int N, bool FULL>
-__global__ void __launch_bounds__((YCfg<T, N>::THREADS))
+__global__ void __launch_bounds__((YCfg<T, N, !FULL>::THREADS))
     k_y_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
             const cx<T>* __restrict__ tw, int rows) {
   using G = Geo<N, FULL>;
-  using C = YCfg<T, N>;
+  using C = YCfg<T, N, !FULL>;
   constexpr int F = C::F;
   __shared__ cx<T> lds[C::LINES * N];
   const int b = threadIdx.x % C::LB, t = threadIdx.x / C::LB;

@@ -82,8 +82,9 @@ struct L3 {
   }
   static void yfwd(Plan* p) {
     p->begin(KID_YFWD);
-    hipLaunchKernelGGL((k_y_fwd<T, N, false>), dim3(xcd_grid(FFWD * N, G::XT * YC::SUB)),
-                       dim3(YC::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), FFWD * N);
+    using YS = YCfg<T, N, true>;
+    hipLaunchKernelGGL((k_y_fwd<T, N, false>), dim3(xcd_grid(FFWD * N, G::XT * YS::SUB)),
+                       dim3(YS::THREADS), 0, p->launch, (const cx<T>*)A(p), B(p), TW(p), FFWD * N);
     launched(p, "k_y_fwd");
     p->end(KID_YFWD);
   }
