@@ -243,6 +243,12 @@ template <typename T, int PROP = kPropVisc>
 constexpr int zpass_waves() {
   return sizeof(T) == 4 ? (prop_boussinesq(PROP) ? 2 : 4) : 1;
 }
+// modes per lane whose u_n and accumulator a z pass loads at once (the
+// propagators of rotation and buoyancy, double precision and the longer
+// transforms need their registers for themselves)
+template <typename T, int N, int PROP>
+constexpr int kZChunk = PROP == kPropVisc && sizeof(T) == 4 && N <= 512 ? 2 : 1;
+
 // twiddle table of a z pass: the LDS copy `twl` (filled by the block) in single
 // precision, the global table otherwise
 template <typename T, int N, int THREADS>
@@ -466,116 +472,153 @@ __global__ void __launch_bounds__((ZCfg<T, N, prop_boussinesq(PROP) ? 4 : 3>::TH
   const bool blk_band = a.m2max >= 0 && xt * kTile + sub * C::LB <= a.bw && my <= a.bw &&
                         my >= -a.bw;
   bool bad = false;  // a non-finite value written to the state
+  // u_n and the accumulator of CH modes are loaded before any of them is
+  // combined and stored: the stores could alias later loads as far as the
+  // compiler knows, so loads issued mode by mode would wait out one memory
+  // round trip per mode
+  auto combine = [&](cx<T>* state, cx<T>* accp) {
+    constexpr int CH = kZChunk<T, N, PROP>;
+    const T exy = a.e1[mx] * a.e1[iy], ehxy = a.eh1[mx] * a.eh1[iy];
 #pragma unroll
-  for (int e = 0; e < 8; e++) {
-    const int iz = t + e * P;
-    const int jz = G::i2j(iz);
-    const bool kept = col && jz >= 0;
-    if (!kept) {
+    for (int e0 = 0; e0 < 8; e0 += CH) {
+      cx<T> us[NC][CH], as[NC][CH];
+      T ez[CH], ehz[CH];
 #pragma unroll
-      for (int c = 0; c < NC; c++) v[c][e] = {0, 0};
-      continue;
-    }
-    const int mz = iz <= N / 2 ? iz : iz - N;
-    const T kz = a.kb * (T)mz;
-    const T k2 = kx * kx + ky * ky + kz * kz;
-    cx<T> nl[NC];
-    if constexpr (kStash) v[0][e] = stash[lidx(0, t + e * P)];
-    if (k2 > (T)0) {
-      const T ik2 = recip(k2);
-      const cx<T> kp = cscale(cscale(v[0][e], kx) + cscale(v[1][e], ky) + cscale(v[2][e], kz), ik2);
-      nl[0] = v[0][e] - cscale(kp, kx);
-      nl[1] = v[1][e] - cscale(kp, ky);
-      nl[2] = v[2][e] - cscale(kp, kz);
-      if constexpr (NC == 4) nl[3] = v[3][e];
-    } else {
-#pragma unroll
-      for (int c = 0; c < NC; c++) nl[c] = {0, 0};
-    }
-    bool band = false;
-    int bi = 0;
-    if (blk_band) {
-      band = in_band(a, band_column(a, mx, my), mz);
-      if (band) {
-        bi = band_index<T>(mx, my, mz, a.bw);
-#pragma unroll
-        for (int c = 0; c < 3; c++) nl[c] = nl[c] + cscale(a.vband[c * bn + bi], alpha);
-      }
-    }
-    const size_t so = ((size_t)iz * N + iy) * NH + mx;
-    if constexpr (MODE == kModeTend) {
-#pragma unroll
-      for (int c = 0; c < NC; c++) a.tend[c * cstride + so] = nl[c];
-    } else {
-      const T E = a.e1[mx] * a.e1[iy] * a.e1[iz];
-      const T Eh = a.eh1[mx] * a.eh1[iy] * a.eh1[iz];
-      const size_t ao = (((size_t)xt * G::M + jy) * G::M + jz) * kTile + sub * C::LB + b;
-      if constexpr (PROP != kPropVisc) {
-        // the combination acts on the mode's NC-vectors
-        cx<T> u[NC], acc[NC], nxt[NC];
+      for (int q = 0; q < CH; q++) {
+        const int iz = t + (e0 + q) * P;
+        const int jz = G::i2j(iz);
+        const size_t so = ((size_t)iz * N + iy) * NH + mx;
+        const size_t ao = (((size_t)xt * G::M + jy) * G::M + jz) * kTile + sub * C::LB + b;
+        const bool kept = col && jz >= 0;
 #pragma unroll
         for (int c = 0; c < NC; c++) {
-          u[c] = acc[c] = cx<T>{0, 0};
-          if constexpr (mode_reads_state(MODE)) u[c] = a.state[c * cstride + so];
-          if constexpr (mode_reads_acc(MODE)) acc[c] = a.acc[c * acstride + ao];
+          us[c][q] = as[c][q] = cx<T>{0, 0};
+          if (kept && mode_reads_state(MODE)) us[c][q] = state[c * cstride + so];
+          if (kept && mode_reads_acc(MODE)) as[c][q] = accp[c * acstride + ao];
         }
-        if (k2 == (T)0) {
-          // the mean mode: the unprojected linear terms (rotation of the
-          // horizontal mean, buoyancy oscillation of the vertical mean)
-          MeanProp<T, NC> R;
-          R.set(a.rotf, prop_boussinesq(PROP) ? a.n2 : (T)0, dt);
-          prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
-        } else if constexpr (PROP == kPropRot) {
-          RotProp<T> R;
-          const T ikn = k2 > (T)0 ? (T)1 / sqrt(k2) : (T)0;
-          R.kh[0] = kx * ikn;
-          R.kh[1] = ky * ikn;
-          R.kh[2] = kz * ikn;
-          const T sg = a.rotf * kz * ikn;
-          R.s1 = sin(sg * dt);
-          R.c1 = cos(sg * dt);
-          R.s2 = sin(sg * dt * (T)0.5);
-          R.c2 = cos(sg * dt * (T)0.5);
-          prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
-        } else if constexpr (PROP == kPropStrat) {
-          StratProp<T> R;
-          R.set(kx, ky, kz, a.n2, dt);
-          prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+        ez[q] = ehz[q] = (T)0;
+        if (kept && MODE != kModeTend) {
+          ez[q] = a.e1[iz];
+          ehz[q] = a.eh1[iz];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < CH; q++) {
+        const int e = e0 + q;
+        const int iz = t + e * P;
+        const int jz = G::i2j(iz);
+        const bool kept = col && jz >= 0;
+        if (!kept) {
+#pragma unroll
+          for (int c = 0; c < NC; c++) v[c][e] = {0, 0};
+          continue;
+        }
+        const int mz = iz <= N / 2 ? iz : iz - N;
+        const T kz = a.kb * (T)mz;
+        const T k2 = kx * kx + ky * ky + kz * kz;
+        cx<T> nl[NC];
+        if constexpr (kStash) v[0][e] = stash[lidx(0, t + e * P)];
+        if (k2 > (T)0) {
+          const T ik2 = recip(k2);
+          const cx<T> kp =
+              cscale(cscale(v[0][e], kx) + cscale(v[1][e], ky) + cscale(v[2][e], kz), ik2);
+          nl[0] = v[0][e] - cscale(kp, kx);
+          nl[1] = v[1][e] - cscale(kp, ky);
+          nl[2] = v[2][e] - cscale(kp, kz);
+          if constexpr (NC == 4) nl[3] = v[3][e];
         } else {
-          StratRotProp<T> R;
-          R.set(kx, ky, kz, a.n2, a.rotf, dt);
-          prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
-        }
 #pragma unroll
-        for (int c = 0; c < NC; c++) {
-          if constexpr (mode_writes_state(MODE)) {
-            a.state[c * cstride + so] = nxt[c];
-            bad |= nonfinite(nxt[c]);
+          for (int c = 0; c < NC; c++) nl[c] = {0, 0};
+        }
+        bool band = false;
+        int bi = 0;
+        if (blk_band) {
+          band = in_band(a, band_column(a, mx, my), mz);
+          if (band) {
+            bi = band_index<T>(mx, my, mz, a.bw);
+#pragma unroll
+            for (int c = 0; c < 3; c++) nl[c] = nl[c] + cscale(a.vband[c * bn + bi], alpha);
           }
-          if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc[c];
-          v[c][e] = nxt[c];
         }
-      } else {
+        const size_t so = ((size_t)iz * N + iy) * NH + mx;
+        if constexpr (MODE == kModeTend) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-          cx<T> acc = {0, 0};
-          cx<T> u = {0, 0};
-          if constexpr (mode_reads_state(MODE)) u = a.state[c * cstride + so];
-          if constexpr (mode_reads_acc(MODE)) acc = a.acc[c * acstride + ao];
-          const cx<T> nxt = rk4_combine<MODE>(u, acc, nl[c], E, Eh, dt);
-          if constexpr (mode_writes_state(MODE)) {
-            a.state[c * cstride + so] = nxt;
-            bad |= nonfinite(nxt);
+          for (int c = 0; c < NC; c++) a.tend[c * cstride + so] = nl[c];
+        } else {
+          const T E = exy * ez[q];
+          const T Eh = ehxy * ehz[q];
+          const size_t ao = (((size_t)xt * G::M + jy) * G::M + jz) * kTile + sub * C::LB + b;
+          if constexpr (PROP != kPropVisc) {
+            // the combination acts on the mode's NC-vectors
+            cx<T> u[NC], acc[NC], nxt[NC];
+#pragma unroll
+            for (int c = 0; c < NC; c++) {
+              u[c] = us[c][q];
+              acc[c] = as[c][q];
+            }
+            if (k2 == (T)0) {
+              // the mean mode: the unprojected linear terms (rotation of the
+              // horizontal mean, buoyancy oscillation of the vertical mean)
+              MeanProp<T, NC> R;
+              R.set(a.rotf, prop_boussinesq(PROP) ? a.n2 : (T)0, dt);
+              prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+            } else if constexpr (PROP == kPropRot) {
+              RotProp<T> R;
+              const T ikn = k2 > (T)0 ? (T)1 / sqrt(k2) : (T)0;
+              R.kh[0] = kx * ikn;
+              R.kh[1] = ky * ikn;
+              R.kh[2] = kz * ikn;
+              const T sg = a.rotf * kz * ikn;
+              R.s1 = sin(sg * dt);
+              R.c1 = cos(sg * dt);
+              R.s2 = sin(sg * dt * (T)0.5);
+              R.c2 = cos(sg * dt * (T)0.5);
+              prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+            } else if constexpr (PROP == kPropStrat) {
+              StratProp<T> R;
+              R.set(kx, ky, kz, a.n2, dt);
+              prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+            } else {
+              StratRotProp<T> R;
+              R.set(kx, ky, kz, a.n2, a.rotf, dt);
+              prop_combine<MODE>(u, acc, nl, E, Eh, dt, R, nxt);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; c++) {
+              if constexpr (mode_writes_state(MODE)) {
+                state[c * cstride + so] = nxt[c];
+                bad |= nonfinite(nxt[c]);
+              }
+              if constexpr (mode_writes_acc(MODE)) accp[c * acstride + ao] = acc[c];
+              v[c][e] = nxt[c];
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+              cx<T> acc = as[c][q];
+              const cx<T> nxt = rk4_combine<MODE>(us[c][q], acc, nl[c], E, Eh, dt);
+              if constexpr (mode_writes_state(MODE)) {
+                state[c * cstride + so] = nxt;
+                bad |= nonfinite(nxt);
+              }
+              if constexpr (mode_writes_acc(MODE)) accp[c * acstride + ao] = acc;
+              v[c][e] = nxt;
+            }
           }
-          if constexpr (mode_writes_acc(MODE)) a.acc[c * acstride + ao] = acc;
-          v[c][e] = nxt;
-        }
-      }
-      if (band && do_p1) {
+          if (band && do_p1) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) a.vband[c * bn + bi] = v[c][e];
+            for (int c = 0; c < 3; c++) a.vband[c * bn + bi] = v[c][e];
+          }
+        }
       }
     }
+  };
+  if constexpr (kZChunk<T, N, PROP> > 1) {
+    // the state and accumulator through pointers the compiler may take as
+    // unaliased: the batched loads need fewer registers that way
+    [&](cx<T>* __restrict__ st, cx<T>* __restrict__ ac) { combine(st, ac); }(a.state, a.acc);
+  } else {
+    combine(a.state, a.acc);
   }
   if constexpr (mode_writes_state(MODE)) {
     if (a.nonfin) flag_wave(a.nonfin, bad);
