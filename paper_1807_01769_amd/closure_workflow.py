@@ -58,7 +58,8 @@ class Config:
     lr_final: float = 1e-4
     clip: float = 6.0        # clip of the standardised network output
     net_seed: int = 7
-    filter: str = "sharp"    # "sharp" cube cutoff or "box" (top-hat, then the cutoff)
+    filter: str = "sharp"    # "sharp" cube cutoff or "box" (top-hat, then the cutoff);
+                             # several, comma-separated ("sharp,box"), share one DNS run
 
 
 def _steps(t: float, dt: float) -> int:
@@ -111,18 +112,20 @@ def stationarity(hist: list, window: float) -> dict:
             "E": float(eb), "eps": float(db)}
 
 
-def collect(cfg: Config, plan: fs.Plan, closure: fs.Closure, u: torch.Tensor):
-    """cfg.nsnap snapshots every cfg.every: lists of A [9][P] and tau [6][P]."""
-    As, taus = [], []
+def collect(cfg: Config, plan: fs.Plan, closures: list, u: torch.Tensor):
+    """cfg.nsnap snapshots every cfg.every, filtered by every closure: per
+    closure, lists of A [9][P] and tau [6][P]."""
+    out = [([], []) for _ in closures]
     k = _steps(cfg.every, cfg.dt)
     for s in range(cfg.nsnap):
         plan.step(u, k)
-        _, A, tau = closure.samples(u)
-        As.append(A)
-        taus.append(tau)
+        for closure, (As, taus) in zip(closures, out):
+            _, A, tau = closure.samples(u)
+            As.append(A)
+            taus.append(tau)
         if s % 4 == 3 or s == cfg.nsnap - 1:
             _log(f"collected {s + 1}/{cfg.nsnap} snapshots")
-    return As, taus
+    return out
 
 
 def standardise(closure: fs.Closure, As, taus):
@@ -179,95 +182,121 @@ def _spectrum(plan: fs.Plan, u: torch.Tensor, kc: int) -> np.ndarray:
     return spec[: kc + 1].cpu().numpy()
 
 
-def evaluate(cfg: Config, fine: fs.Plan, coarse: fs.Plan, closure: fs.Closure, u: torch.Tensor,
-             net: fs.Mlp, a_scale: float, tau_scale):
-    """DNS, LES with the network and no-model LES over cfg.eval_time from the
-    filtered state of `u` (advanced in place)."""
+def evaluate(cfg: Config, fine: fs.Plan, coarse: fs.Plan, models: list, u: torch.Tensor):
+    """DNS, and per (closure, net, a_scale, tau_scale) in `models` the LES with
+    the network and the no-model LES, over cfg.eval_time from the filtered
+    state of `u` (advanced in place).  Returns one result per model."""
     kc = (cfg.nc - 1) // 3
     les_dt = cfg.dt * cfg.les_dt_factor
     n_dns = _steps(cfg.eval_every, cfg.dt)
     n_les = _steps(cfg.eval_every, les_dt)
     nwin = int(round(cfg.eval_time / cfg.eval_every))
-    uc0, _, _ = closure.samples(u)
-    runs = {}
-    for name, model in (("model", net), ("no_model", None)):
-        runs[name] = {"state": uc0.clone(), "les": fs.Les(coarse, model, a_scale, tau_scale, cfg.clip),
-                      "spectra": [], "energy": [], "seconds": 0.0, "finite": True}
-    dns_spectra, dns_energy, dns_seconds = [], [], 0.0
+    cases = []
+    for closure, net, a_scale, tau_scale in models:
+        uc0, _, _ = closure.samples(u)
+        runs = {}
+        for name, model in (("model", net), ("no_model", None)):
+            runs[name] = {"state": uc0.clone(),
+                          "les": fs.Les(coarse, model, a_scale, tau_scale, cfg.clip),
+                          "spectra": [], "energy": [], "seconds": 0.0, "finite": True}
+        cases.append({"closure": closure, "runs": runs, "dns_spectra": [], "dns_energy": []})
+    dns_seconds = 0.0
     for w in range(nwin):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fine.step(u, n_dns)
         torch.cuda.synchronize()
         dns_seconds += time.perf_counter() - t0
-        uc, _, _ = closure.samples(u)
-        s = _spectrum(coarse, uc, kc)
-        dns_spectra.append(s)
-        dns_energy.append(float(s[1:].sum()))
-        for name, r in runs.items():
-            if not r["finite"]:
-                continue
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r["les"].step(r["state"], n_les)
-            torch.cuda.synchronize()
-            r["seconds"] += time.perf_counter() - t0
-            sp = _spectrum(coarse, r["state"], kc)
-            if not np.all(np.isfinite(sp)):
-                r["finite"] = False
-                _log(f"LES {name} became non-finite at window {w + 1}")
-                continue
-            r["spectra"].append(sp)
-            r["energy"].append(float(sp[1:].sum()))
-        _log(f"eval t={(w + 1) * cfg.eval_every:.2f}: E_fDNS={dns_energy[-1]:.5f} " +
-             " ".join(f"E_{k}={r['energy'][-1]:.5f}" for k, r in runs.items() if r["energy"]))
-    ref = np.mean(dns_spectra, axis=0)
-    out = {"k": list(range(1, kc + 1)), "E_fdns": ref[1:].tolist(),
-           "dns_seconds_per_time": dns_seconds / cfg.eval_time}
-    for name, r in runs.items():
-        if r["finite"] and len(r["spectra"]) == nwin:
-            m = np.mean(r["spectra"], axis=0)
-            ratio = m[1:] / ref[1:]
-            out[name] = {"E": m[1:].tolist(), "max_rel_err": float(np.abs(ratio - 1).max()),
-                         "ratio": ratio.tolist(),
-                         "seconds_per_time": r["seconds"] / cfg.eval_time,
-                         "energy_history": r["energy"]}
-        else:
-            out[name] = {"max_rel_err": float("inf"), "finite": False}
-        r["les"].close()
-    out["fdns_energy_history"] = dns_energy
-    if "model" in out and "seconds_per_time" in out.get("model", {}):
-        out["speedup_model_vs_dns"] = out["dns_seconds_per_time"] / out["model"]["seconds_per_time"]
-    return out
+        for case in cases:
+            uc, _, _ = case["closure"].samples(u)
+            s = _spectrum(coarse, uc, kc)
+            case["dns_spectra"].append(s)
+            case["dns_energy"].append(float(s[1:].sum()))
+            for name, r in case["runs"].items():
+                if not r["finite"]:
+                    continue
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r["les"].step(r["state"], n_les)
+                torch.cuda.synchronize()
+                r["seconds"] += time.perf_counter() - t0
+                sp = _spectrum(coarse, r["state"], kc)
+                if not np.all(np.isfinite(sp)):
+                    r["finite"] = False
+                    _log(f"LES {name} ({case['closure'].filter}) became non-finite at window {w + 1}")
+                    continue
+                r["spectra"].append(sp)
+                r["energy"].append(float(sp[1:].sum()))
+            _log(f"eval t={(w + 1) * cfg.eval_every:.2f} {case['closure'].filter}: "
+                 f"E_fDNS={case['dns_energy'][-1]:.5f} " +
+                 " ".join(f"E_{k}={r['energy'][-1]:.5f}" for k, r in case["runs"].items()
+                          if r["energy"]))
+    results = []
+    for case in cases:
+        ref = np.mean(case["dns_spectra"], axis=0)
+        out = {"filter": case["closure"].filter, "k": list(range(1, kc + 1)),
+               "E_fdns": ref[1:].tolist(), "dns_seconds_per_time": dns_seconds / cfg.eval_time}
+        for name, r in case["runs"].items():
+            if r["finite"] and len(r["spectra"]) == nwin:
+                m = np.mean(r["spectra"], axis=0)
+                ratio = m[1:] / ref[1:]
+                out[name] = {"E": m[1:].tolist(), "max_rel_err": float(np.abs(ratio - 1).max()),
+                             "ratio": ratio.tolist(),
+                             "seconds_per_time": r["seconds"] / cfg.eval_time,
+                             "ms_per_step": 1e3 * r["seconds"] / (nwin * n_les),
+                             "energy_history": r["energy"]}
+            else:
+                out[name] = {"max_rel_err": float("inf"), "finite": False}
+            r["les"].close()
+        out["fdns_energy_history"] = case["dns_energy"]
+        if "seconds_per_time" in out.get("model", {}):
+            out["speedup_model_vs_dns"] = (out["dns_seconds_per_time"] /
+                                           out["model"]["seconds_per_time"])
+        results.append(out)
+    return results
 
 
 def run(cfg: Config) -> dict:
+    """The workflow for every filter in cfg.filter from one DNS run.  With one
+    filter, result["training"] and result["evaluation"] are its outcome; with
+    several, result["filters"][name] holds each filter's."""
     if not torch.cuda.is_available():
         raise RuntimeError("the closure workflow needs a HIP device")
+    filters = [f.strip() for f in cfg.filter.split(",") if f.strip()]
     fine = fs.Plan(cfg.nf, nu=cfg.nu, dt=cfg.dt, forcing_power=cfg.power,
                    forcing_kmin=cfg.kf_min, forcing_kmax=cfg.kf_max)
     coarse = fs.Plan(cfg.nc, nu=cfg.nu, dt=cfg.dt * cfg.les_dt_factor, forcing_power=cfg.power,
                      forcing_kmin=cfg.kf_min, forcing_kmax=cfg.kf_max)
-    closure = fs.Closure(fine, coarse, filter=cfg.filter)
+    closures = [fs.Closure(fine, coarse, filter=f) for f in filters]
     u = torch.from_numpy(inputs.random_solenoidal_3d(cfg.nf, seed=cfg.seed, energy=cfg.energy0,
                                                      dtype=np.complex64)).cuda()
     result = {"config": asdict(cfg)}
     hist = spin_up(cfg, fine, u)
     result["spinup"] = {"history": hist, "stationarity": stationarity(hist, min(4.0, cfg.spinup))}
     _log(f"stationarity over the last window: {result['spinup']['stationarity']}")
-    As, taus = collect(cfg, fine, closure, u)
-    a_scale, tau_scale = standardise(closure, As, taus)
-    result["scales"] = {"a_scale": a_scale, "tau_scale": tau_scale}
-    net, tr = train(cfg, closure, As, taus, a_scale, tau_scale)
-    result["training"] = tr
-    del As, taus
+    samples = collect(cfg, fine, closures, u)
+    models, per = [], {}
+    for f, closure, (As, taus) in zip(filters, closures, samples):
+        a_scale, tau_scale = standardise(closure, As, taus)
+        _log(f"filter {f}: training")
+        net, tr = train(cfg, closure, As, taus, a_scale, tau_scale)
+        per[f] = {"scales": {"a_scale": a_scale, "tau_scale": tau_scale}, "training": tr}
+        models.append((closure, net, a_scale, tau_scale))
+    del samples
     fine.step(u, _steps(cfg.gap, cfg.dt))
-    result["evaluation"] = evaluate(cfg, fine, coarse, closure, u, net, a_scale, tau_scale)
-    ev = result["evaluation"]
-    _log("spectral error up to the cutoff: model "
-         f"{ev['model'].get('max_rel_err')}, no model {ev['no_model'].get('max_rel_err')}; "
-         f"speedup vs DNS {ev.get('speedup_model_vs_dns')}")
-    for o in (net, closure, coarse, fine):
+    for f, ev in zip(filters, evaluate(cfg, fine, coarse, models, u)):
+        per[f]["evaluation"] = ev
+        _log(f"filter {f}: spectral error up to the cutoff: model "
+             f"{ev['model'].get('max_rel_err')}, no model {ev['no_model'].get('max_rel_err')}; "
+             f"LES {ev['model'].get('ms_per_step')} ms/step; "
+             f"speedup vs DNS {ev.get('speedup_model_vs_dns')}")
+    if len(filters) == 1:
+        result.update(per[filters[0]])
+    else:
+        result["filters"] = per
+    for _, net, _, _ in models:
+        net.close()
+    for o in (*closures, coarse, fine):
         o.close()
     return result
 
