@@ -227,7 +227,37 @@ def time_ensemble(fs, torch, I, np, steps):
            "finite": bool(torch.isfinite(torch.view_as_real(st)).all()),
            "schedule": ens.schedule()}
     ens.close()
+    # the same steps launched directly, each class's chain on its own stream
+    ens = fs.Ensemble(sizes, nu=ENS_NU, dt=ENS_DT, graphs=False)
+    st2 = ens.pack(fields)
+    ens.step(st2, 2)
+    st2 = ens.pack(fields)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(st2, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res["direct_streams"] = {"gridpoint_steps_per_s": pts * steps / (t1 - t0),
+                             "ms_total": (t1 - t0) * 1e3,
+                             "same_result": bool(torch.equal(st, st2))}
+    ens.close()
+    res["counters"] = read_ensemble_counters()
     return res, sizes, fields
+
+
+ENSEMBLE_COUNTERS = os.path.join(ROOT, "profiles", "ensemble_2d_counters.md")
+
+
+def read_ensemble_counters():
+    """L2 and memory-side traffic of the ensemble step from its counter
+    summary (the line that starts with "DATA "), or None."""
+    if not os.path.exists(ENSEMBLE_COUNTERS):
+        return None
+    with open(ENSEMBLE_COUNTERS) as fh:
+        for line in fh:
+            if line.startswith("DATA "):
+                return json.loads(line[5:])
+    return None
 
 
 def bench_ensemble(args) -> int:
@@ -236,6 +266,18 @@ def bench_ensemble(args) -> int:
     from paper_1807_01769_amd import fs, inputs as I
 
     nu, dt, steps = ENS_NU, ENS_DT, args.ens_steps
+    if args.ens_counter_pass:
+        # only the step's kernels: default schedules (no tuning launches),
+        # direct launches, for counter collection
+        sizes = I.ensemble_sizes()
+        fields = [I.ensemble_vorticity(r, n).astype(np.complex64) for r, n in enumerate(sizes)]
+        ens = fs.Ensemble(sizes, nu=nu, dt=dt, autotune=False, graphs=False)
+        st = ens.pack(fields)
+        ens.step(st, steps)
+        torch.cuda.synchronize()
+        ens.close()
+        log(f"ensemble counter pass: {steps} steps")
+        return 0
     res, sizes, fields = time_ensemble(fs, torch, I, np, steps)
     rate, pts, finite = res["gridpoint_steps_per_s"], res["gridpoints"], res["finite"]
     cpu = None
@@ -256,7 +298,9 @@ def bench_ensemble(args) -> int:
            "config": {"workload": "2D NS ensemble: 128 runs at 128^2, 96 at 256^2, 32 at 512^2, "
                                   "FP32, nu=1e-4, dt=5e-4, E(k)~k exp(-(k/6)^2), seeds 1000+r",
                       "gridpoints": pts},
-           "alg_GBps": res["alg_GBps"], "schedule": res["schedule"], "cpu_baseline": cpu}
+           "alg_GBps": res["alg_GBps"], "schedule": res["schedule"],
+           "direct_streams": res["direct_streams"], "counters": res["counters"],
+           "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -331,6 +375,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["3d", "ensemble"], default="3d")
     ap.add_argument("--ens-steps", type=int, default=200)
+    ap.add_argument("--ens-counter-pass", action="store_true",
+                    help="ensemble workload: run --ens-steps steps of the default schedules "
+                         "with direct launches and print nothing (for counter collection)")
     ap.add_argument("--les-n", type=int, default=64,
                     help="LES grid of the closure speedup measurement (0 = skip)")
     ap.add_argument("--les-steps", type=int, default=200)

@@ -507,8 +507,19 @@ fs_status fs_ensemble_step_rk4(fs_ensemble* ens, void* packed_state, int nsteps)
   }
   if (nsteps == 0) return FS_OK;
   if (e->flags & FS_NO_GRAPH) {
-    for (auto& c : e->cls) fs::class_steps(e, c, packed_state, nsteps, e->stream);
-    return fs::ok(e, hipGetLastError(), "launch") ? FS_OK : FS_E_DEVICE;
+    // the classes' chains on their own streams, forked from and joined back
+    // into the caller's stream
+    bool good = fs::ok(e, hipEventRecord(e->fork, e->stream), "fork");
+    for (size_t i = 0; good && i < e->cls.size(); i++) {
+      auto& c = e->cls[i];
+      good = fs::ok(e, hipStreamWaitEvent(c.stream, e->fork, 0), "fork wait");
+      if (!good) break;
+      fs::class_steps(e, c, packed_state, nsteps, c.stream);
+      good = fs::ok(e, hipGetLastError(), "launch") &&
+             fs::ok(e, hipEventRecord(e->joins[i], c.stream), "join") &&
+             fs::ok(e, hipStreamWaitEvent(e->stream, e->joins[i], 0), "join wait");
+    }
+    return good ? FS_OK : FS_E_DEVICE;
   }
   if (e->graph && (e->gstate != packed_state || e->gsteps != nsteps)) {
     hipGraphExecDestroy(e->graph);
