@@ -350,8 +350,11 @@ fs_status fs_ensemble_offsets(const fs_ensemble *ens, int64_t *offsets);
 /*
  * Advance every run of the packed state (device memory) by nsteps Lawson
  * IF-RK4 steps, exactly as fs_step_rk4 would advance each run alone.  All
- * steps of all classes are captured as parallel branches of one hipGraph
- * and launched once (reused while the pointer and nsteps are unchanged).
+ * steps of one size class are captured as one hipGraph (reused while the
+ * pointer and nsteps are unchanged); the classes' graphs are launched once
+ * each on streams of their own, forked from and joined back into the
+ * ensemble's stream, so that the classes run concurrently.  With FS_NO_GRAPH
+ * the same chains are launched kernel by kernel on those streams.
  */
 fs_status fs_ensemble_step_rk4(fs_ensemble *ens, void *packed_state, int nsteps);
 /* Chosen schedule of class cls (classes in increasing size): its size, run
