@@ -111,19 +111,72 @@ __global__ void __launch_bounds__(RP * N / 8)
   using R = RowPairs<N>;
   constexpr int P = G::P;
   constexpr int NL = 2 + NF;  // inverse lines: (u, v) of each row, (w[, b]) of both rows
-  __shared__ cx<T> lds[RP * NL * R::NPAD];
+  // plain flow transforms one line at a time (one line of LDS per row pair,
+  // fewer registers, more waves per CU); with buoyancy the lines go together
+  constexpr int NLDS = NF == 1 ? 1 : NL;
+  __shared__ cx<T> lds[RP * NLDS * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
   const Twiddles<T, N> twr(tw, t);
   const int run = blockIdx.x / bt.bpr, part = blockIdx.x % bt.bpr;
   in += run * bt.in_stride;
   out += run * bt.out_stride;
   const int y0 = 2 * (part * RP + rp);
-  cx<T>* my_lds = lds + rp * NL * R::NPAD;
+  cx<T>* my_lds = lds + rp * NLDS * R::NPAD;
   auto lidx = [=](int f, int pos) { return f * R::NPAD + R::pad(pos); };
   const size_t fstride = (size_t)G::XT * N * kTile;
   auto at = [=](int f, int y, int m) -> cx<T> {
     return in[f * fstride + ((size_t)(m >> 4) * N + y) * kTile + (m & 15)];
   };
+  if constexpr (NF == 1) {
+    // (w(y0) + i w(y1)) first, then per row (u + i v), its products (u w,
+    // v w) forward-transformed as one line and untangled
+    cx<T> v[1][8];
+#pragma unroll
+    for (int e = 0; e < 8; e++)
+      v[0][e] = c2r_pair_at<T, N, false>(t + e * P, [&](int m) { return at(2, y0, m); },
+                                         [&](int m) { return at(2, y0 + 1, m); });
+    fft_lines<T, N, +1, 1>(v, t, my_lds, lidx, twr);
+    T ws[2][8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      ws[0][e] = v[0][e].re * scale;
+      ws[1][e] = v[0][e].im * scale;
+    }
+    double um = 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      // this row's loads stay after the previous transform (through an
+      // opaque copy of the read-only input), not hoisted into its registers
+      const cx<T>* inr = opaque_ptr(in);
+      auto atr = [=](int f, int m) -> cx<T> {
+        return inr[f * fstride + ((size_t)(m >> 4) * N + y0 + r) * kTile + (m & 15)];
+      };
+#pragma unroll
+      for (int e = 0; e < 8; e++)
+        v[0][e] = c2r_pair_at<T, N, false>(t + e * P, [&](int m) { return atr(0, m); },
+                                           [&](int m) { return atr(1, m); });
+      fft_lines<T, N, +1, 1>(v, t, my_lds, lidx, twr);
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        if (umax) um = fmax(um, (double)fmax(fabs(v[0][e].re), fabs(v[0][e].im)));
+        v[0][e] = {v[0][e].re * ws[r][e], v[0][e].im * ws[r][e]};
+      }
+      fft_lines<T, N, -1, 1>(v, t, my_lds, lidx, twr);
+#pragma unroll
+      for (int e = 0; e < 8; e++) my_lds[lidx(0, t + e * P)] = v[0][e];
+      __syncthreads();
+      for (int m = t; m < G::XT * kTile; m += P) {
+        const size_t o = ((size_t)(m >> 4) * N + (y0 + r)) * kTile + (m & 15);
+        cx<T> A = {0, 0}, B = {0, 0};
+        if (m < G::H) r2c_untangle(my_lds[lidx(0, m)], my_lds[lidx(0, (N - m) & (N - 1))], A, B);
+        out[o] = A;
+        out[fstride + o] = B;
+      }
+      __syncthreads();
+    }
+    if (umax) umax_wave(umax, um);
+    return;
+  }
   cx<T> v[NL][8];
 #pragma unroll
   for (int e = 0; e < 8; e++) {
