@@ -20,14 +20,17 @@
 // component: the inverse passes move six and seven fields (u, w, b), the x pass also
 // forms the buoyancy flux u b, and the forward passes move six (u x w, u b).
 #pragma once
+#include <type_traits>
+
 #include "ns_common.h"
 
 namespace fs {
 
 // ---------------------------------------------------------------------------
 // X pass: for each row pair (y0, y0+1) at height z, inverse-transform
-// (ux,uy) (uz,wz) (wx,wy) of each row, form p = (u x w) * scale, forward
-// transform (px + i py) of each row and (pz(y0) + i pz(y1)), store kept kx.
+// (ux,uy) and (wx,wy) of each row and (uz(y0),uz(y1)), (wz(y0),wz(y1)),
+// form p = (u x w) * scale, forward transform (px + i py) of each row and
+// (pz(y0) + i pz(y1)), store kept kx.
 // One transform line is in flight at a time and the cross product is built
 // as its factors arrive (u kept, partial products accumulated).  The kept
 // coefficients of one row (six fields) are staged in LDS with 16-byte loads
@@ -47,7 +50,8 @@ template <typename T, int N, bool STRAT>
 using XRows = RowPairs<N, (STRAT && sizeof(T) == 8) ? 32 : 64>;
 
 template <typename T, int N, bool STRAT = false>
-__global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
+__global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
+                                  (sizeof(T) == 4 && !STRAT ? 3 : 1))
     k3_x(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
          T scale, unsigned long long* __restrict__ umax) {
   using G = Geo<N, false>;
@@ -74,9 +78,13 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
 
   // staging of rows y0 + r0 .. y0 + r0 + NRS - 1: for each (field, tile) the
   // rows are NRS*16 contiguous coefficients; 16-byte loads, all in flight.
-  auto stage_rows = [&](int r0) {
+  // With SKIP, fields 2 and 3 (uz, wz) are left out: the second row's are
+  // read for the cross lines before its staging.
+  auto stage_rows = [&](int r0, auto skip) {
+    constexpr bool SKIP = decltype(skip)::value;
     constexpr int PER = 16 / (int)sizeof(cx<T>);          // coefficients per load
-    constexpr int LOADS = FIN * G::XT * NRS * kTile / PER;  // per stage
+    constexpr int NF = SKIP ? FIN - 2 : FIN;              // fields staged
+    constexpr int LOADS = NF * G::XT * NRS * kTile / PER;  // per stage
     const uint4* src4 = reinterpret_cast<const uint4*>(in);
     uint4* st4 = reinterpret_cast<uint4*>(st);
 #pragma unroll
@@ -84,16 +92,14 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
       const int i = i0 + t;
       if (i < LOADS) {
         const int c = i / (NRS * kTile / PER), l = i % (NRS * kTile / PER);
-        const int f = c / G::XT, xt = c % G::XT;
+        const int fs = c / G::XT, xt = c % G::XT;
+        const int f = SKIP && fs >= 2 ? fs + 2 : fs;
         const int r = l / (kTile / PER), lo = l % (kTile / PER);
         const size_t g = ((((size_t)f * N + z) * G::XT + xt) * N + y0 + r0) * kTile;
         st4[((f * NRS + r) * G::XT + xt) * (kTile / PER) + lo] = src4[g / PER + l];
       }
     }
   };
-  stage_rows(0);
-  __syncthreads();
-
   // Register e holds position k = t + e*P of the complex line a + i b; it
   // needs coefficient m = k (k <= K) or the conjugate mirror m = N - k
   // (k >= N - K) of both half spectra.
@@ -105,13 +111,39 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
     kind[e] = k <= G::K ? (k == 0 ? 2 : 1) : (k >= N - G::K ? -1 : 0);
     off[e] = m;
   }
-  // inverse transform of the complex line A + i B (half spectra ba, bb)
-  auto inverse_line = [&](const cx<T>* ba, const cx<T>* bb, cx<T> (&v)[1][8]) {
+  // the second row's field f at every register position, from HBM (off[e]
+  // = 0 where nothing is kept: a valid element, loaded unconditionally so
+  // that all loads are in flight together)
+  auto row1_field = [&](int f, cx<T> (&bv)[8]) {
+    const cx<T>* src = in + (((size_t)f * N + z) * G::XT * N + (y0 + 1)) * kTile;
+#pragma unroll
+    for (int e = 0; e < 8; e++) bv[e] = src[(size_t)(off[e] >> 4) * N * kTile + (off[e] & 15)];
+  };
+  // the second row's wz and uz (see the lines below) are loaded with the
+  // staging of the first row and have arrived by its barrier
+  cx<T> bw[8], bu[8];
+  if constexpr (NRS == 1) {
+    row1_field(3, bw);
+    row1_field(2, bu);
+  }
+  stage_rows(0, std::false_type{});
+  if constexpr (NRS == 1) {
+    // held here, before the barrier: not sunk below it into the transforms
+#pragma unroll
+    for (int e = 0; e < 8; e++)
+      asm volatile("" : "+v"(bw[e].re), "+v"(bw[e].im), "+v"(bu[e].re), "+v"(bu[e].im));
+  }
+  __syncthreads();
+
+  // inverse transform of the complex line A + i B (half spectrum A staged in
+  // ba)
+  // (bv: B at each register position, loaded beforehand)
+  auto inverse_line_v = [&](const cx<T>* ba, const cx<T> (&bv)[8], cx<T> (&v)[1][8]) {
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       cx<T> res = {0, 0};
       if (kind[e] != 0) {
-        cx<T> A = ba[off[e]], B = bb[off[e]];
+        cx<T> A = ba[off[e]], B = bv[e];
         if (kind[e] == 2) A.im = B.im = 0;
         res = kind[e] > 0 ? cx<T>{A.re - B.im, A.im + B.re} : cx<T>{A.re + B.im, B.re - A.im};
       }
@@ -119,10 +151,11 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
     }
     fft_lines<T, N, +1, 1>(v, t, line, lidx, twr);
   };
-  // fields (2g, 2g+1) of row r
-  auto inverse_pair = [&](int g, int r, cx<T> (&v)[1][8]) {
-    const cx<T>* ba = st + ((2 * g) * NRS + (NRS == 2 ? r : 0)) * G::XT * kTile;
-    inverse_line(ba, ba + NRS * G::XT * kTile, v);
+  auto inverse_line = [&](const cx<T>* ba, const cx<T>* bb, cx<T> (&v)[1][8]) {
+    cx<T> bv[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) bv[e] = bb[off[e]];
+    inverse_line_v(ba, bv, v);
   };
 
   cx<T>* outz = out + (size_t)z * G::XT * N * kTile;
@@ -143,47 +176,79 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
     __syncthreads();
   };
 
-  // Row by row: three inverse transforms build p = (u x w) * scale as the
-  // factors arrive; (px + i py) is transformed at once, pz of the first row
-  // waits to be paired with pz of the second.
-  T pz0[8];
+  // Lines: (ux + i uy) and (wx + i wy) of each row, and across the pair
+  // (uz(y0) + i uz(y1)), (wz(y0) + i wz(y1)): like with like.  A velocity and
+  // a vorticity component in one line would leave the vorticity's rounding,
+  // about |k| times larger, on the velocity (the single-precision error of
+  // the tendency then grows with N).  Row by row the cross product is built
+  // as its factors arrive; (px + i py) of each row is transformed at once,
+  // pz of the first row waits to be paired with pz of the second.  The two
+  // cross lines come first; the second row's uz, wz are read from HBM
+  // directly (16 lanes per 128-byte row), in flight with the staging loads
+  // of the first row.
+  auto row_ptr = [&](int f, int r) -> const cx<T>* {
+    return st + (f * NRS + (NRS == 2 ? r : 0)) * G::XT * kTile;
+  };
+  T pz0[8], uz1[8], wz1[8], wz0[8];
   double um = 0.0;  // largest |u_c| seen (only when umax is requested)
   // buoyancy of both rows (b(y0) + i b(y1)) and the first row's fz
   T bq[2][8], fz0[8];
   if constexpr (STRAT) {
     cx<T> v[1][8];
-    const cx<T>* ba = st + 6 * 2 * G::XT * kTile;
-    inverse_line(ba, ba + G::XT * kTile, v);
+    inverse_line(row_ptr(6, 0), row_ptr(6, 1), v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       bq[0][e] = v[0][e].re * scale;
       bq[1][e] = v[0][e].im * scale;
     }
   }
+  T uz0[8];
+  {
+    cx<T> v[1][8];
+    if constexpr (NRS == 2) {
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        bw[e] = row_ptr(3, 1)[off[e]];
+        bu[e] = row_ptr(2, 1)[off[e]];
+      }
+    }
+    inverse_line_v(row_ptr(3, 0), bw, v);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      wz0[e] = v[0][e].re;
+      wz1[e] = v[0][e].im;
+    }
+    inverse_line_v(row_ptr(2, 0), bu, v);
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      uz0[e] = v[0][e].re;
+      uz1[e] = v[0][e].im;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 2; r++) {
     if (NRS == 1 && r == 1) {
       // every read of row 0 ended before the last barrier of its stores
-      stage_rows(1);
+      stage_rows(1, std::true_type{});
       __syncthreads();
     }
     T ux[8], uy[8], uz[8], qx[8], qy[8];
     cx<T> v[1][8];
-    inverse_pair(0, r, v);
+    inverse_line(row_ptr(0, r), row_ptr(1, r), v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       ux[e] = v[0][e].re;
       uy[e] = v[0][e].im;
-    }
-    inverse_pair(1, r, v);
-#pragma unroll
-    for (int e = 0; e < 8; e++) {
-      uz[e] = v[0][e].re;
-      if (umax)
-        um = fmax(um, (double)fmax(fmax(fabs(ux[e]), fabs(uy[e])), fabs(uz[e])));
-      const T wz = v[0][e].im;
+      const T wz = r == 0 ? wz0[e] : wz1[e];
       qx[e] = uy[e] * wz;   // px = uy wz - uz wy
       qy[e] = -ux[e] * wz;  // py = uz wx - ux wz
+    }
+#pragma unroll
+    for (int e = 0; e < 8; e++) uz[e] = r == 0 ? uz0[e] : uz1[e];
+    if (umax) {
+#pragma unroll
+      for (int e = 0; e < 8; e++)
+        um = fmax(um, (double)fmax(fmax(fabs(ux[e]), fabs(uy[e])), fabs(uz[e])));
     }
     if constexpr (STRAT) {
       // buoyancy flux u b (b carries the scale): (fx + i fy) now, fz paired
@@ -199,7 +264,7 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS))
         forward_store(v, 5, y0, 5, y0 + 1);
       }
     }
-    inverse_pair(2, r, v);
+    inverse_line(row_ptr(4, r), row_ptr(5, r), v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       const T wx = v[0][e].re, wy = v[0][e].im;

@@ -7,10 +7,13 @@ them would pass a global relative-L2 check.  Here every kept mode carries
 signal (per-mode rms exp(-|m|/K), K the largest kept mode), and each result
 is checked two ways against the FP64 oracle on the same (rounded) input:
 
-* relative L2 over the kept modes (half-spectrum weights): 1e-5 in FP32
-  (the stated target), 1e-12 in FP64;
+* relative L2 over the kept modes (half-spectrum weights): 1.5e-6 in FP32
+  (the stated target is 1e-5; a plain single-precision evaluation of the
+  same tendency, scipy's transforms in FP32, gives 3.4e-7 to 3.8e-7 at 64^3
+  to 128^3 and the GPU path 3.3e-7 to 4.2e-7 at 64^3 to 512^3), 1e-12 in
+  FP64;
 * per mode: the largest error over all kept modes and components, relative
-  to the largest reference value (FP32 5e-5, FP64 5e-12).  The FP32
+  to the largest reference value (FP32 2e-6, FP64 5e-12).  The FP32
   rounding error of the transforms and of the physical product is spread
   over all modes at a level set by the largest values (a few 2^-24
   sqrt(log2 N) of them), so this is the bound for rounding;
@@ -22,11 +25,16 @@ is checked two ways against the FP64 oracle on the same (rounded) input:
   anywhere (a whole wrong value) is of the order of the shell's own values
   and exceeds this bound by a wide margin.
 
-These bounds found the one real defect they were written for: the x pass
-once paired uz and wx in one complex transform line, and the rounding that
-couples a line's real and imaginary parts then biased the product uz wx, an
-error that averages out nowhere except on the (kx, 0, 0) line (up to 1e-4
-of the largest value there, rel-L2 unaffected).
+These bounds found two defects of the x pass's complex transform lines.
+It once paired uz and wx in one line, and the rounding that couples a
+line's real and imaginary parts then biased the product uz wx, an error
+that averages out nowhere except on the (kx, 0, 0) line (up to 1e-4 of the
+largest value there, rel-L2 unaffected).  Later it paired uz with wz: a
+velocity and a vorticity component in one line leave the vorticity's
+rounding, about |k| times larger, on the velocity, and the error grew with
+N (rel-L2 6.6e-7, 1.3e-6, 2.9e-6, 6.1e-6 at 64^3 to 512^3, under the old
+1e-5 bound); with like paired with like (uz of both rows, wz of both rows)
+it stays at the single-precision floor, which the bounds now hold.
 
 Sizes span several kx tiles and a ragged last tile (K = 21, 42, 85, 170 at
 N = 64, 128, 256, 512: 22, 43, 86, 171 kept kx values in tiles of 16), and
@@ -40,8 +48,8 @@ from paper_1807_01769_amd import inputs as I
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-TOL_L2 = {"f32": 1e-5, "f64": 1e-12}
-TOL_MODE = {"f32": 5e-5, "f64": 5e-12}
+TOL_L2 = {"f32": 1.5e-6, "f64": 1e-12}
+TOL_MODE = {"f32": 2e-6, "f64": 5e-12}
 TOL_SHELL = {"f32": 1e-2, "f64": 1e-9}
 
 
