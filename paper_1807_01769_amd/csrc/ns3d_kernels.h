@@ -44,8 +44,7 @@ namespace fs {
 // Grid: (N/2/RP, N) with RP = XRows<T, N, STRAT>::RP.
 // ---------------------------------------------------------------------------
 // Row pairs of a block: the seven staged fields of a double-precision
-// stratified pass take half as many row pairs per block, so that the block
-// stays within 64 KiB of LDS.
+// stratified pass take half as many row pairs per block (LDS).
 template <typename T, int N, bool STRAT>
 using XRows = RowPairs<N, (STRAT && sizeof(T) == 8) ? 32 : 64>;
 
@@ -58,45 +57,43 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
   using R = XRows<T, N, STRAT>;
   constexpr int P = G::P;
   constexpr int FIN = STRAT ? 7 : 6;  // input fields
-  // staging: kept coefficients [field][row][xt][16] of one row at a time
-  // (the stratified pass stages the pair: b of both rows forms one line)
-  constexpr int NRS = STRAT ? 2 : 1;
-  constexpr int SPAIR = FIN * G::XT * NRS * kTile;
+  // staging: kept coefficients [field][xt][16] of one row at a time (the
+  // second row's fields of the cross-row lines come from HBM directly)
+  constexpr int SROW = FIN * G::XT * kTile;
   static_assert(STRAT == false || N > 512 || sizeof(T) == 4 ||
-                    (size_t)R::RP * (SPAIR + R::NPAD) * sizeof(cx<T>) <= 65536,
+                    (size_t)R::RP * (SROW + R::NPAD) * sizeof(cx<T>) <= 65536,
                 "x-pass staging exceeds 64 KiB of LDS");
-  __shared__ cx<T> stage[R::RP * SPAIR];
+  __shared__ cx<T> stage[R::RP * SROW];
   __shared__ cx<T> lds[R::RP * R::NPAD];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
   const Twiddles<T, N> twr(tw, t);
   const int z = blockIdx.y;
   const int y0 = 2 * (blockIdx.x * R::RP + rp);
   cx<T>* line = lds + rp * R::NPAD;
-  cx<T>* st = stage + rp * SPAIR;
+  cx<T>* st = stage + rp * SROW;
   auto lidx = [=](int, int pos) { return R::pad(pos); };
   const size_t fstride = (size_t)N * G::XT * N * kTile;  // one field
 
-  // staging of rows y0 + r0 .. y0 + r0 + NRS - 1: for each (field, tile) the
-  // rows are NRS*16 contiguous coefficients; 16-byte loads, all in flight.
-  // With SKIP, fields 2 and 3 (uz, wz) are left out: the second row's are
-  // read for the cross lines before its staging.
-  auto stage_rows = [&](int r0, auto skip) {
+  // staging of row y0 + r: for each (field, tile) the row is 16 contiguous
+  // coefficients; 16-byte loads, all in flight.  With SKIP, the fields of
+  // the cross-row lines (uz, wz; b) are left out: the second row's are read
+  // for those lines before its staging.
+  auto stage_row = [&](int r, auto skip) {
     constexpr bool SKIP = decltype(skip)::value;
-    constexpr int PER = 16 / (int)sizeof(cx<T>);          // coefficients per load
-    constexpr int NF = SKIP ? FIN - 2 : FIN;              // fields staged
-    constexpr int LOADS = NF * G::XT * NRS * kTile / PER;  // per stage
+    constexpr int PER = 16 / (int)sizeof(cx<T>);  // coefficients per load
+    constexpr int NF = SKIP ? 4 : FIN;            // fields staged: 0, 1, 4, 5 with SKIP
+    constexpr int LOADS = NF * G::XT * kTile / PER;
     const uint4* src4 = reinterpret_cast<const uint4*>(in);
     uint4* st4 = reinterpret_cast<uint4*>(st);
 #pragma unroll
     for (int i0 = 0; i0 < LOADS; i0 += P) {
       const int i = i0 + t;
       if (i < LOADS) {
-        const int c = i / (NRS * kTile / PER), l = i % (NRS * kTile / PER);
+        const int c = i / (kTile / PER), lo = i % (kTile / PER);
         const int fs = c / G::XT, xt = c % G::XT;
         const int f = SKIP && fs >= 2 ? fs + 2 : fs;
-        const int r = l / (kTile / PER), lo = l % (kTile / PER);
-        const size_t g = ((((size_t)f * N + z) * G::XT + xt) * N + y0 + r0) * kTile;
-        st4[((f * NRS + r) * G::XT + xt) * (kTile / PER) + lo] = src4[g / PER + l];
+        const size_t g = ((((size_t)f * N + z) * G::XT + xt) * N + y0 + r) * kTile;
+        st4[(f * G::XT + xt) * (kTile / PER) + lo] = src4[g / PER + lo];
       }
     }
   };
@@ -119,19 +116,18 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
 #pragma unroll
     for (int e = 0; e < 8; e++) bv[e] = src[(size_t)(off[e] >> 4) * N * kTile + (off[e] & 15)];
   };
-  // the second row's wz and uz (see the lines below) are loaded with the
-  // staging of the first row and have arrived by its barrier
-  cx<T> bw[8], bu[8];
-  if constexpr (NRS == 1) {
-    row1_field(3, bw);
-    row1_field(2, bu);
-  }
-  stage_rows(0, std::false_type{});
-  if constexpr (NRS == 1) {
-    // held here, before the barrier: not sunk below it into the transforms
+  // the second row's wz, uz (and b) for the cross lines below are loaded
+  // with the staging of the first row and have arrived by its barrier
+  cx<T> bw[8], bu[8], bb[STRAT ? 8 : 1];
+  row1_field(3, bw);
+  row1_field(2, bu);
+  if constexpr (STRAT) row1_field(6, bb);
+  stage_row(0, std::false_type{});
+  // held here, before the barrier: not sunk below it into the transforms
 #pragma unroll
-    for (int e = 0; e < 8; e++)
-      asm volatile("" : "+v"(bw[e].re), "+v"(bw[e].im), "+v"(bu[e].re), "+v"(bu[e].im));
+  for (int e = 0; e < 8; e++) {
+    asm volatile("" : "+v"(bw[e].re), "+v"(bw[e].im), "+v"(bu[e].re), "+v"(bu[e].im));
+    if constexpr (STRAT) asm volatile("" : "+v"(bb[e].re), "+v"(bb[e].im));
   }
   __syncthreads();
 
@@ -186,16 +182,15 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
   // cross lines come first; the second row's uz, wz are read from HBM
   // directly (16 lanes per 128-byte row), in flight with the staging loads
   // of the first row.
-  auto row_ptr = [&](int f, int r) -> const cx<T>* {
-    return st + (f * NRS + (NRS == 2 ? r : 0)) * G::XT * kTile;
-  };
+  // field f of the staged row
+  auto row_ptr = [&](int f) -> const cx<T>* { return st + f * G::XT * kTile; };
   T pz0[8], uz1[8], wz1[8], wz0[8];
   double um = 0.0;  // largest |u_c| seen (only when umax is requested)
   // buoyancy of both rows (b(y0) + i b(y1)) and the first row's fz
   T bq[2][8], fz0[8];
   if constexpr (STRAT) {
     cx<T> v[1][8];
-    inverse_line(row_ptr(6, 0), row_ptr(6, 1), v);
+    inverse_line_v(row_ptr(6), bb, v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       bq[0][e] = v[0][e].re * scale;
@@ -205,20 +200,13 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
   T uz0[8];
   {
     cx<T> v[1][8];
-    if constexpr (NRS == 2) {
-#pragma unroll
-      for (int e = 0; e < 8; e++) {
-        bw[e] = row_ptr(3, 1)[off[e]];
-        bu[e] = row_ptr(2, 1)[off[e]];
-      }
-    }
-    inverse_line_v(row_ptr(3, 0), bw, v);
+    inverse_line_v(row_ptr(3), bw, v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       wz0[e] = v[0][e].re;
       wz1[e] = v[0][e].im;
     }
-    inverse_line_v(row_ptr(2, 0), bu, v);
+    inverse_line_v(row_ptr(2), bu, v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       uz0[e] = v[0][e].re;
@@ -227,14 +215,14 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
   }
 #pragma unroll
   for (int r = 0; r < 2; r++) {
-    if (NRS == 1 && r == 1) {
+    if (r == 1) {
       // every read of row 0 ended before the last barrier of its stores
-      stage_rows(1, std::true_type{});
+      stage_row(1, std::true_type{});
       __syncthreads();
     }
     T ux[8], uy[8], uz[8], qx[8], qy[8];
     cx<T> v[1][8];
-    inverse_line(row_ptr(0, r), row_ptr(1, r), v);
+    inverse_line(row_ptr(0), row_ptr(1), v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       ux[e] = v[0][e].re;
@@ -264,7 +252,7 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
         forward_store(v, 5, y0, 5, y0 + 1);
       }
     }
-    inverse_line(row_ptr(4, r), row_ptr(5, r), v);
+    inverse_line(row_ptr(4), row_ptr(5), v);
 #pragma unroll
     for (int e = 0; e < 8; e++) {
       const T wx = v[0][e].re, wy = v[0][e].im;
