@@ -115,6 +115,7 @@ __global__ void __launch_bounds__(RP * N / 8)
   // fewer registers, more waves per CU); with buoyancy the lines go together
   constexpr int NLDS = NF == 1 ? 1 : NL;
   __shared__ cx<T> lds[RP * NLDS * R::NPAD];
+  __shared__ cx<T> stage[NF == 1 ? RP * 6 * G::XT * kTile : 1];
   const int rp = threadIdx.x / P, t = threadIdx.x % P;
   const Twiddles<T, N> twr(tw, t);
   const int run = blockIdx.x / bt.bpr, part = blockIdx.x % bt.bpr;
@@ -128,13 +129,35 @@ __global__ void __launch_bounds__(RP * N / 8)
     return in[f * fstride + ((size_t)(m >> 4) * N + y) * kTile + (m & 15)];
   };
   if constexpr (NF == 1) {
-    // (w(y0) + i w(y1)) first, then per row (u + i v), its products (u w,
-    // v w) forward-transformed as one line and untangled
+    // The pair's kept coefficients of u, v, w (for each field, row and tile
+    // 16 contiguous values) are staged in LDS with 16-byte loads, all in
+    // flight; then (w(y0) + i w(y1)), and per row (u + i v) and its products
+    // (u w, v w) forward-transformed as one line and untangled.
+    constexpr int SROW = G::XT * kTile;  // one field of one row
+    cx<T>* stg = stage + rp * 6 * SROW;
+    {
+      constexpr int PER = 16 / (int)sizeof(cx<T>);
+      constexpr int LOADS = 6 * SROW / PER;
+      const uint4* src4 = reinterpret_cast<const uint4*>(in);
+      uint4* st4 = reinterpret_cast<uint4*>(stg);
+#pragma unroll
+      for (int i0 = 0; i0 < LOADS; i0 += P) {
+        const int i = i0 + t;
+        if (i < LOADS) {
+          const int c = i / (kTile / PER), lo = i % (kTile / PER);
+          const int fr = c / G::XT, xt = c % G::XT;  // fr = 2 f + r
+          const size_t g = (fr / 2) * fstride + ((size_t)xt * N + y0 + fr % 2) * kTile;
+          st4[c * (kTile / PER) + lo] = src4[g / PER + lo];
+        }
+      }
+      __syncthreads();
+    }
+    auto sat = [=](int f, int r) { return stg + (2 * f + r) * SROW; };
     cx<T> v[1][8];
 #pragma unroll
     for (int e = 0; e < 8; e++)
-      v[0][e] = c2r_pair_at<T, N, false>(t + e * P, [&](int m) { return at(2, y0, m); },
-                                         [&](int m) { return at(2, y0 + 1, m); });
+      v[0][e] = c2r_pair_at<T, N, false>(t + e * P, [&](int m) { return sat(2, 0)[m]; },
+                                         [&](int m) { return sat(2, 1)[m]; });
     fft_lines<T, N, +1, 1>(v, t, my_lds, lidx, twr);
     T ws[2][8];
 #pragma unroll
@@ -145,16 +168,10 @@ __global__ void __launch_bounds__(RP * N / 8)
     double um = 0.0;
 #pragma unroll
     for (int r = 0; r < 2; r++) {
-      // this row's loads stay after the previous transform (through an
-      // opaque copy of the read-only input), not hoisted into its registers
-      const cx<T>* inr = opaque_ptr(in);
-      auto atr = [=](int f, int m) -> cx<T> {
-        return inr[f * fstride + ((size_t)(m >> 4) * N + y0 + r) * kTile + (m & 15)];
-      };
 #pragma unroll
       for (int e = 0; e < 8; e++)
-        v[0][e] = c2r_pair_at<T, N, false>(t + e * P, [&](int m) { return atr(0, m); },
-                                           [&](int m) { return atr(1, m); });
+        v[0][e] = c2r_pair_at<T, N, false>(t + e * P, [&](int m) { return sat(0, r)[m]; },
+                                           [&](int m) { return sat(1, r)[m]; });
       fft_lines<T, N, +1, 1>(v, t, my_lds, lidx, twr);
 #pragma unroll
       for (int e = 0; e < 8; e++) {
