@@ -131,9 +131,8 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
   }
   __syncthreads();
 
-  // inverse transform of the complex line A + i B (half spectrum A staged in
-  // ba)
-  // (bv: B at each register position, loaded beforehand)
+  // inverse transform of the complex line A + i B: half spectrum A staged at
+  // ba, B given at each register position (bv)
   auto inverse_line_v = [&](const cx<T>* ba, const cx<T> (&bv)[8], cx<T> (&v)[1][8]) {
 #pragma unroll
     for (int e = 0; e < 8; e++) {
@@ -179,11 +178,10 @@ __global__ void __launch_bounds__((XRows<T, N, STRAT>::THREADS),
   // the tendency then grows with N).  Row by row the cross product is built
   // as its factors arrive; (px + i py) of each row is transformed at once,
   // pz of the first row waits to be paired with pz of the second.  The two
-  // cross lines come first; the second row's uz, wz are read from HBM
-  // directly (16 lanes per 128-byte row), in flight with the staging loads
-  // of the first row.
-  // field f of the staged row
-  auto row_ptr = [&](int f) -> const cx<T>* { return st + f * G::XT * kTile; };
+  // cross lines (and b's) come first; the second row's fields of them are
+  // read from HBM directly (16 lanes per 128-byte row), in flight with the
+  // staging loads of the first row.
+  auto row_ptr = [&](int f) -> const cx<T>* { return st + f * G::XT * kTile; };  // staged row
   T pz0[8], uz1[8], wz1[8], wz0[8];
   double um = 0.0;  // largest |u_c| seen (only when umax is requested)
   // buoyancy of both rows (b(y0) + i b(y1)) and the first row's fz
