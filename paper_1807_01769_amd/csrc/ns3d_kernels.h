@@ -316,7 +316,8 @@ __device__ __forceinline__ const cx<T>* zpass_twiddles(const cx<T>* __restrict__
 // ---------------------------------------------------------------------------
 // Inverse z transforms of a stage input v held in registers as v[c][e] at
 // z-position t + e*P of line b: the velocity and the horizontal vorticity
-// (wx, wy; w = i k x v), written to Wm[5][N][XT][M][16] as ux uy uz wx wy.
+// (wx, wy; w = i k x v), written to the compact workspace Wm (Geo::wm_row) as
+// ux uy uz wx wy.
 // The vertical vorticity needs no kz and is formed by the inverse y pass.
 // NC = 4 adds the buoyancy v[3] as field 5.
 // ---------------------------------------------------------------------------
@@ -327,9 +328,9 @@ __device__ __forceinline__ void z_inverse(cx<T> (&v)[NC][8], int t, int b, int j
   using G = Geo<N, false>;
   using C = ZCfg<T, N, NC>;
   constexpr int P = G::P;
-  const size_t fstride = (size_t)N * G::XT * G::M * kTile;
-  cx<T>* dst0 = w1 + (size_t)xt * G::M * kTile + (size_t)jy * kTile + sub * C::LB + b;
-  const size_t zstride = (size_t)G::XT * G::M * kTile;
+  const size_t fstride = G::wm_row(1, 0, 0);
+  cx<T>* dst0 = w1 + G::wm_row(0, xt, 0) + (size_t)jy * kTile + sub * C::LB + b;
+  const size_t zstride = G::kWmZ;
   auto lidx = [=](int, int pos) { return pos * C::LB + b; };
   const T kx = kb * (T)mx, ky = kb * (T)my;
   // vorticity first (needs v), then velocity in place
@@ -435,7 +436,7 @@ __global__ void __launch_bounds__((ZCfg<T, N, NC>::THREADS))
 }
 
 // ---------------------------------------------------------------------------
-// Z pass: forward z transforms of the stage's products (Wm[3][N][XT][M][16]),
+// Z pass: forward z transforms of the stage's products (Wm[3], Geo::wm_row),
 // projection + forcing -> tendency of this stage, Lawson RK4 combine, and
 // (do_p1) the next stage's five (six) inverse z transforms into w1.
 // MODE kModeTend writes the tendency to a.tend instead.  PROP selects the
@@ -467,9 +468,9 @@ __global__ void __launch_bounds__((ZCfg<T, N, prop_boussinesq(PROP) ? 4 : 3>::TH
   auto lidx = [=](int, int pos) { return pos * C::LB + b; };
 
   // forward z transforms of the three product components
-  const size_t fstride = (size_t)N * G::XT * G::M * kTile;
-  const size_t zstride = (size_t)G::XT * G::M * kTile;
-  const cx<T>* src0 = w4 + (size_t)xt * G::M * kTile + (size_t)jy * kTile + sub * C::LB + b;
+  const size_t fstride = G::wm_row(1, 0, 0);
+  const size_t zstride = G::kWmZ;
+  const cx<T>* src0 = w4 + G::wm_row(0, xt, 0) + (size_t)jy * kTile + sub * C::LB + b;
   // all three components' loads are issued before the first transform
   cx<T> v[NC][8];
 #pragma unroll

@@ -13,7 +13,8 @@
 //
 // Intermediate workspace arrays are tile-blocked so that every strided pass
 // reads and writes whole 16-element (128 B for complex64) rows:
-//   Wm[f][z][xt][j][16]  (compact index along y)
+//   Wm[f][z][xt][j][16]  (compact index along y; from N = 1024 on the 3D step
+//                         uses Wm[f][xt][z][j][16], see Geo::wm_row)
 //   Wn[f][z][xt][y][16]  (full index along y)
 // In 2D the z extent is 1.
 #pragma once
@@ -54,6 +55,21 @@ struct Geo {
   }
   // signed mode number of a kept compact index
   __host__ __device__ static constexpr int jmode(int j) { return j <= K ? j : j - M; }
+  // First element of row (field f, kx tile xt, z plane z) of the compact-y
+  // workspace of a dealiased 3D step, and the distance between the rows of
+  // adjacent z planes.  From N = 1024 on the z planes of one kx tile are
+  // adjacent, Wm[f][xt][z][j][16]: a z line then steps M rows per plane, not
+  // XT * M (1.9 MB at 1024), so the 128 planes that one access of a z-pass
+  // block touches lie in a few large pages instead of one page each, which
+  // the per-CU address translation cache could not hold.  Below 1024 the
+  // planes lie within few pages either way and Wm[f][z][xt][j][16] keeps the
+  // y passes' neighbouring blocks on neighbouring rows.
+  static constexpr bool kWmTileMajor = N >= 1024;
+  __host__ __device__ static constexpr size_t wm_row(int f, int xt, int z) {
+    return kWmTileMajor ? (((size_t)f * XT + xt) * N + z) * M * kTile
+                        : (((size_t)f * N + z) * XT + xt) * M * kTile;
+  }
+  static constexpr size_t kWmZ = (size_t)(kWmTileMajor ? 1 : XT) * M * kTile;
 };
 
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -557,7 +573,7 @@ __global__ void __launch_bounds__((YCfg<T, N, true>::THREADS), 4)
   const size_t zoff = (size_t)z * G::XT + xt;
   const int fin = unit == 0 ? 0 : unit + 1;
   const int fout = unit == 0 ? 0 : (unit == 1 ? 2 : unit + 2);
-  const cx<T>* src = in + (zoff + (size_t)fin * N * G::XT) * G::M * kTile + lane;
+  const cx<T>* src = in + G::wm_row(fin, xt, z) + lane;
   cx<T>* dst = out + (zoff + (size_t)fout * N * G::XT) * N * kTile + lane;
   cx<T> v[F][8];
 #pragma unroll
@@ -596,7 +612,7 @@ __global__ void __launch_bounds__((YCfg<T, N, true>::THREADS), 4)
   for (int e = 0; e < 8; e++) st_lines<T, F>(&dst[(t + e * P) * kTile], v, e);
   // uy is loaded only now: hoisted above the ux transform, its loads would
   // hold a third line of registers through it
-  const cx<T>* src1 = opaque_ptr(in) + (zoff + (size_t)N * G::XT) * G::M * kTile + lane;
+  const cx<T>* src1 = opaque_ptr(in) + G::wm_row(1, xt, z) + lane;
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int j = G::i2j(t + e * P);
@@ -659,7 +675,9 @@ __global__ void __launch_bounds__((YCfg<T, N, !FULL>::THREADS))
   }
   fft_lines<T, N, -1, F>(v, t, lds, [=](int f, int pos) { return pos * C::LINES + F * b + f; },
                          twr);
-  cx<T>* dst = out + tile * G::M * kTile + sub * C::LINES + F * b;
+  const size_t orow = FULL ? tile * G::M * kTile
+                           : G::wm_row(row / N, rem / C::SUB, row % N);
+  cx<T>* dst = out + orow + sub * C::LINES + F * b;
 #pragma unroll
   for (int e = 0; e < 8; e++) {
     const int j = G::i2j(t + e * G::P);
