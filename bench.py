@@ -187,24 +187,35 @@ def closure_les_speed(fs, torch, plan, state, nc, steps, dns_ms_per_step):
 ENS_NU, ENS_DT = 1e-4, 5e-4
 
 
-def ensemble_alg_bytes(sizes) -> float:
+RESIDENT_SIZES = (64, 128)  # classes advanced block-resident by default
+
+
+def ensemble_alg_bytes(sizes, resident=RESIDENT_SIZES) -> float:
     """Bytes one 2D RK4 step of the ensemble must move if only kept modes
     travel: per stage the x pass reads 3 fields and writes 2 (N x H each), the
     y pass reads those 2, the state and accumulator (M x H) and writes 3
-    fields and the accumulator; the state is written once per step."""
+    fields and the accumulator; the state is written once per step.  A
+    block-resident run keeps the N x H fields in LDS and moves only the state
+    and accumulator: 3 state and 3 accumulator reads, 3 accumulator writes
+    and one state write per step."""
     tot = 0.0
     for n in sizes:
         K = (n - 1) // 3
         M, H = 2 * K + 1, K + 1
         un, us = n * H * 8.0, M * H * 8.0
-        tot += 4 * (3 * un + 2 * un + 2 * un + 3 * un + 3 * us) + us
+        if n in resident:
+            tot += 10 * us
+        else:
+            tot += 4 * (3 * un + 2 * un + 2 * un + 3 * un + 3 * us) + us
     return tot
 
 
 def time_ensemble(fs, torch, I, np, steps):
     """256 independent 2D runs (128 at 128^2, 96 at 256^2, 32 at 512^2), FP32,
     nu = 1e-4, dt = 5e-4, `steps` RK4 steps: one graph launch per size class,
-    the classes on streams of their own; then the same with direct launches."""
+    the classes on streams of their own (the 128^2 class block-resident);
+    then the same with direct launches, and with the 128^2 class
+    class-batched."""
     sizes = I.ensemble_sizes()
     fields = [I.ensemble_vorticity(r, n).astype(np.complex64) for r, n in enumerate(sizes)]
     log("ensemble inputs ready")
@@ -241,6 +252,22 @@ def time_ensemble(fs, torch, I, np, steps):
     res["direct_streams"] = {"gridpoint_steps_per_s": pts * steps / (t1 - t0),
                              "ms_total": (t1 - t0) * 1e3,
                              "same_result": bool(torch.equal(st, st2))}
+    ens.close()
+    # the 128^2 class class-batched too (two passes per stage through HBM)
+    # instead of block-resident, one graph per class
+    ens = fs.Ensemble(sizes, nu=ENS_NU, dt=ENS_DT, resident=False)
+    st3 = ens.pack(fields)
+    ens.step(st3, steps)
+    st3 = ens.pack(fields)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.step(st3, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res["class_batched_small"] = {"gridpoint_steps_per_s": pts * steps / (t1 - t0),
+                                  "ms_total": (t1 - t0) * 1e3,
+                                  "same_result": bool(torch.equal(st, st3)),
+                                  "schedule": ens.schedule()}
     ens.close()
     res["counters"] = read_ensemble_counters()
     return res, sizes, fields
@@ -301,7 +328,8 @@ def bench_ensemble(args) -> int:
                                   "FP32, nu=1e-4, dt=5e-4, E(k)~k exp(-(k/6)^2), seeds 1000+r",
                       "gridpoints": pts},
            "alg_GBps": res["alg_GBps"], "schedule": res["schedule"],
-           "direct_streams": res["direct_streams"], "counters": res["counters"],
+           "direct_streams": res["direct_streams"],
+           "class_batched_small": res["class_batched_small"], "counters": res["counters"],
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
     return 0

@@ -72,6 +72,7 @@ enum { FS_SCHEME_RK4 = 0, FS_SCHEME_RK2 = 1 };
 #define FS_NO_GRAPH 0x1u /* launch kernels one by one instead of a captured graph */
 #define FS_PROFILE 0x2u  /* time every kernel with events (see fs_profile_read) */
 #define FS_NO_AUTOTUNE 0x4u /* ensembles: keep the default schedules */
+#define FS_NO_RESIDENT 0x20u /* ensembles: no block-resident small classes */
 /* Boussinesq (stably stratified) flow with a buoyancy field b (Prandtl
  * number 1, squared buoyancy frequency opts.n2), advected in conservative
  * form and dealiased like the velocity.
@@ -121,7 +122,7 @@ typedef struct {
   double forcing_kmin;  /* forcing band kmin <= |k| <= kmax (default 2, 3) */
   double forcing_kmax;
   unsigned flags;       /* FS_NO_GRAPH | FS_PROFILE | FS_NO_AUTOTUNE | FS_BOUSSINESQ |
-                           FS_CHECK_FINITE */
+                           FS_CHECK_FINITE | FS_NO_RESIDENT */
   int scheme;           /* FS_SCHEME_RK4 (default) or FS_SCHEME_RK2 */
   double cfl;           /* > 0: adaptive steps, dt_n = min(dt, cfl (L/n) / umax_n) with
                            umax_n the largest |u_c| of the physical velocity of u_n
@@ -335,12 +336,16 @@ fs_status fs_profile_read(fs_plan *plan, double *ms, long *counts, const char **
  *
  * fs_ensemble_create: nruns runs with grid sizes n[r] in {64, 128, 256, 512}
  * sharing L, nu, dt (opts: ndim must be 2, precision FS_F32, no forcing;
- * flags FS_NO_GRAPH, FS_NO_AUTOTUNE; fixed-dt RK4, no rotation or buoyancy,
- * no caller workspace).  The packed state is the concatenation
+ * flags FS_NO_GRAPH, FS_NO_AUTOTUNE, FS_NO_RESIDENT; fixed-dt RK4, no rotation
+ * or buoyancy, no caller workspace).  The packed state is the concatenation
  * of the runs' 2D states, run r at complex offset offsets[r] (see
- * fs_ensemble_offsets).  Runs of equal size form a class; at creation the
- * block schedule of every class is chosen by timing candidates on the
- * device (unless FS_NO_AUTOTUNE).  Owns its workspace.
+ * fs_ensemble_offsets).  Runs of equal size form a class.  Classes of 64 and
+ * 128 points a side are advanced block-resident: one block per run keeps the
+ * run's intermediate fields in LDS through all steps of a call and touches
+ * HBM only for the state and its accumulator (the class-batched results up
+ * to rounding; FS_NO_RESIDENT treats them like the larger classes).  For the other
+ * classes the block schedule is chosen at creation by timing candidates on
+ * the device (unless FS_NO_AUTOTUNE).  Owns its workspace.
  */
 typedef struct fs_ensemble fs_ensemble;
 fs_status fs_ensemble_create(fs_ensemble **out, int nruns, const int *n, double L, double nu,
@@ -359,7 +364,8 @@ fs_status fs_ensemble_offsets(const fs_ensemble *ens, int64_t *offsets);
 fs_status fs_ensemble_step_rk4(fs_ensemble *ens, void *packed_state, int nsteps);
 /* Chosen schedule of class cls (classes in increasing size): its size, run
  * count, y-pass lines per block, x-pass row pairs per block and the tuned
- * per-launch times in microseconds (0 when taken from the cache). */
+ * per-launch times in microseconds (0 when taken from the cache); a
+ * block-resident class reports 0 for the last four. */
 fs_status fs_ensemble_schedule(const fs_ensemble *ens, int cls, int *n, int *nruns, int *y_lines,
                                int *x_rowpairs, double *us_y, double *us_x);
 fs_status fs_ensemble_destroy(fs_ensemble *ens); /* NULL is a no-op */

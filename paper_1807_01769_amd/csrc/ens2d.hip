@@ -7,6 +7,11 @@
 // steps, as one hipGraph and launches the classes' graphs once each on their
 // own streams, which run concurrently.
 //
+// Classes of at most 128 points a side are advanced block-resident: one block
+// per run holds the run's (kx, y) intermediate in LDS through all steps of a
+// call (k2_resident), one launch per call, the class-batched result up to
+// rounding; FS_NO_RESIDENT runs them class-batched like the larger classes.
+//
 // Schedules: the y passes can use 16, 8, 4 or 2 kx lines per block and the
 // x pass one, two or four times the default row pairs per block.  At creation an
 // autotuner times every candidate of every class on the class's own
@@ -38,6 +43,7 @@ constexpr int kXCand[] = {1, 2, 4};   // multiples of the default row pairs
 struct EnsClass {
   int n = 0, nruns = 0;
   int ylines = 16, xmul = 1;           // chosen schedule
+  bool resident = false;               // advanced by k2_resident
   double us_y = 0, us_x = 0;           // tuned per-launch times (microseconds)
   std::vector<int> runs;               // global run index of each local run
   long long* state_off = nullptr;      // device, per local run
@@ -192,8 +198,24 @@ void class_x(const Ensemble* e, const EnsClass& c, hipStream_t s) {
   }
 }
 
+template <int N>
+void launch_resident(const Ensemble* e, const EnsClass& c, void* state, int nsteps,
+                     hipStream_t s) {
+  if constexpr (Resident<N>::kFits) {
+    Batch bt{c.state_off, 0, 0, c.accs, 1};
+    hipLaunchKernelGGL((k2_resident<N>), dim3(c.nruns), dim3(Resident<N>::THREADS), 0, s,
+                       args_of(e, c, state), bt, nsteps);
+  }
+}
+bool resident_size(int n) { return n == 64 || n == 128; }
+
 // all steps of one class on stream s
 void class_steps(Ensemble* e, EnsClass& c, void* state, int nsteps, hipStream_t s) {
+  if (c.resident) {
+    if (c.n == 64) launch_resident<64>(e, c, state, nsteps, s);
+    else launch_resident<128>(e, c, state, nsteps, s);
+    return;
+  }
   class_p1(e, c, state, s);
   for (int k = 0; k < nsteps; k++)
     for (int mode = 1; mode <= 4; mode++) {
@@ -326,7 +348,7 @@ fs_status fs_ensemble_create(fs_ensemble** out, int nruns, const int* n, double 
     fs::set_error("ensembles have no forcing");
     return FS_E_UNSUPPORTED;
   }
-  if (o.flags & ~(FS_NO_GRAPH | FS_NO_AUTOTUNE)) {
+  if (o.flags & ~(FS_NO_GRAPH | FS_NO_AUTOTUNE | FS_NO_RESIDENT)) {
     fs::set_error("unsupported flags for an ensemble");
     return FS_E_INVALID;
   }
@@ -362,6 +384,7 @@ fs_status fs_ensemble_create(fs_ensemble** out, int nruns, const int* n, double 
       if (n[r] == sz) c.runs.push_back(r);
     if (!c.runs.empty()) {
       c.nruns = (int)c.runs.size();
+      c.resident = fs::resident_size(sz) && !(o.flags & FS_NO_RESIDENT);
       e->cls.push_back(c);
     }
   }
@@ -435,7 +458,7 @@ fs_status fs_ensemble_create(fs_ensemble** out, int nruns, const int* n, double 
     // zero offsets so every run of a class reads the same scratch run
     for (auto& c : e->cls) {
       if (!good) break;
-      if (!(o.flags & FS_NO_AUTOTUNE)) {
+      if (!(o.flags & FS_NO_AUTOTUNE) && !c.resident) {
         std::vector<long long> zero(c.nruns, 0);
         for (int l = 0; l < c.nruns; l++) zero[l] = (long long)l * c.n * (c.n / 2 + 1);
         good = fs::ok(e, hipMemcpy(c.state_off, zero.data(), sizeof(long long) * c.nruns, hipMemcpyHostToDevice), "copy");
@@ -481,6 +504,13 @@ fs_status fs_ensemble_schedule(const fs_ensemble* ens, int cls, int* n, int* nru
   const EnsClass& c = ens->e.cls[cls];
   if (n) *n = c.n;
   if (nruns) *nruns = c.nruns;
+  if (c.resident) {
+    if (y_lines) *y_lines = 0;
+    if (x_rowpairs) *x_rowpairs = 0;
+    if (us_y) *us_y = 0;
+    if (us_x) *us_x = 0;
+    return FS_OK;
+  }
   if (y_lines) *y_lines = c.ylines;
   int rp = 1;
   switch (c.n) {

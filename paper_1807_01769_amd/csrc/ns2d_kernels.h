@@ -25,6 +25,8 @@
 // mx = part * LB + b of the padded kx range [0, 16 XT); X passes use RP row
 // pairs per block, RP * N/8 threads.
 #pragma once
+#include <type_traits>
+
 #include "ns_common.h"
 
 namespace fs {
@@ -335,6 +337,228 @@ __global__ void __launch_bounds__(LB * N / 8)
   }
   if constexpr (MODE != kModeTend) {
     if (do_p1) y_inverse_fields<T, N, LB, NF>(w, t, b, mx, a.kb, w1, lds, twr);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-resident steps of small plain-flow runs (an ensemble's small size
+// classes).  Up to N = 128 the (kx, y) intermediate of a run -- u, v, w at the
+// kept kx, 3 x N x H complex values (132 KB at 128) -- fits in LDS next to one
+// transform line per lane group, so one block advances one run through all
+// the steps of a call and goes to HBM only for the state and the accumulator
+// (29 KB each at 128, which stay in L2).  Each stage is the x pass and the y
+// pass of k2_x / k2_y done in turn on the block's LDS:
+//   x phase: per row pair, C2R of (w(y0) + i w(y1)) and of (u + i v) of each
+//            row, the products, R2C of (u w + i v w), untangled and written
+//            over u and v of that row;
+//   y phase: per kx column, forward y of (u w, v w), tendency, Lawson combine,
+//            and the inverse y transforms of the next input's u, v, w, each
+//            line using its own column slot as its exchange space.
+// The operations of the two kernels, in their order: the runs end where the
+// class-batched passes leave them up to rounding (the compiler may contract
+// multiply-adds differently in the two kernels).
+// LDS rows have an odd stride S >= H (column accesses of a wave's 16
+// positions then fall in distinct banks).  Grid: one block per run.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Resident {
+  static constexpr int P = N / 8;
+  static constexpr int H = Geo<N, false>::H;
+  static constexpr int S = H | 1;
+  // line groups: as many as the intermediate leaves LDS for (one padded
+  // exchange line each)
+  static constexpr int GROUPS = N == 128 ? 24 : 32;
+  static constexpr int THREADS = GROUPS * P;
+  static constexpr int NPAD = RowPairs<N>::NPAD;
+  static constexpr size_t kLds = (size_t)(3 * N * S + GROUPS * NPAD) * sizeof(cx<float>);
+  static constexpr bool kFits = N <= 128 && kLds <= 163840;
+};
+
+template <int N>
+__global__ void __launch_bounds__((Resident<N>::THREADS))
+    k2_resident(StageArgs<float> a, Batch bt, int steps) {
+  using T = float;
+  using G = Geo<N, false>;
+  using RS = Resident<N>;
+  static_assert(RS::kFits, "a run does not fit one block's LDS");
+  constexpr int P = G::P, NH = N / 2 + 1, S = RS::S, H = G::H;
+  // [field u v w][y][kx < S], then one exchange line per group: one array,
+  // so that a transform can take either as its exchange space through its
+  // index map alone (no branch around the barriers inside)
+  constexpr int kX = 3 * N * S;
+  __shared__ cx<T> buf[kX + RS::GROUPS * RS::NPAD];
+  const int g = threadIdx.x / P;
+  // t and kb are laundered at the start of every phase (relaunder): what
+  // derives from them is then recomputed per phase instead of being hoisted
+  // out of the step loop and held in registers through all of it
+  int t = threadIdx.x % P;
+  T kb = a.kb;
+  auto relaunder = [&]() { asm volatile("" : "+v"(t), "+s"(kb)); };
+  const Twiddles<T, N> twr(a.tw, t);
+  const int run = blockIdx.x;
+  const size_t soff = bt.state_off ? bt.state_off[run] : 0;
+  const int xo = kX + g * RS::NPAD;  // this group's exchange line
+  cx<T>* const myx = buf + xo;
+  auto row = [&](int f, int y) { return buf + (f * N + y) * S; };
+  // exchange space of line f of column mx: its own slot in the intermediate
+  // (act) or the group's exchange line
+  auto col_idx = [=](int f, int mx, bool act) {
+    return [=](int, int pos) { return act ? (f * N + pos) * S + mx : xo + RowPairs<N>::pad(pos); };
+  };
+  const T scale = (T)(1.0 / ((double)N * N));
+  const T dt = stage_dt(a);
+
+  // inverse y transforms of (u, v, w) of the stage input w0 at column mx into
+  // the column's slots (or, for a group past the last column, through its
+  // exchange line with nothing stored)
+  auto y_inverse = [&](const cx<T> (&w0)[8], int mx, bool act) {
+    const T kx = kb * (T)mx;
+#pragma unroll
+    for (int f = 0; f < 3; f++) {
+      cx<T> v[1][8];
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        const int iy = t + e * P;
+        const T ky = kb * (T)(iy <= N / 2 ? iy : iy - N);
+        const T k2 = kx * kx + ky * ky;
+        const T ik2 = k2 > (T)0 ? (T)1 / k2 : (T)0;
+        if (f == 0) v[0][e] = mul_i(cscale(w0[e], ky * ik2));
+        else if (f == 1) v[0][e] = mul_i(cscale(w0[e], -kx * ik2));
+        else v[0][e] = w0[e];
+      }
+      fft_lines<T, N, +1, 1>(v, t, buf, col_idx(f, mx, act), twr);
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < 8; e++) row(f, t + e * P)[mx] = v[0][e];
+      }
+    }
+  };
+
+  // first inverse pass of the call, from the state
+  for (int c0 = 0; c0 < H; c0 += RS::GROUPS) {
+    const int mx = c0 + g;
+    const bool act = mx < H;
+    cx<T> w0[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+      const int iy = t + e * P;
+      w0[e] = act && G::i2j(iy) >= 0 ? a.state[soff + (size_t)iy * NH + mx] : cx<T>{0, 0};
+    }
+    y_inverse(w0, mx, act);
+  }
+  __syncthreads();
+
+  auto x_phase = [&]() {
+    relaunder();
+    auto lidx = [=](int, int pos) { return RowPairs<N>::pad(pos); };
+    for (int p0 = 0; p0 < N / 2; p0 += RS::GROUPS) {
+      const int p = p0 + g;
+      const bool act = p < N / 2;
+      const int y0 = act ? 2 * p : 0;  // a spare group transforms rows 0, 1 and stores nothing
+      cx<T> v[1][8];
+#pragma unroll
+      for (int e = 0; e < 8; e++)
+        v[0][e] = c2r_pair_at<T, N, false>(t + e * P, [&](int m) { return row(2, y0)[m]; },
+                                           [&](int m) { return row(2, y0 + 1)[m]; });
+      fft_lines<T, N, +1, 1>(v, t, myx, lidx, twr);
+      T ws[2][8];
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        ws[0][e] = v[0][e].re * scale;
+        ws[1][e] = v[0][e].im * scale;
+      }
+#pragma unroll
+      for (int r = 0; r < 2; r++) {
+#pragma unroll
+        for (int e = 0; e < 8; e++)
+          v[0][e] = c2r_pair_at<T, N, false>(t + e * P, [&](int m) { return row(0, y0 + r)[m]; },
+                                             [&](int m) { return row(1, y0 + r)[m]; });
+        fft_lines<T, N, +1, 1>(v, t, myx, lidx, twr);
+#pragma unroll
+        for (int e = 0; e < 8; e++) v[0][e] = {v[0][e].re * ws[r][e], v[0][e].im * ws[r][e]};
+        fft_lines<T, N, -1, 1>(v, t, myx, lidx, twr);
+#pragma unroll
+        for (int e = 0; e < 8; e++) myx[lidx(0, t + e * P)] = v[0][e];
+        __syncthreads();
+        if (act) {
+          for (int m = t; m < H; m += P) {
+            cx<T> A, B;
+            r2c_untangle(myx[lidx(0, m)], myx[lidx(0, (N - m) & (N - 1))], A, B);
+            row(0, y0 + r)[m] = A;
+            row(1, y0 + r)[m] = B;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  };
+
+  auto y_phase = [&](auto mode_c, bool do_inv) {
+    constexpr int MODE = decltype(mode_c)::value;
+    relaunder();
+    bool bad = false;  // a non-finite value written to the state
+    for (int c0 = 0; c0 < H; c0 += RS::GROUPS) {
+      const int mx = c0 + g;
+      const bool act = mx < H;
+      const int ml = act ? mx : 0;
+      cx<T> f[2][1][8];
+#pragma unroll
+      for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int e = 0; e < 8; e++) f[c][0][e] = row(c, t + e * P)[ml];
+#pragma unroll
+      for (int c = 0; c < 2; c++) fft_lines<T, N, -1, 1>(f[c], t, buf, col_idx(c, mx, act), twr);
+      const T kx = kb * (T)mx;
+      cx<T> w0[8];
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        const int iy = t + e * P;
+        const int jy = G::i2j(iy);
+        if (!(act && jy >= 0)) {
+          w0[e] = {0, 0};
+          continue;
+        }
+        const int my = iy <= N / 2 ? iy : iy - N;
+        const T ky = kb * (T)my;
+        const size_t ci = ((size_t)(mx >> 4) * G::M + jy) * kTile + (mx & 15);
+        cx<T> nl = {0, 0};
+        if (mx != 0 || my != 0) nl = mul_i(cscale(f[0][0][e], -kx) - cscale(f[1][0][e], ky));
+        const size_t so = soff + (size_t)iy * NH + mx;
+        const T E = a.e1[mx] * a.e1[iy];
+        const T Eh = a.eh1[mx] * a.eh1[iy];
+        const size_t ao = run * bt.acc_stride + ci;
+        cx<T> acc = {0, 0}, u = {0, 0};
+        if constexpr (mode_reads_state(MODE)) u = a.state[so];
+        if constexpr (mode_reads_acc(MODE)) acc = a.acc[ao];
+        const cx<T> nxt = rk4_combine<MODE>(u, acc, nl, E, Eh, dt);
+        if constexpr (mode_writes_state(MODE)) {
+          a.state[so] = nxt;
+          bad |= nonfinite(nxt);
+        }
+        if constexpr (mode_writes_acc(MODE)) a.acc[ao] = acc;
+        w0[e] = nxt;
+      }
+      if (do_inv) y_inverse(w0, mx, act);
+    }
+    if constexpr (mode_writes_state(MODE)) {
+      if (a.nonfin) flag_wave(a.nonfin, bad);
+    }
+  };
+
+  for (int k = 0; k < steps; k++) {
+    const bool more = k + 1 < steps;
+    x_phase();
+    y_phase(std::integral_constant<int, kStage1>{}, true);
+    __syncthreads();
+    x_phase();
+    y_phase(std::integral_constant<int, kStage2>{}, true);
+    __syncthreads();
+    x_phase();
+    y_phase(std::integral_constant<int, kStage3>{}, true);
+    __syncthreads();
+    x_phase();
+    y_phase(std::integral_constant<int, kStage4>{}, more);
+    __syncthreads();
   }
 }
 

@@ -350,6 +350,7 @@ class Plan:
 
 
 FS_NO_AUTOTUNE = 0x4
+FS_NO_RESIDENT = 0x20
 lib.fs_ensemble_create.argtypes = [C.POINTER(_vp), _i, C.POINTER(_i), _d, _d, _d, C.POINTER(Opts)]
 lib.fs_ensemble_offsets.argtypes = [_vp, C.POINTER(C.c_int64)]
 lib.fs_ensemble_step_rk4.argtypes = [_vp, _vp, _i]
@@ -365,7 +366,8 @@ class Ensemble:
     """Independent 2D FP32 runs of uneven sizes (64/128/256/512) advanced together."""
 
     def __init__(self, sizes, L: float = 2 * math.pi, nu: float = 0.0, dt: float = 1e-3,
-                 stream=None, autotune: bool = True, graphs: bool = True):
+                 stream=None, autotune: bool = True, graphs: bool = True,
+                 resident: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1807_01769_amd.fs needs a HIP device")
         self.sizes = [int(s) for s in sizes]
@@ -374,7 +376,8 @@ class Ensemble:
         o.ndim = 2
         o.precision = FS_F32
         o.stream = _stream_ptr(stream)
-        o.flags = (0 if autotune else FS_NO_AUTOTUNE) | (0 if graphs else FS_NO_GRAPH)
+        o.flags = ((0 if autotune else FS_NO_AUTOTUNE) | (0 if graphs else FS_NO_GRAPH) |
+                   (0 if resident else FS_NO_RESIDENT))
         arr = (_i * len(self.sizes))(*self.sizes)
         h = _vp()
         _check(lib.fs_ensemble_create(C.byref(h), len(self.sizes), arr, float(L), float(nu),
@@ -416,8 +419,11 @@ class Ensemble:
                                           C.byref(xr), C.byref(uy), C.byref(ux))
             if st != FS_OK:
                 break
-            out.append({"n": n.value, "runs": nr.value, "y_lines": yl.value,
-                        "x_rowpairs": xr.value, "us_y": uy.value, "us_x": ux.value})
+            if yl.value == 0:  # block-resident class
+                out.append({"n": n.value, "runs": nr.value, "resident": True})
+            else:
+                out.append({"n": n.value, "runs": nr.value, "y_lines": yl.value,
+                            "x_rowpairs": xr.value, "us_y": uy.value, "us_x": ux.value})
             c += 1
         return out
 

@@ -75,3 +75,45 @@ def test_full_ensemble_200_steps(fs, oracle_mod):
         e = _rel(got[r].astype(np.complex128), ref, n)
         print(f"run {r} n={n}: 200 steps vs oracle {e:.2e}", flush=True)
         assert e <= 1e-5
+
+
+@pytest.mark.parametrize("graphs,steps", [(True, 3), (False, 1), (False, 2)])
+def test_resident_classes_match_class_batched(fs, graphs, steps):
+    """Classes of 64 and 128 points a side are advanced block-resident (one
+    block per run, its intermediate in LDS through all the steps of a call):
+    every run must match the class-batched passes to rounding (the same
+    operations in the same order; the compiler may contract multiply-adds
+    differently in the two kernels), for classes of one run and of several,
+    next to a class-batched 256^2 class; a run alone in its resident class
+    must match the same run in a larger one bit for bit."""
+    print(f"case resident vs class-batched graphs={graphs} steps={steps}", flush=True)
+    sizes = [128, 64, 256, 128, 128, 64, 64, 64]
+    nu, dt = 1e-4, 5e-4
+    fields = [I.ensemble_vorticity(50 + r, n).astype(np.complex64) for r, n in enumerate(sizes)]
+    out = {}
+    for resident in (True, False):
+        with fs.Ensemble(sizes, nu=nu, dt=dt, graphs=graphs, resident=resident) as ens:
+            sch = ens.schedule()
+            print("schedule", sch, flush=True)
+            assert [c.get("resident", False) for c in sch] == [resident, resident, False]
+            st = ens.pack(fields)
+            ens.step(st, steps)
+            torch.cuda.synchronize()
+            out[resident] = st.cpu()
+    assert torch.isfinite(torch.view_as_real(out[True])).all()
+    offs = ens.offsets
+    for r, n in enumerate(sizes):
+        a = out[True][offs[r]:offs[r + 1]].numpy().reshape(n, n // 2 + 1).astype(np.complex128)
+        b = out[False][offs[r]:offs[r + 1]].numpy().reshape(n, n // 2 + 1).astype(np.complex128)
+        e = _rel(a, b, n)
+        print(f"run {r} n={n}: resident vs class-batched {e:.2e}, max |diff| "
+              f"{np.max(np.abs(a - b)):.2e}", flush=True)
+        assert e <= 1e-6
+        if n == 256:
+            assert np.array_equal(a, b)  # the same kernels
+    with fs.Ensemble([128], nu=nu, dt=dt, graphs=graphs) as ens:
+        st = ens.pack(fields[:1])
+        ens.step(st, steps)
+        torch.cuda.synchronize()
+        one = st.cpu()
+    assert torch.equal(one, out[True][:one.numel()])
