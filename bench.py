@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 METRIC = "RK4 step ns/gridpoint at 512³ FP32, % HBM roofline; closure-LES vs DNS speedup"
 HBM_PEAK_GBS = 8000.0
 NU, DT, POWER, KMIN, KMAX, SEED = 2e-4, 1e-3, 5e-3, 2.0, 3.0, 1
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_3d_512.txt")
+TRAFFIC_FILES = {"plain": os.path.join(ROOT, "profiles", "traffic_3d_512.txt"),
+                 "boussinesq": os.path.join(ROOT, "profiles", "traffic_3d_512_boussinesq.txt")}
 KERNEL_SOURCES = ["fft_core.h", "ns_common.h", "ns3d_kernels.h", "ops3d_impl.h"]
 
 
@@ -44,12 +45,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """Measured HBM bytes per launch from the counter summary: its line that
+def read_traffic(variant="plain"):
+    """Measured HBM bytes per launch of a workload (plain flow, or stratified
+    Boussinesq flow without rotation) from its counter summary: the line that
     starts with "DATA " holds {"n", "source_hash", "bytes_per_launch"}."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(variant)
+    if path is None or not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if line.startswith("DATA "):
                 return json.loads(line[5:])
@@ -501,7 +504,10 @@ def main() -> int:
     # `--breakdown-steps` steps right after the timed region; the roofline of
     # the dominant kernel uses these per-launch averages.
     kernels, roofline = {}, None
-    tr = read_traffic()
+    tvariant = "plain" if plain else (
+        "boussinesq" if args.boussinesq and args.rotation == 0.0 else None)
+    tr = read_traffic(tvariant)
+    tr_ok = bool(tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n)
     bsteps = args.breakdown_steps
     if bsteps > 0:
         plan.close()
@@ -524,9 +530,7 @@ def main() -> int:
                 rec["alg_GBps"] = tot / cnt / (ms / cnt * 1e-3) / 1e9
             kernels[name] = rec
         dom = max((k for k in kernels if "alg_GBps" in kernels[k]), key=lambda k: kernels[k]["ms_total"])
-        traffic = None
-        if plain and tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
-            traffic = tr.get("bytes_per_launch", {}).get(dom)
+        traffic = tr.get("bytes_per_launch", {}).get(dom) if tr_ok else None
         ach = kernels[dom]["alg_GBps"]
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -542,7 +546,7 @@ def main() -> int:
             roofline["step_unfused_model_frac"] = round(
                 unfused_model_bytes(n) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
-        if plain and tr and tr.get("source_hash") == kernel_source_hash() and tr.get("n") == n:
+        if tr_ok:
             bpl = tr.get("bytes_per_launch", {})
             names = [k for k in ("z_stage", "x_c2r_product_r2c", "y_inverse", "y_forward")
                      if k in bpl and k in kernels]
