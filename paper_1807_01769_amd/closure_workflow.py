@@ -1,5 +1,5 @@
 """Learned-closure workflow on one GPU: forced DNS -> filtered samples ->
-network training -> coarse LES judged against the filtered DNS.
+network training -> coarse LES compared with the filtered DNS.
 
 Every numerical step runs in libfs kernels (fs.Plan, fs.Closure, fs.Mlp,
 fs.Les); torch only holds device memory, shuffles sample indices and

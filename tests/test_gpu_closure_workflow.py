@@ -1,6 +1,6 @@
 """The trained closure against the method without it: a small forced DNS
 (128^3, nu = 1e-3) is filtered to 32^3, the network is trained on the GPU by
-the library's kernels, and LES with and without it are judged against the
+the library's kernels, and LES with and without it are compared with the
 filtered DNS spectra (shells 1..10 up to the cutoff, averaged over 4 time
 units from a held-out snapshot).  Every step is deterministic, so the
 outcome is reproducible; measured: max spectral error 0.39 with the network,
